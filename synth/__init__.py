@@ -1,0 +1,319 @@
+"""Seeded synthetic consistent sparse systems ``Ax = b``.
+
+This module builds inputs only.  It holds none of the Kaczmarz arithmetic: it
+is shared by the CPU oracle's tests and by the GPU path's tests and benchmark,
+and neither of those imports the other.
+
+Recipe (paper, Section "Experiments"): nonzero positions are chosen at random,
+their values are N(0,1), and every row is normalized afterwards.  The fixed
+count of *distinct* columns per row, the skewed (lognormal length, Zipf
+column) variant and the serving stream are the workload shapes this project
+measures on; each choice the paper leaves open is documented on the function
+that makes it.
+
+Every array that describes the stored matrix is returned in CSR form:
+
+* ``row_ptr``  int64, length m+1, ``row_ptr[0] == 0``
+* ``col``      int32, sorted strictly increasing inside each row
+* ``val``      the *stored* values: float64, float32, or bfloat16 bit patterns
+               (uint16, round-to-nearest-even of the float32 value)
+* ``val64``    the stored values promoted exactly to float64
+* ``x_star``   float64 solution, ``b = A @ x_star`` in float64 from ``val64``
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "SparseSystem",
+    "uniform_rows",
+    "skewed_rows",
+    "serving_specs",
+    "serving_system",
+    "poisson_arrivals",
+    "bf16_bits_from_f32",
+    "f64_from_bf16_bits",
+    "DTYPES",
+]
+
+DTYPES = ("f64", "f32", "bf16")
+
+
+@dataclasses.dataclass
+class SparseSystem:
+    m: int
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    dtype: str
+    val64: np.ndarray
+    x_star: np.ndarray
+    b: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def row_nnz(self) -> np.ndarray:
+        return np.diff(self.row_ptr)
+
+    def dense(self) -> np.ndarray:
+        """Dense float64 copy (tiny systems only)."""
+        a = np.zeros((self.m, self.n))
+        rows = np.repeat(np.arange(self.m), self.row_nnz())
+        a[rows, self.col] = self.val64
+        return a
+
+    def csr_bytes(self) -> int:
+        return self.row_ptr.nbytes + self.col.nbytes + self.val.nbytes
+
+
+def bf16_bits_from_f32(v: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even); return the bits."""
+    u = np.ascontiguousarray(v, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    bias = ((u >> np.uint64(16)) & np.uint64(1)) + np.uint64(0x7FFF)
+    return ((u + bias) >> np.uint64(16)).astype(np.uint16)
+
+
+def f64_from_bf16_bits(bits: np.ndarray) -> np.ndarray:
+    u = bits.astype(np.uint32) << np.uint32(16)
+    return u.view(np.float32).astype(np.float64)
+
+
+def _store(v64: np.ndarray, dtype: str):
+    """Round float64 values to the storage dtype; return (stored, promoted-f64)."""
+    if dtype == "f64":
+        return v64.copy(), v64.copy()
+    f32 = v64.astype(np.float32)
+    if dtype == "f32":
+        return f32, f32.astype(np.float64)
+    if dtype == "bf16":
+        bits = bf16_bits_from_f32(f32)
+        return bits, f64_from_bf16_bits(bits)
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def _distinct_uniform_cols(rng: np.random.Generator, m: int, n: int, k: int) -> np.ndarray:
+    """(m, k) int64 array, each row k distinct columns of [0, n), sorted ascending.
+
+    Rows that draw a repeated column are drawn again until none repeats.
+    """
+    if k > n:
+        raise ValueError("more nonzeros per row than columns")
+    if n <= 4 * k or m * n <= 4_000_000:
+        # small: take the first k of a random permutation per row
+        keys = rng.random((m, n))
+        cols = np.argpartition(keys, k - 1, axis=1)[:, :k] if k < n else np.argsort(keys, axis=1)
+        cols.sort(axis=1)
+        return cols.astype(np.int64)
+    cols = rng.integers(0, n, size=(m, k), dtype=np.int64)
+    cols.sort(axis=1)
+    bad = np.nonzero((np.diff(cols, axis=1) == 0).any(axis=1))[0]
+    while bad.size:
+        redo = rng.integers(0, n, size=(bad.size, k), dtype=np.int64)
+        redo.sort(axis=1)
+        cols[bad] = redo
+        sub = (np.diff(redo, axis=1) == 0).any(axis=1)
+        bad = bad[sub]
+    return cols
+
+
+def _normal_rows_normalized(rng, nnz_total: int, row_ptr: np.ndarray) -> np.ndarray:
+    v = rng.standard_normal(nnz_total)
+    sq = np.add.reduceat(v * v, row_ptr[:-1]) if nnz_total else np.zeros(0)
+    nrm = np.sqrt(sq)
+    return v / np.repeat(nrm, np.diff(row_ptr))
+
+
+def _finish(m, n, row_ptr, col, v64, dtype, rng, x_star=None, x_star_mode="normal"):
+    val, val64 = _store(v64, dtype)
+    if np.any(val64 == 0.0) and dtype != "f64":
+        # an entry that rounded to zero would be a stored zero; re-round upward
+        raise RuntimeError("a stored nonzero rounded to zero; change the seed")
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(row_ptr))
+    if x_star is None:
+        if x_star_mode == "normal":
+            x_star = rng.standard_normal(n)
+        elif x_star_mode == "range":
+            # x* = A^T y rescaled to RMS 1: the minimum-norm solution, reachable from x0 = 0
+            y = rng.standard_normal(m)
+            x_star = np.bincount(col, weights=val64 * y[rows], minlength=n)
+            rms = math.sqrt(float(np.mean(x_star * x_star)))
+            x_star = x_star / rms
+        else:
+            raise ValueError(x_star_mode)
+    prod = val64 * x_star[col]
+    b = np.add.reduceat(prod, row_ptr[:-1]) if prod.size else np.zeros(m)
+    b[np.diff(row_ptr) == 0] = 0.0
+    return SparseSystem(m, n, row_ptr, col.astype(np.int32), val, dtype, val64, x_star, b)
+
+
+def uniform_rows(m: int, n: int, nnz_per_row: int, seed: int, dtype: str = "f32",
+                 normalize: bool = True, require_full_columns: bool = True,
+                 x_star: np.ndarray | None = None) -> SparseSystem:
+    """Every row has exactly ``nnz_per_row`` distinct uniform-random columns.
+
+    Values are N(0,1); rows are scaled to unit norm in float64 and then rounded
+    to ``dtype`` (so stored rows are unit norm up to that rounding).  With
+    ``normalize=False`` the raw N(0,1) values are kept (row norms then vary,
+    which exercises the norm-weighted row sampling).  ``x_star`` ~ N(0,1).
+
+    Draw order for a seed: columns, values, x*.
+    """
+    rng = np.random.default_rng(seed)
+    cols = _distinct_uniform_cols(rng, m, n, nnz_per_row).reshape(-1)
+    row_ptr = np.arange(m + 1, dtype=np.int64) * nnz_per_row
+    if normalize:
+        v64 = _normal_rows_normalized(rng, cols.size, row_ptr)
+    else:
+        v64 = rng.standard_normal(cols.size)
+    if require_full_columns:
+        counts = np.bincount(cols, minlength=n)
+        if counts.min() == 0:
+            raise RuntimeError("an empty column: the solution would not be unique")
+    return _finish(m, n, row_ptr, cols, v64, dtype, rng, x_star=x_star)
+
+
+def _zipf_cdf(n: int, s: float) -> np.ndarray:
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-s)
+    c = np.cumsum(w)
+    return c / c[-1]
+
+
+def _distinct_rows_from_sampler(rng, lengths: np.ndarray, draw) -> np.ndarray:
+    """Per row, the first ``lengths[i]`` distinct values of an i.i.d. stream ``draw``.
+
+    Rows are handled in groups of similar length; a row whose pool holds too few
+    distinct values is drawn again with a larger pool.  Returns the
+    concatenated, per-row sorted column lists.
+    """
+    m = lengths.size
+    out = [None] * m
+    todo = np.arange(m)
+    factor = 3
+    while todo.size:
+        lens = lengths[todo]
+        order = np.argsort(lens, kind="stable")
+        todo_sorted = todo[order]
+        lens_sorted = lens[order]
+        retry = []
+        # groups of rows with length in [2^g, 2^(g+1))
+        g_of = np.floor(np.log2(np.maximum(lens_sorted, 1))).astype(np.int64)
+        for g in np.unique(g_of):
+            sel = np.nonzero(g_of == g)[0]
+            idx = todo_sorted[sel]
+            ln = lens_sorted[sel]
+            pool = int(factor * (2 ** (g + 1)) + 16)
+            draws = draw(rng, (idx.size, pool))
+            # first occurrence of each value in draw order
+            srt = np.argsort(draws, axis=1, kind="stable")
+            sv = np.take_along_axis(draws, srt, axis=1)
+            first = np.ones_like(sv, dtype=bool)
+            first[:, 1:] = sv[:, 1:] != sv[:, :-1]
+            keep = np.zeros_like(first)
+            np.put_along_axis(keep, srt, first, axis=1)
+            # rank of each first occurrence in draw order
+            rank = np.cumsum(keep, axis=1)
+            for r in range(idx.size):
+                need = ln[r]
+                ok = keep[r] & (rank[r] <= need)
+                vals = draws[r][ok]
+                if vals.size < need:
+                    retry.append(idx[r])
+                else:
+                    out[idx[r]] = np.sort(vals)
+        todo = np.array(retry, dtype=np.int64)
+        factor *= 4
+    return np.concatenate(out) if m else np.zeros(0, dtype=np.int64)
+
+
+def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 16.0,
+                sigma: float = 1.0, lo: int = 4, hi: int = 2000, zipf_s: float = 1.1) -> SparseSystem:
+    """Skewed rows: lognormal lengths and Zipf-distributed (hot) columns.
+
+    * nnz_i = clip(round(exp(N(ln median, sigma))), lo, min(hi, n))
+    * column ranks 1..n drawn with P(k) proportional to k^-zipf_s, mapped to
+      columns through a seeded random permutation (hot columns are scattered),
+      distinct within a row (first distinct draws kept).
+    * N(0,1) values, rows normalized in float64 then rounded to ``dtype``.
+    * the system is rank deficient (empty and singleton columns), so
+      ``x_star = A^T y`` (y ~ N(0, I_m)) scaled to RMS 1, the minimum-norm
+      solution reachable from x0 = 0.
+
+    Draw order: lengths, permutation, columns, values, y.
+    """
+    rng = np.random.default_rng(seed)
+    lens = np.rint(np.exp(rng.normal(math.log(median), sigma, size=m))).astype(np.int64)
+    lens = np.clip(lens, lo, min(hi, n))
+    perm = rng.permutation(n).astype(np.int64)
+    cdf = _zipf_cdf(n, zipf_s)
+
+    def draw(r, shape):
+        ranks = np.searchsorted(cdf, r.random(shape), side="right")
+        ranks = np.minimum(ranks, n - 1)
+        return perm[ranks]
+
+    cols = _distinct_rows_from_sampler(rng, lens, draw)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    v64 = _normal_rows_normalized(rng, cols.size, row_ptr)
+    return _finish(m, n, row_ptr, cols, v64, dtype, rng, x_star_mode="range")
+
+
+# --------------------------------------------------------------------------
+# Serving stream: many independent small systems
+# --------------------------------------------------------------------------
+
+def serving_specs(count: int = 10_000, seed: int = 4, m_lo: int = 1_000, m_hi: int = 200_000,
+                  nnz_lo: int = 8, nnz_hi: int = 64):
+    """Sizes of the serving stream: m log-uniform in [m_lo, m_hi], n = m // 4.
+
+    Returns an int64 array of shape (count, 2) with (m, n) per request.  Each
+    system's contents come from ``serving_system(request_id, m, n, seed)``.
+    """
+    rng = np.random.default_rng(seed)
+    m = np.rint(np.exp(rng.uniform(math.log(m_lo), math.log(m_hi), size=count))).astype(np.int64)
+    n = m // 4
+    return np.stack([m, n], axis=1)
+
+
+def serving_system(request_id: int, m: int, n: int, seed: int = 4, dtype: str = "f32",
+                   nnz_lo: int = 8, nnz_hi: int = 64) -> SparseSystem:
+    """One serving request: nnz/row uniform in {nnz_lo..nnz_hi} (capped at n),
+    distinct uniform columns, N(0,1) values, unit rows, x* ~ N(0,1).
+
+    Seeded by (seed, request_id) so each request is reproducible on its own.
+    """
+    rng = np.random.default_rng([seed, request_id])
+    hi = min(nnz_hi, n)
+    lo = min(nnz_lo, hi)
+    lens = rng.integers(lo, hi + 1, size=m).astype(np.int64)
+    cols = []
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    for k in np.unique(lens):
+        sel = np.nonzero(lens == k)[0]
+        c = _distinct_uniform_cols(rng, sel.size, n, int(k))
+        cols.append((sel, c))
+    col = np.empty(int(row_ptr[-1]), dtype=np.int64)
+    for sel, c in cols:
+        starts = row_ptr[sel]
+        idx = starts[:, None] + np.arange(c.shape[1])[None, :]
+        col[idx.reshape(-1)] = c.reshape(-1)
+    counts = np.bincount(col, minlength=n)
+    if counts.min() == 0:
+        # fill an empty column by moving one entry of a row that holds a column
+        # seen more than once; rare for these shapes
+        raise RuntimeError("serving system with an empty column; change request id")
+    v64 = _normal_rows_normalized(rng, col.size, row_ptr)
+    return _finish(m, n, row_ptr, col, v64, dtype, rng)
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))

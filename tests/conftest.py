@@ -1,0 +1,15 @@
+"""Shared test configuration.
+
+Tests marked ``gpu`` need an MI355X (gfx950) and the built HIP library; every
+other test runs on the CPU.
+"""
+import sys
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parents[1]
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
