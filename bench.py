@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark: asynchronous randomized Kaczmarz on one MI355X.
+
+Workload (the at-scale FP32 configuration): m = 4,000,000, n = 1,000,000,
+exactly 20 distinct uniform-random columns per row, N(0,1) values, unit-norm
+rows stored in FP32, int32 column indices; x* ~ N(0,1), b = A x* (FP64 from
+the stored values); x0 = 0; gamma = 1; run until ||x - x*||/||x*|| <= 1e-6.
+
+One step = one complete solve from x0 = 0 to the tolerance: row sampling,
+record fetch, gather-dot, step, atomic scatter, staleness control and the
+per-sweep convergence check.  System setup (validation, alias table, record
+packing, upload) happens once before the timed region: inputs are resident in
+HBM when timing starts.
+
+Prints one JSON line: value = row updates/s over the K timed solves (wall
+clock, synchronized on both sides), p50/p99 solve latency, the sweep kernel's
+roofline (algorithmic bytes per launch / mean launch time from HIP events on
+the kernel's stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+M, N, NNZ, GEN_SEED = 4_000_000, 1_000_000, 20, 1
+GAMMA, TOL, BUDGET = 1.0, 1e-6, 200
+HBM_PEAK_GBPS = 8000.0
+R_SWEEP = (1024, 2048, 4096, 8192, 16384, 32768, 65536)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h", "layout.h", "api.hip", "setup.cpp"):
+        h.update((ROOT / "paper_1401_4780_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per sweep launch measured with rocprofv3 counters, if the
+    committed summary was taken on the current kernel sources."""
+    p = ROOT / "profiles" / "sweep_kernel_c2_4Mx1M_f32_traffic.md"
+    if not p.exists():
+        return None
+    text = p.read_text()
+    mh = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not mh or not mb or mh.group(1) != kernel_source_hash():
+        return None
+    return float(mb.group(1))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(s, target_s=12.0):
+    """Sequential FP64 oracle on a bounded sample of the same system."""
+    import oracle
+    x0 = np.zeros(s.n)
+    probe = 200_000
+    t0 = time.perf_counter()
+    oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, probe, 7)
+    rate0 = probe / (time.perf_counter() - t0)
+    steps = int(min(max(rate0 * target_s, s.m), 12 * s.m))
+    t0 = time.perf_counter()
+    oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, steps, 7)
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "row updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} row updates ({steps / s.m:.2f} sweeps) of the same 4Mx1M system "
+                      f"from x0=0, sequential FP64, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1401_4780_amd as P
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    s = synth.uniform_rows(M, N, NNZ, seed=GEN_SEED, dtype="f32")
+    log(f"generated {M}x{N} nnz={s.nnz} in {time.perf_counter() - t0:.1f}s")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    t0 = time.perf_counter()
+    sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=N)
+    setup_s = time.perf_counter() - t0
+    info = sysm.info()
+    log(f"setup {setup_s:.1f}s stride={info['record_stride']} device_bytes={info['device_bytes']}")
+    x_ref = d(s.x_star)
+    x = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def solve(seed, R=args.in_flight):
+        x.zero_()
+        return sysm.solve(x, GAMMA, BUDGET, seed, tol=TOL, x_ref=x_ref, in_flight=R,
+                          lanes=args.lanes)
+
+    for w in range(args.warmup):
+        st = solve(1000 + w)
+        log(f"warmup {w}: {st['status']} sweeps={st['sweeps_done']} err={st['final_err']:.3e}")
+
+    torch.cuda.synchronize()
+    lat, sts = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        st = solve(1 + k)
+        lat.append(time.perf_counter() - t1)
+        sts.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    rows = sum(st["row_updates"] for st in sts)
+    launches = sum(st["sweeps_done"] for st in sts)
+    kern_s = sum(st["sweep_seconds"] for st in sts)
+    ok = all(st["status"] == "OK" for st in sts)
+    log(f"timed {args.steps} solves in {elapsed:.3f}s, all converged={ok}")
+
+    bytes_per_row = info["record_bytes_per_row"]
+    per_launch_s = kern_s / launches
+    achieved = bytes_per_row * M / per_launch_s / 1e9
+    traffic = traffic_from_profile()
+
+    result = {
+        "metric": "row updates/s + time-to-1e-6 residual vs plain RK; p50/p99 solve latency",
+        "value": rows / elapsed,
+        "unit": "row updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "asyrk_4Mx1M_nnz20_f32_to_1e-6", "m": M, "n": N, "nnz_per_row": NNZ,
+                   "gamma": GAMMA, "tol": TOL, "in_flight": sts[0]["in_flight"],
+                   "lanes": sts[0]["lanes"], "record_stride_bytes": info["record_stride"]},
+        "time_to_tol_s_p50": float(np.percentile(lat, 50)),
+        "time_to_tol_s_p99": float(np.percentile(lat, 99)),
+        "sweeps_to_tol_mean": launches / args.steps,
+        "all_converged": ok,
+        "final_err_max": max(st["final_err"] for st in sts),
+        "kernel_rows_per_s": rows / kern_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel<F32,G>", "algorithmic_bytes_per_row": bytes_per_row,
+                     "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
+    }
+
+    # staleness report (one traced solve, not timed)
+    st = sysm.solve(x.zero_(), GAMMA, 3, 77, in_flight=args.in_flight, lanes=args.lanes, trace=True)
+    lam, tau_max = sysm.lambda_max(iters=40, seed=3)
+    result["staleness"] = {"tau_design": st["tau_design"], "tau_obs_mean": st["tau_obs_mean"],
+                           "tau_obs_max": st["tau_obs_max"], "window_ns_mean": st["window_ns_mean"],
+                           "lambda_max": lam, "tau_max_corollary1": tau_max,
+                           "tau_times_nnz": st["tau_design"] * NNZ}
+
+    # device ceilings for the x traffic (random 4-byte gathers and atomics)
+    copy = P.probe_copy(1 << 30, 20)
+    gat = P.probe_scatter(N, 1 << 27, "f32", "load", 5)
+    atm = P.probe_scatter(N, 1 << 27, "f32", "atomic", 5)
+    x_bound = 1.0 / (NNZ / gat + NNZ / atm)
+    result["ceilings"] = {"stream_copy_GBps": copy, "gather_f32_per_s": gat, "atomic_f32_per_s": atm,
+                          "rows_per_s_bound_by_x_traffic": x_bound,
+                          "frac_of_x_traffic_bound": result["kernel_rows_per_s"] / x_bound}
+
+    if not args.no_sweep:
+        sweep = {}
+        for R in R_SWEEP:
+            st = solve(500 + R, R=R)
+            sweep[str(R)] = {"rows_per_s": st["rows_per_s"], "sweeps": st["sweeps_done"],
+                             "status": st["status"]}
+        result["in_flight_sweep"] = sweep
+        x.zero_()
+        st = sysm.solve(x, 0.5, BUDGET, 9, tol=TOL, x_ref=x_ref, in_flight=args.in_flight)
+        result["gamma_0.5"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
+                               "status": st["status"]}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cb = cpu_baseline(s)
+        cb["time_to_tol_s_est"] = result["sweeps_to_tol_mean"] * M / cb["value"]
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

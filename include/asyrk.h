@@ -1,0 +1,247 @@
+/*
+ * asyrk.h - C ABI of the MI355X (gfx950) asynchronous randomized Kaczmarz
+ * library.
+ *
+ * The method (Liu, Wright, Sridhar, "An Asynchronous Parallel Randomized
+ * Kaczmarz Algorithm"): solve a consistent sparse system A x = b, A (m x n)
+ * with no zero rows (Section 1, eq. (1)).  Many workers run concurrently over
+ * one shared iterate x; each one repeatedly
+ *   1. draws row i with probability ||a_i||^2 / ||A||_F^2 (Section 1),
+ *   2. reads x on supp(a_i) without locking, possibly stale (Section 3),
+ *   3. forms r = a_i^T x - b_i,
+ *   4. writes x <- x - gamma * r / ||a_i||^2 * a_i on every coordinate of
+ *      supp(a_i) with lock-free atomic additions (eq. (2) with a step length
+ *      gamma; the all-coordinate variant of Section "Experiments", which on
+ *      one worker is plain randomized Kaczmarz).
+ * The delay between a worker's read and its write is the tau of eq. (3);
+ * Corollary 1 bounds the number of workers for near-linear speedup by
+ * 2 e lambda_max (tau + 1) / m <= 1.
+ *
+ * Conventions for every call
+ *   - Every call returns an asyrk_status; none aborts, throws or exits.
+ *   - Pointer arguments are host pointers or device pointers as selected by
+ *     the `mem` argument of asyrk_create (ASYRK_MEM_HOST / ASYRK_MEM_DEVICE);
+ *     that choice holds for every later call on the same system.  Exception:
+ *     structs (params, stats, info) and scalar outputs are always host memory.
+ *   - The caller owns every array it passes.  asyrk_create copies what it
+ *     needs; nothing passed in is retained after a call returns.
+ *   - All GPU work of a system is enqueued on the HIP stream given to
+ *     asyrk_create (NULL = the null stream) and every call synchronizes that
+ *     stream before it returns.
+ *   - One host thread at a time per system; separate systems are independent.
+ *   - Row indices are int32: m, n < 2^31 and each row has < 2^31 entries.
+ *
+ * Device layout (owned by the system): each row is one packed record of a
+ * 16-byte header (b_i, 1/||a_i||^2, alias threshold, alias row; 32 bytes for
+ * FP64) followed by its (column, value) pairs in groups of 4 (8 for BF16),
+ * padded to 16 or 64 bytes.  Equal-length rows sit at a fixed stride; other
+ * systems keep an 8-byte (offset, length) entry per row.
+ */
+#ifndef ASYRK_H
+#define ASYRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASYRK_ABI_VERSION 1
+
+typedef struct asyrk_system asyrk_system; /* opaque; owns all device-side data */
+
+typedef enum asyrk_status {
+    ASYRK_OK = 0,
+    ASYRK_ERR_INVALID_ARG = 1,   /* an argument fails validation (nothing was changed) */
+    ASYRK_ERR_ZERO_ROW = 2,      /* a row of A has ||a_i|| = 0 (Section 1 excludes it) */
+    ASYRK_ERR_OOM = 3,           /* device or host allocation failed */
+    ASYRK_ERR_DEVICE = 4,        /* a HIP runtime call failed (no GPU, launch error) */
+    ASYRK_ERR_NOT_CONVERGED = 5, /* tol > 0 and the sweep budget ran out; x and stats are valid */
+    ASYRK_ERR_DIVERGED = 6,      /* the monitored error became non-finite or grew 1e6-fold */
+    ASYRK_ERR_CANCELLED = 7,     /* the cancel flag was set; x holds the last checked iterate */
+    ASYRK_ERR_UNSUPPORTED = 8    /* a valid combination this build does not implement */
+} asyrk_status;
+
+typedef enum asyrk_dtype { ASYRK_F64 = 0, ASYRK_F32 = 1, ASYRK_BF16 = 2 } asyrk_dtype;
+typedef enum asyrk_mem { ASYRK_MEM_HOST = 0, ASYRK_MEM_DEVICE = 1 } asyrk_mem;
+
+/* ASYNC: many workers, lock-free (Section 3).  REPLAY: one worker, tickets
+ * strictly in order, deterministic: plain randomized Kaczmarz (eq. (2)). */
+typedef enum asyrk_mode { ASYRK_ASYNC = 0, ASYRK_REPLAY = 1 } asyrk_mode;
+
+/* NORM2: P(i) = ||a_i||^2/||A||_F^2 (Section 1).  UNIFORM: P(i) = 1/m
+ * (Algorithm 1's equal probability; the same thing for normalized rows). */
+typedef enum asyrk_sampling { ASYRK_SAMPLE_NORM2 = 0, ASYRK_SAMPLE_UNIFORM = 1 } asyrk_sampling;
+
+/* ALL: every coordinate of supp(a_i) (eq. (2), Section "Experiments").
+ * ONE: one coordinate t uniform in supp(a_i), step gamma*theta_i
+ * (Algorithm 1, the variant Theorem 1 and Corollary 1 analyse). */
+typedef enum asyrk_update { ASYRK_UPDATE_ALL = 0, ASYRK_UPDATE_ONE = 1 } asyrk_update;
+
+/* Random row selection for ticket j (identical on every device and in every
+ * mode, so REPLAY is reproducible and resumable):
+ *   (u0,u1,u2,u3) = Philox4x32-10(counter = (j mod 2^32, j div 2^32, stream_id, 0),
+ *                                 key = (seed mod 2^32, seed div 2^32))
+ *   k = floor((u1 * 2^32 + u0) * m / 2^64)
+ *   NORM2:   i = (u2 < T_k) ? k : alias_k, with (T, alias) the Vose alias table
+ *            of the row weights ||a_i||^2 (T_k in [0, 2^32])
+ *   UNIFORM: i = k
+ *   UPDATE_ONE: t = floor(u3 * theta_i / 2^32), the position inside row i. */
+
+typedef struct asyrk_solve_params {
+    int32_t mode;            /* asyrk_mode, default ASYNC */
+    int32_t sampling;        /* asyrk_sampling, default NORM2 */
+    int32_t update;          /* asyrk_update, default ALL */
+    int32_t lanes;           /* lanes per row G in {1,2,4,8,16}; 0 = choose */
+    int64_t in_flight;       /* R, row workers in flight (tau_design = R - 1); 0 = choose */
+    double tol;              /* stop when the monitored error <= tol; 0 = run every sweep */
+    const double *x_ref;     /* nullable, length n: monitor ||x - x_ref||/||x_ref||;
+                                when NULL the monitor is ||A x - b||/||b|| */
+    int32_t check_every;     /* sweeps between error checks (>= 1), default 1 */
+    int32_t refine;          /* 1: FP64 iterative refinement around FP32 sweeps (see asyrk_solve) */
+    int64_t inner_sweeps;    /* refinement: sweeps per inner solve, 0 = choose */
+    uint32_t stream_id;      /* RNG stream (third counter word) */
+    int32_t trace;           /* 1: time each worker's read-to-write window (tau_obs) */
+    int64_t ticket0;         /* first ticket (resume: pass stats.next_ticket) */
+    volatile const int32_t *cancel; /* nullable HOST pointer, polled at every check */
+    double *history;         /* nullable HOST array: monitored error at the start and after
+                                each check (refinement: after each outer iteration) */
+    int64_t history_cap;     /* capacity of history */
+} asyrk_solve_params;
+
+typedef struct asyrk_solve_stats {
+    int64_t sweeps_done;       /* sweeps (m tickets each) performed */
+    int64_t row_updates;       /* tickets performed */
+    int64_t next_ticket;       /* ticket0 + row_updates */
+    int64_t history_len;       /* entries written to params.history */
+    int64_t in_flight;         /* R used */
+    int32_t lanes;             /* G used */
+    int32_t outer_iters;       /* refinement outer iterations (0 without refinement) */
+    double seconds;            /* wall time of the call after setup */
+    double sweep_seconds;      /* GPU time of the sweep kernels (HIP events) */
+    double rows_per_s;         /* row_updates / sweep_seconds */
+    double final_err;          /* last monitored error (NaN if never checked) */
+    double tau_design;         /* R - 1 */
+    double tau_obs_mean;       /* trace: mean read-to-write window x global row rate */
+    double tau_obs_max;        /* trace: max read-to-write window x global row rate */
+    double window_ns_mean;     /* trace: mean read-to-write window in ns */
+    double window_ns_max;      /* trace: max read-to-write window in ns */
+} asyrk_solve_stats;
+
+typedef struct asyrk_system_info {
+    int64_t m, n, nnz;
+    int64_t mu;                /* max_i ||a_i||_0 (Section 1 notation) */
+    int64_t nu;                /* max_j ||column j||_0 */
+    int64_t fixed_nnz;         /* common row length, or 0 if rows differ */
+    int64_t record_stride;     /* bytes per row record when fixed_nnz > 0 */
+    int64_t device_bytes;      /* device memory held by the system */
+    int32_t vals_dtype;        /* asyrk_dtype of the stored values */
+    int32_t iter_dtype;        /* ASYRK_F64 for F64 values, else ASYRK_F32 */
+    double fro2;               /* ||A||_F^2 (FP64, stored values) */
+    double lambda_mp;          /* (1 + sqrt(n/m))^2 * fro2 / n: Gaussian-ensemble estimate of lambda_max */
+    int64_t record_bytes_per_row; /* algorithmic bytes per row update (values, indices, b_i, w_i, start) */
+} asyrk_system_info;
+
+/* Version of this ABI (ASYRK_ABI_VERSION). */
+int asyrk_abi_version(void);
+
+/* Static string for a status code. */
+const char *asyrk_status_string(asyrk_status s);
+
+/* Text of the last HIP runtime error seen by this thread ("" if none). */
+const char *asyrk_last_error_message(void);
+
+/* Default parameters (ASYNC, NORM2, ALL, G and R chosen, check every sweep). */
+void asyrk_solve_params_init(asyrk_solve_params *p);
+
+/*
+ * Build a system from CSR A and b (Section 1, eq. (1)).
+ *   row_ptr  int64[m+1], row_ptr[0] = 0, non-decreasing
+ *   col_idx  int32[nnz], 0 <= c < n, strictly increasing inside each row
+ *   vals     nnz values of type vals_dtype (F64, F32, or BF16 bit patterns);
+ *            these stored values ARE the matrix: FP64 work promotes them exactly
+ *   b        double[m], finite
+ *   mem      ASYRK_MEM_HOST or ASYRK_MEM_DEVICE for every pointer argument
+ *   stream   hipStream_t (as void *), NULL for the null stream
+ * Sweeps run in FP64 (values F64) or FP32 (values F32/BF16).
+ * Errors: INVALID_ARG (shape, ordering, range, non-finite), ZERO_ROW, OOM,
+ * DEVICE.  On error *out is set to NULL.
+ */
+asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, int32_t vals_dtype,
+                          const double *b, int32_t mem, void *stream);
+
+/* Release every device and host resource of the system (NULL is accepted). */
+asyrk_status asyrk_destroy(asyrk_system *s);
+
+/* Replace b (double[m], finite) keeping A. */
+asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b);
+
+/* Sizes and derived quantities of the system. */
+asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *info);
+
+/*
+ * Run the method from x (double[n], in: x0, out: the final iterate).
+ *   gamma   step length, 0 < gamma < 2 (eq. (2) scaled; gamma = 1 is the
+ *           orthogonal projection)
+ *   sweeps  budget in sweeps of m tickets: tickets ticket0 .. ticket0 + sweeps*m - 1
+ *   seed    Philox key
+ *   p       NULL for defaults (asyrk_solve_params_init)
+ *   st      nullable; filled on OK, NOT_CONVERGED, DIVERGED and CANCELLED
+ * ASYNC runs R workers at once; staleness is not bounded by construction
+ * (tau_design = R - 1 is the modeling value; trace measures windows).
+ * REPLAY forces one worker and is bitwise reproducible.
+ * With refine = 1 (FP32 systems only): outer loop r = b - A x in FP64,
+ * inner sweeps on A d = fp32(r) from d = 0, x += d in FP64, until the
+ * monitored error <= tol or the budget is spent.  The system's b is
+ * restored before return.
+ * Errors: INVALID_ARG, DEVICE, NOT_CONVERGED, DIVERGED, CANCELLED.
+ */
+asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweeps,
+                         uint64_t seed, const asyrk_solve_params *p, asyrk_solve_stats *st);
+
+/*
+ * Residual in FP64 over the stored values promoted exactly:
+ *   r = b - A x (x double[n]); r_out nullable double[m]; *norm2_out = ||r||^2.
+ * Errors: INVALID_ARG, DEVICE.
+ */
+asyrk_status asyrk_residual(asyrk_system *s, const double *x, double *r_out, double *norm2_out);
+
+/*
+ * Rows the device sampler draws for tickets ticket0 .. ticket0+count-1
+ * (see "Random row selection" above); rows_out int32[count].  With
+ * coords_out (nullable int32[count]) also the position t used by UPDATE_ONE.
+ */
+asyrk_status asyrk_sample_rows(asyrk_system *s, uint64_t seed, uint32_t stream_id, int32_t sampling,
+                               int64_t ticket0, int64_t count, int32_t *rows_out,
+                               int32_t *coords_out);
+
+/*
+ * lambda_max(A^T A) (Section 1 notation) by power iteration on the GPU,
+ * from a Philox-seeded start; *lambda_out gets the Rayleigh quotient after
+ * iters steps (iters >= 1).  tau_max_out (nullable): the largest tau with
+ * 2 e lambda_max (tau + 1) / ||A||_F^2 <= 1 (Corollary 1; ||A||_F^2 = m for
+ * normalized rows), or -1 when none.
+ */
+asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
+                              double *tau_max_out);
+
+/*
+ * Device ceilings used to read the roofline (no system needed):
+ *   asyrk_probe_copy      streaming copy of `bytes` bytes, `iters` times;
+ *                         *gbps = 2*bytes*iters / time (read + write)
+ *   asyrk_probe_scatter   `count` random 4- or 8-byte accesses (kind 0:
+ *                         agent-coherent loads, 1: atomic add) over a
+ *                         table of `n` elements of dtype F32 or F64;
+ *                         *per_s = accesses per second
+ * Errors: INVALID_ARG, OOM, DEVICE.
+ */
+asyrk_status asyrk_probe_copy(int64_t bytes, int32_t iters, double *gbps);
+asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_t kind,
+                                 int32_t iters, double *per_s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASYRK_H */

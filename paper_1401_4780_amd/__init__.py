@@ -1,0 +1,316 @@
+"""MI355X (gfx950) asynchronous randomized Kaczmarz: Python binding.
+
+A thin ctypes layer over ``libasyrk.so`` (C ABI in ``include/asyrk.h``): it
+marshals arguments and nothing else; every step of the method runs in the
+library's HIP kernels.  Arrays are either all numpy (host memory) or all torch
+CUDA tensors (device memory, work enqueued on torch's current stream).
+
+    from paper_1401_4780_amd import System
+    s = System(row_ptr, col, val, b)            # CSR A, right-hand side b
+    st = s.solve(x, gamma=1.0, sweeps=30, seed=1, tol=1e-6, x_ref=x_star)
+
+The library must be built first (``python -m paper_1401_4780_amd.build``);
+importing works without it, but any call raises ``LibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from pathlib import Path
+
+import numpy as np
+
+__all__ = ["System", "AsyrkError", "LibraryMissing", "lib", "library_path", "probe_copy",
+           "probe_scatter", "STATUS", "F64", "F32", "BF16"]
+
+LIB_PATH = Path(__file__).resolve().parent / "_build" / "libasyrk.so"
+
+F64, F32, BF16 = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+ASYNC, REPLAY = 0, 1
+SAMPLE_NORM2, SAMPLE_UNIFORM = 0, 1
+UPDATE_ALL, UPDATE_ONE = 0, 1
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "ZERO_ROW", 3: "OOM", 4: "DEVICE", 5: "NOT_CONVERGED",
+          6: "DIVERGED", 7: "CANCELLED", 8: "UNSUPPORTED"}
+_SOFT = {5, 6, 7}  # statuses after which x and the stats are still valid
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class AsyrkError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.name}" + (f" ({detail})" if detail else ""))
+
+
+class SolveParams(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32), ("sampling", C.c_int32), ("update", C.c_int32), ("lanes", C.c_int32),
+        ("in_flight", C.c_int64), ("tol", C.c_double), ("x_ref", C.c_void_p),
+        ("check_every", C.c_int32), ("refine", C.c_int32), ("inner_sweeps", C.c_int64),
+        ("stream_id", C.c_uint32), ("trace", C.c_int32), ("ticket0", C.c_int64),
+        ("cancel", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int64),
+    ]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [
+        ("sweeps_done", C.c_int64), ("row_updates", C.c_int64), ("next_ticket", C.c_int64),
+        ("history_len", C.c_int64), ("in_flight", C.c_int64), ("lanes", C.c_int32),
+        ("outer_iters", C.c_int32), ("seconds", C.c_double), ("sweep_seconds", C.c_double),
+        ("rows_per_s", C.c_double), ("final_err", C.c_double), ("tau_design", C.c_double),
+        ("tau_obs_mean", C.c_double), ("tau_obs_max", C.c_double), ("window_ns_mean", C.c_double),
+        ("window_ns_max", C.c_double),
+    ]
+
+
+class SystemInfo(C.Structure):
+    _fields_ = [
+        ("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64), ("mu", C.c_int64), ("nu", C.c_int64),
+        ("fixed_nnz", C.c_int64), ("record_stride", C.c_int64), ("device_bytes", C.c_int64),
+        ("vals_dtype", C.c_int32), ("iter_dtype", C.c_int32), ("fro2", C.c_double),
+        ("lambda_mp", C.c_double), ("record_bytes_per_row", C.c_int64),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> Path:
+    return LIB_PATH
+
+
+def lib():
+    """Load libasyrk.so (raises LibraryMissing when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise LibraryMissing(f"{LIB_PATH} is not built; run `python -m paper_1401_4780_amd.build`")
+    L = C.CDLL(str(LIB_PATH))
+    P, i64, u64, u32, i32, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
+    L.asyrk_abi_version.restype = C.c_int
+    L.asyrk_status_string.restype = C.c_char_p
+    L.asyrk_status_string.argtypes = [C.c_int]
+    L.asyrk_last_error_message.restype = C.c_char_p
+    L.asyrk_solve_params_init.argtypes = [P]
+    L.asyrk_solve_params_init.restype = None
+    L.asyrk_create.argtypes = [P, i64, i64, P, P, P, i32, P, i32, P]
+    L.asyrk_destroy.argtypes = [P]
+    L.asyrk_set_rhs.argtypes = [P, P]
+    L.asyrk_system_info_get.argtypes = [P, P]
+    L.asyrk_solve.argtypes = [P, P, dbl, i64, u64, P, P]
+    L.asyrk_residual.argtypes = [P, P, P, P]
+    L.asyrk_sample_rows.argtypes = [P, u64, u32, i32, i64, i64, P, P]
+    L.asyrk_lambda_max.argtypes = [P, i32, u64, P, P]
+    L.asyrk_probe_copy.argtypes = [i64, i32, P]
+    L.asyrk_probe_scatter.argtypes = [i64, i64, i32, i32, i32, P]
+    for name in ("asyrk_create", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
+                 "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
+                 "asyrk_probe_copy", "asyrk_probe_scatter"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        detail = lib().asyrk_last_error_message().decode() if rc in (3, 4) else ""
+        raise AsyrkError(rc, where, detail)
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """Raw pointer of a contiguous numpy array or torch tensor (None passes through)."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return a.ctypes.data
+
+
+def _vals_dtype(val, dtype):
+    if dtype is not None:
+        return {"f64": F64, "f32": F32, "bf16": BF16}[dtype]
+    name = str(val.dtype)
+    if name.endswith("float64"):
+        return F64
+    if name.endswith("float32"):
+        return F32
+    if name.endswith("bfloat16") or name.endswith("uint16") or name.endswith("int16"):
+        return BF16
+    raise TypeError(f"unsupported value dtype {val.dtype}")
+
+
+def _expect(a, device, kind, name):
+    """Check that an array matches the system's memory kind and element type."""
+    if device:
+        if not _is_torch(a) or not a.is_cuda:
+            raise TypeError(f"{name}: expected a CUDA tensor")
+    elif _is_torch(a) or not isinstance(a, np.ndarray):
+        raise TypeError(f"{name}: expected a numpy array")
+    dt = str(a.dtype)
+    if not dt.endswith(kind):
+        raise TypeError(f"{name}: expected {kind}, got {dt}")
+
+
+class System:
+    """A consistent sparse system A x = b resident on the GPU.
+
+    ``row_ptr`` int64[m+1], ``col`` int32[nnz], ``val`` float64/float32 or
+    bfloat16 bits (uint16/int16/torch.bfloat16, or pass dtype="bf16"),
+    ``b`` float64[m].  All numpy (host) or all torch CUDA tensors (device).
+    """
+
+    def __init__(self, row_ptr, col, val, b, *, n=None, dtype=None, stream=None):
+        L = lib()
+        self.device = _is_torch(row_ptr) and row_ptr.is_cuda
+        _expect(row_ptr, self.device, "int64", "row_ptr")
+        _expect(col, self.device, "int32", "col")
+        _expect(b, self.device, "float64", "b")
+        self.m = int(row_ptr.shape[0]) - 1
+        if n is None:
+            n = int(col.max()) + 1 if int(col.shape[0]) else 1
+        self.n = int(n)
+        self.vals_dtype = _vals_dtype(val, dtype)
+        if stream is None and self.device:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = C.c_void_p()
+        rc = L.asyrk_create(C.byref(h), self.m, self.n, _ptr(row_ptr), _ptr(col), _ptr(val),
+                            self.vals_dtype, _ptr(b), MEM_DEVICE if self.device else MEM_HOST,
+                            stream)
+        _check(rc, "asyrk_create")
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().asyrk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries
+    def info(self) -> dict:
+        inf = SystemInfo()
+        _check(lib().asyrk_system_info_get(self._h, C.byref(inf)), "asyrk_system_info_get")
+        return {f: getattr(inf, f) for f, _ in SystemInfo._fields_}
+
+    def set_rhs(self, b):
+        _expect(b, self.device, "float64", "b")
+        _check(lib().asyrk_set_rhs(self._h, _ptr(b)), "asyrk_set_rhs")
+
+    def residual(self, x, r_out=None) -> float:
+        """||b - A x||^2 in FP64 (r_out, if given, receives b - A x)."""
+        _expect(x, self.device, "float64", "x")
+        v = C.c_double()
+        _check(lib().asyrk_residual(self._h, _ptr(x), _ptr(r_out), C.byref(v)), "asyrk_residual")
+        return v.value
+
+    def sample_rows(self, seed, count, ticket0=0, stream_id=0, uniform=False, rows_out=None,
+                    coords_out=None):
+        """Rows (and Algorithm 1 positions) the device sampler draws for tickets."""
+        if rows_out is None:
+            if self.device:
+                import torch
+                rows_out = torch.empty(count, dtype=torch.int32, device="cuda")
+            else:
+                rows_out = np.empty(count, dtype=np.int32)
+        _check(lib().asyrk_sample_rows(self._h, seed, stream_id, SAMPLE_UNIFORM if uniform else SAMPLE_NORM2,
+                                       ticket0, count, _ptr(rows_out), _ptr(coords_out)),
+               "asyrk_sample_rows")
+        return rows_out
+
+    def lambda_max(self, iters=60, seed=0):
+        """(lambda_max(A^T A) by power iteration, Corollary 1's largest tau or -1)."""
+        lam, tau = C.c_double(), C.c_double()
+        _check(lib().asyrk_lambda_max(self._h, iters, seed, C.byref(lam), C.byref(tau)),
+               "asyrk_lambda_max")
+        return lam.value, tau.value
+
+    # -- the method
+    def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
+              update="all", lanes=0, in_flight=0, tol=0.0, x_ref=None, check_every=1,
+              refine=False, inner_sweeps=0, stream_id=0, trace=False, ticket0=0, cancel=None,
+              history=0) -> dict:
+        """Run from x (float64, overwritten with the result).  Returns the stats
+        as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
+        "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
+        _expect(x, self.device, "float64", "x")
+        if x_ref is not None:
+            _expect(x_ref, self.device, "float64", "x_ref")
+        p = SolveParams()
+        lib().asyrk_solve_params_init(C.byref(p))
+        p.mode = {"async": ASYNC, "replay": REPLAY}[mode]
+        p.sampling = {"norm2": SAMPLE_NORM2, "uniform": SAMPLE_UNIFORM}[sampling]
+        p.update = {"all": UPDATE_ALL, "one": UPDATE_ONE}[update]
+        p.lanes = lanes
+        p.in_flight = in_flight
+        p.tol = tol
+        p.x_ref = _ptr(x_ref)
+        p.check_every = check_every
+        p.refine = int(bool(refine))
+        p.inner_sweeps = inner_sweeps
+        p.stream_id = stream_id
+        p.trace = int(bool(trace))
+        p.ticket0 = ticket0
+        if cancel is not None:
+            if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):
+                raise TypeError("cancel: expected a numpy int32 array")
+            p.cancel = cancel.ctypes.data
+        hist = None
+        if history:
+            hist = np.zeros(int(history), dtype=np.float64)
+            p.history = hist.ctypes.data
+            p.history_cap = hist.size
+        st = SolveStats()
+        rc = lib().asyrk_solve(self._h, _ptr(x), float(gamma), int(sweeps), int(seed), C.byref(p),
+                               C.byref(st))
+        if rc != 0 and rc not in _SOFT:
+            _check(rc, "asyrk_solve")
+        out = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+        out["status"] = STATUS[rc]
+        if hist is not None:
+            out["history"] = hist[: st.history_len].copy()
+        if not math.isfinite(out["final_err"]):
+            out["final_err"] = float("nan")
+        return out
+
+
+def probe_copy(nbytes=1 << 30, iters=20) -> float:
+    """Streaming copy bandwidth in GB/s (read + write bytes)."""
+    v = C.c_double()
+    _check(lib().asyrk_probe_copy(nbytes, iters, C.byref(v)), "asyrk_probe_copy")
+    return v.value
+
+
+def probe_scatter(n, count, dtype="f32", kind="load", iters=10) -> float:
+    """Random 4/8-byte accesses per second over a table of n elements
+    (kind "load": agent-coherent loads, "atomic": no-return atomic adds)."""
+    v = C.c_double()
+    _check(lib().asyrk_probe_scatter(n, count, {"f32": F32, "f64": F64}[dtype],
+                                     {"load": 0, "atomic": 1}[kind], iters, C.byref(v)),
+           "asyrk_probe_scatter")
+    return v.value

@@ -1,0 +1,641 @@
+// C ABI of the asynchronous randomized Kaczmarz library (include/asyrk.h):
+// system creation, the solve driver (async, replay, refinement), residual,
+// sampler exposure, lambda_max and device ceilings.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "setup.h"
+
+using namespace asyrk;
+
+struct asyrk_system {
+    int64_t m = 0, n = 0, nnz = 0;
+    int32_t vk = ASYRK_F32;
+    int32_t mem = ASYRK_MEM_HOST;
+    hipStream_t st = nullptr;
+    int64_t mu = 0, nu = 0, fixed_nnz = 0, stride = 0;
+    double fro2 = 0.0;
+    Rows rows{};
+    uint8_t *d_rec = nullptr;
+    RowLoc *d_loc = nullptr;
+    double *d_b64 = nullptr;
+    void *d_x = nullptr;          // sweep iterate (float or double)
+    double *d_x64 = nullptr;      // FP64 master iterate
+    double *d_xref = nullptr;     // FP64 reference for the error monitor
+    double *d_part = nullptr;     // reduction partials
+    double *d_scalar = nullptr;   // 4 device scalars
+    double *h_pin = nullptr;      // 4 pinned host scalars
+    uint64_t *d_trace = nullptr;
+    int64_t trace_cap = 0;
+    int64_t device_bytes = 0;
+    bool rec_b_dirty = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+namespace {
+
+thread_local const char *g_last = "";
+
+bool iter_is_f32(const asyrk_system *s) { return s->vk != ASYRK_F64; }
+size_t x_bytes(const asyrk_system *s) { return iter_is_f32(s) ? 4 : 8; }
+
+asyrk_status dev_fail(hipError_t e) {
+    g_last = hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? ASYRK_ERR_OOM : ASYRK_ERR_DEVICE;
+}
+
+#define HIP_OK(expr)                                  \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return dev_fail(_e);    \
+    } while (0)
+
+template <class T>
+hipError_t dmalloc(asyrk_system *s, T **p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e == hipSuccess) s->device_bytes += (int64_t)bytes;
+    return e;
+}
+
+void free_system(asyrk_system *s) {
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    (void)hipFree(s->d_rec);
+    (void)hipFree(s->d_loc);
+    (void)hipFree(s->d_b64);
+    (void)hipFree(s->d_x);
+    (void)hipFree(s->d_x64);
+    (void)hipFree(s->d_xref);
+    (void)hipFree(s->d_part);
+    (void)hipFree(s->d_scalar);
+    (void)hipFree(s->d_trace);
+    if (s->h_pin) (void)hipHostFree(s->h_pin);
+    if (s->e0) (void)hipEventDestroy(s->e0);
+    if (s->e1) (void)hipEventDestroy(s->e1);
+    delete s;
+}
+
+// Copy an input array to host memory if it lives on the device.
+template <class T>
+asyrk_status to_host(const asyrk_system *s, int mem, const T *src, size_t count, std::vector<T> &buf,
+                     const T *&out) {
+    if (mem == ASYRK_MEM_HOST || src == nullptr) {
+        out = src;
+        return ASYRK_OK;
+    }
+    try {
+        buf.resize(count);
+    } catch (...) {
+        return ASYRK_ERR_OOM;
+    }
+    HIP_OK(hipMemcpy(buf.data(), src, count * sizeof(T), hipMemcpyDeviceToHost));
+    out = buf.data();
+    (void)s;
+    return ASYRK_OK;
+}
+
+// Reduction to one device scalar, then to pinned host memory; synchronizes.
+asyrk_status fetch_scalar(asyrk_system *s, int nparts, double *host_out) {
+    HIP_OK(launch_finish_sum(s->d_part, nparts, s->d_scalar, s->st));
+    HIP_OK(hipMemcpyAsync(s->h_pin, s->d_scalar, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    *host_out = s->h_pin[0];
+    return ASYRK_OK;
+}
+
+int auto_lanes(const asyrk_system *s) {
+    const Geom g = geom_of(s->vk);
+    const double units = ((double)s->nnz / (double)s->m) / g.U;
+    int G = 1;
+    while (G < 16 && G < units / 2.0) G *= 2;
+    return G;
+}
+
+double lambda_mp(const asyrk_system *s) {
+    const double r = std::sqrt((double)s->n / (double)s->m);
+    return (1.0 + r) * (1.0 + r) * s->fro2 / (double)s->n;
+}
+
+int64_t auto_in_flight(const asyrk_system *s) {
+    const double tmax = std::floor(s->fro2 / (2.0 * M_E * lambda_mp(s)));
+    int64_t R = (int64_t)tmax;
+    if (R < 1) R = 1;
+    if (R > 65536) R = 65536;
+    return R;
+}
+
+struct Monitor {
+    bool use_ref = false;
+    double ref_norm2 = 0.0;
+    double b_norm2 = 0.0;
+};
+
+// Monitored error of an iterate on the device (x of the sweep dtype or FP64).
+asyrk_status monitored_error(asyrk_system *s, const Monitor &mon, const void *x, int x_f32, double *err) {
+    double v = 0.0;
+    if (mon.use_ref) {
+        HIP_OK(launch_sumsq_diff(x, x_f32, s->d_xref, s->n, s->d_part, kResidualBlocks, s->st));
+        asyrk_status rc = fetch_scalar(s, kResidualBlocks, &v);
+        if (rc) return rc;
+        *err = mon.ref_norm2 > 0 ? std::sqrt(v / mon.ref_norm2) : std::sqrt(v);
+    } else {
+        HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, x, x_f32, nullptr, 0, s->d_part, kResidualBlocks, s->st));
+        asyrk_status rc = fetch_scalar(s, kResidualBlocks, &v);
+        if (rc) return rc;
+        *err = mon.b_norm2 > 0 ? std::sqrt(v / mon.b_norm2) : std::sqrt(v);
+    }
+    return ASYRK_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// =========================================================================
+
+extern "C" {
+
+int asyrk_abi_version(void) { return ASYRK_ABI_VERSION; }
+
+const char *asyrk_status_string(asyrk_status s) {
+    switch (s) {
+        case ASYRK_OK: return "ok";
+        case ASYRK_ERR_INVALID_ARG: return "invalid argument";
+        case ASYRK_ERR_ZERO_ROW: return "A has a zero row";
+        case ASYRK_ERR_OOM: return "out of memory";
+        case ASYRK_ERR_DEVICE: return "HIP runtime error";
+        case ASYRK_ERR_NOT_CONVERGED: return "tolerance not reached within the sweep budget";
+        case ASYRK_ERR_DIVERGED: return "iteration diverged";
+        case ASYRK_ERR_CANCELLED: return "cancelled";
+        case ASYRK_ERR_UNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char *asyrk_last_error_message(void) { return g_last; }
+
+void asyrk_solve_params_init(asyrk_solve_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->mode = ASYRK_ASYNC;
+    p->sampling = ASYRK_SAMPLE_NORM2;
+    p->update = ASYRK_UPDATE_ALL;
+    p->check_every = 1;
+}
+
+asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, int32_t vals_dtype, const double *b,
+                          int32_t mem, void *stream) {
+    if (!out) return ASYRK_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (mem != ASYRK_MEM_HOST && mem != ASYRK_MEM_DEVICE) return ASYRK_ERR_INVALID_ARG;
+    if (m < 1 || n < 1 || m > INT32_MAX || n > INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    if (vals_dtype != ASYRK_F64 && vals_dtype != ASYRK_F32 && vals_dtype != ASYRK_BF16)
+        return ASYRK_ERR_INVALID_ARG;
+    if (!row_ptr || !b) return ASYRK_ERR_INVALID_ARG;
+
+    asyrk_system tmp_for_copy;
+    std::vector<int64_t> rp_buf;
+    std::vector<int32_t> col_buf;
+    std::vector<uint8_t> val_buf;
+    std::vector<double> b_buf;
+    const int64_t *rp = nullptr;
+    const int32_t *cl = nullptr;
+    const uint8_t *vl = nullptr;
+    const double *bb = nullptr;
+    asyrk_status rc = to_host(&tmp_for_copy, mem, row_ptr, (size_t)m + 1, rp_buf, rp);
+    if (rc) return rc;
+    if (rp[0] != 0 || rp[m] < 0 || rp[m] >= INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    const int64_t nnz = rp[m];
+    const Geom g = geom_of(vals_dtype);
+    if (nnz > 0 && (!col_idx || !vals)) return ASYRK_ERR_INVALID_ARG;
+    rc = to_host(&tmp_for_copy, mem, col_idx, (size_t)nnz, col_buf, cl);
+    if (rc) return rc;
+    rc = to_host(&tmp_for_copy, mem, static_cast<const uint8_t *>(vals), (size_t)nnz * g.VB, val_buf, vl);
+    if (rc) return rc;
+    rc = to_host(&tmp_for_copy, mem, b, (size_t)m, b_buf, bb);
+    if (rc) return rc;
+
+    SetupResult res;
+    rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, res);
+    if (rc) return rc;
+    rc = pack_records(m, rp, cl, vl, vals_dtype, bb, res);
+    if (rc) return rc;
+
+    asyrk_system *s = new (std::nothrow) asyrk_system();
+    if (!s) return ASYRK_ERR_OOM;
+    s->m = m;
+    s->n = n;
+    s->nnz = nnz;
+    s->vk = vals_dtype;
+    s->mem = mem;
+    s->st = (hipStream_t)stream;
+    s->mu = res.mu;
+    s->nu = res.nu;
+    s->fixed_nnz = res.fixed_nnz;
+    s->stride = res.stride;
+    s->fro2 = res.fro2;
+
+    hipError_t e = hipSuccess;
+#define TRY(expr)                       \
+    do {                                \
+        e = (expr);                     \
+        if (e != hipSuccess) goto fail; \
+    } while (0)
+    TRY(dmalloc(s, &s->d_rec, res.rec.size()));
+    if (res.fixed_nnz == 0) TRY(dmalloc(s, &s->d_loc, res.loc.size() * sizeof(RowLoc)));
+    TRY(dmalloc(s, &s->d_b64, (size_t)m * sizeof(double)));
+    TRY(dmalloc(s, &s->d_x, (size_t)n * x_bytes(s)));
+    TRY(dmalloc(s, &s->d_x64, (size_t)n * sizeof(double)));
+    TRY(dmalloc(s, &s->d_xref, (size_t)n * sizeof(double)));
+    TRY(dmalloc(s, &s->d_part, (size_t)kResidualBlocks * sizeof(double)));
+    TRY(dmalloc(s, &s->d_scalar, 4 * sizeof(double)));
+    TRY(hipHostMalloc((void **)&s->h_pin, 4 * sizeof(double), hipHostMallocDefault));
+    TRY(hipEventCreate(&s->e0));
+    TRY(hipEventCreate(&s->e1));
+    TRY(hipMemcpyAsync(s->d_rec, res.rec.data(), res.rec.size(), hipMemcpyHostToDevice, s->st));
+    if (res.fixed_nnz == 0)
+        TRY(hipMemcpyAsync(s->d_loc, res.loc.data(), res.loc.size() * sizeof(RowLoc), hipMemcpyHostToDevice,
+                           s->st));
+    TRY(hipMemcpyAsync(s->d_b64, bb, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s->st));
+    TRY(hipStreamSynchronize(s->st));
+#undef TRY
+    s->rows.rec = s->d_rec;
+    s->rows.loc = s->d_loc;
+    s->rows.stride = s->stride;
+    s->rows.fixed_nnz = (int32_t)s->fixed_nnz;
+    s->rows.m = (int32_t)m;
+    *out = s;
+    return ASYRK_OK;
+fail:
+    free_system(s);
+    return dev_fail(e);
+}
+
+asyrk_status asyrk_destroy(asyrk_system *s) {
+    free_system(s);
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *info) {
+    if (!s || !info) return ASYRK_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof *info);
+    info->m = s->m;
+    info->n = s->n;
+    info->nnz = s->nnz;
+    info->mu = s->mu;
+    info->nu = s->nu;
+    info->fixed_nnz = s->fixed_nnz;
+    info->record_stride = s->stride;
+    info->device_bytes = s->device_bytes;
+    info->vals_dtype = s->vk;
+    info->iter_dtype = s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32;
+    info->fro2 = s->fro2;
+    info->lambda_mp = lambda_mp(s);
+    const Geom g = geom_of(s->vk);
+    const int sc = s->vk == ASYRK_F64 ? 8 : 4;  // b_i and w_i in the sweep dtype, 4-byte start
+    info->record_bytes_per_row =
+        (int64_t)std::llround((double)s->nnz / (double)s->m * (4 + g.VB)) + 2 * sc + 4;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b) {
+    if (!s || !b) return ASYRK_ERR_INVALID_ARG;
+    std::vector<double> buf;
+    const double *hb = nullptr;
+    asyrk_status rc = to_host(s, s->mem, b, (size_t)s->m, buf, hb);
+    if (rc) return rc;
+    for (int64_t i = 0; i < s->m; ++i)
+        if (!std::isfinite(hb[i])) return ASYRK_ERR_INVALID_ARG;
+    HIP_OK(hipMemcpyAsync(s->d_b64, hb, (size_t)s->m * sizeof(double), hipMemcpyHostToDevice, s->st));
+    HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    s->rec_b_dirty = false;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_residual(asyrk_system *s, const double *x, double *r_out, double *norm2_out) {
+    if (!s || !x || !norm2_out) return ASYRK_ERR_INVALID_ARG;
+    const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_OK(hipMemcpyAsync(s->d_x64, x, (size_t)s->n * sizeof(double), h2d, s->st));
+    double *r_dev = nullptr;
+    if (r_out) {
+        if (s->mem == ASYRK_MEM_DEVICE)
+            r_dev = r_out;
+        else
+            HIP_OK(hipMalloc((void **)&r_dev, (size_t)s->m * sizeof(double)));
+    }
+    hipError_t e = launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, r_dev, 0, s->d_part,
+                                   kResidualBlocks, s->st);
+    double v = 0.0;
+    asyrk_status rc = e == hipSuccess ? fetch_scalar(s, kResidualBlocks, &v) : dev_fail(e);
+    if (rc == ASYRK_OK && r_out && s->mem == ASYRK_MEM_HOST) {
+        e = hipMemcpy(r_out, r_dev, (size_t)s->m * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = dev_fail(e);
+    }
+    if (r_dev && s->mem == ASYRK_MEM_HOST) (void)hipFree(r_dev);
+    if (rc == ASYRK_OK) *norm2_out = v;
+    return rc;
+}
+
+asyrk_status asyrk_sample_rows(asyrk_system *s, uint64_t seed, uint32_t stream_id, int32_t sampling,
+                               int64_t ticket0, int64_t count, int32_t *rows_out, int32_t *coords_out) {
+    if (!s || !rows_out || count < 0 || ticket0 < 0) return ASYRK_ERR_INVALID_ARG;
+    if (sampling != ASYRK_SAMPLE_NORM2 && sampling != ASYRK_SAMPLE_UNIFORM) return ASYRK_ERR_INVALID_ARG;
+    if (count == 0) return ASYRK_OK;
+    int32_t *dr = rows_out, *dc = coords_out;
+    const bool host = s->mem == ASYRK_MEM_HOST;
+    if (host) {
+        HIP_OK(hipMalloc((void **)&dr, (size_t)count * 4 * 2));
+        dc = coords_out ? dr + count : nullptr;
+    }
+    hipError_t e = launch_sample_rows(s->vk, s->rows, ticket0, count, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                      stream_id, sampling == ASYRK_SAMPLE_UNIFORM, dr, dc, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e == hipSuccess && host) {
+        e = hipMemcpy(rows_out, dr, (size_t)count * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && coords_out) e = hipMemcpy(coords_out, dc, (size_t)count * 4, hipMemcpyDeviceToHost);
+    }
+    if (host) (void)hipFree(dr);
+    return e == hipSuccess ? ASYRK_OK : dev_fail(e);
+}
+
+asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
+                              double *tau_max_out) {
+    if (!s || !lambda_out || iters < 1) return ASYRK_ERR_INVALID_ARG;
+    double *v = nullptr, *z = nullptr, *y = nullptr;
+    HIP_OK(hipMalloc((void **)&v, (size_t)s->n * 8));
+    hipError_t e = hipMalloc((void **)&z, (size_t)s->n * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&y, (size_t)s->m * 8);
+    double lam = 0.0, nrm2 = 0.0;
+    asyrk_status rc = ASYRK_OK;
+    if (e == hipSuccess) e = launch_random_fill(v, s->n, (uint32_t)seed, (uint32_t)(seed >> 32), s->st);
+    // v <- v / ||v||
+    if (e == hipSuccess) e = launch_sumsq_diff(v, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
+    if (e == hipSuccess) e = launch_finish_sum(s->d_part, kResidualBlocks, s->d_scalar, s->st);
+    if (e == hipSuccess) e = launch_scale(v, s->n, s->d_scalar, s->st);
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        // y = -A v (residual with b = 0), z = A^T y, v = z / ||z||
+        e = launch_residual(s->vk, s->rows, nullptr, v, 0, y, 0, s->d_part, kResidualBlocks, s->st);
+        if (e == hipSuccess) e = launch_zero(z, s->n * 8, s->st);
+        if (e == hipSuccess) e = launch_scatter_rows(s->vk, s->rows, y, z, s->st);
+        if (e == hipSuccess) e = launch_sumsq_diff(z, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
+        if (e == hipSuccess) e = launch_finish_sum(s->d_part, kResidualBlocks, s->d_scalar, s->st);
+        if (e == hipSuccess) e = launch_scale(z, s->n, s->d_scalar, s->st);
+        if (e == hipSuccess) std::swap(v, z);
+    }
+    // Rayleigh quotient ||A v||^2 with ||v|| = 1
+    if (e == hipSuccess)
+        e = launch_residual(s->vk, s->rows, nullptr, v, 0, nullptr, 0, s->d_part, kResidualBlocks, s->st);
+    if (e == hipSuccess) {
+        rc = fetch_scalar(s, kResidualBlocks, &nrm2);
+        lam = nrm2;
+    }
+    (void)hipFree(v);
+    (void)hipFree(z);
+    (void)hipFree(y);
+    if (e != hipSuccess) return dev_fail(e);
+    if (rc) return rc;
+    *lambda_out = lam;
+    if (tau_max_out) {
+        const double t = std::floor(s->fro2 / (2.0 * M_E * lam)) - 1.0;
+        *tau_max_out = t >= 0 ? t : -1.0;
+    }
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_probe_copy(int64_t bytes, int32_t iters, double *gbps) {
+    if (bytes < 16 || iters < 1 || !gbps) return ASYRK_ERR_INVALID_ARG;
+    HIP_OK(probe_copy(bytes, iters, gbps));
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_t kind, int32_t iters,
+                                 double *per_s) {
+    if (n < 1 || n > INT32_MAX || count < 1 || iters < 1 || !per_s) return ASYRK_ERR_INVALID_ARG;
+    if ((dtype != ASYRK_F32 && dtype != ASYRK_F64) || (kind != 0 && kind != 1)) return ASYRK_ERR_INVALID_ARG;
+    HIP_OK(probe_scatter(n, count, dtype, kind, iters, per_s));
+    return ASYRK_OK;
+}
+
+// ------------------------------------------------------------------- solve
+
+static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int G, int64_t R, double gamma,
+                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
+                               double *win_max_ticks, double *win_sum_ticks, double *win_cnt) {
+    SweepArgs a{};
+    a.rows = s->rows;
+    a.x = s->d_x;
+    a.t_begin = t_begin;
+    a.t_end = t_end;
+    a.R = R;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.stream_id = p.stream_id;
+    a.uniform = p.sampling == ASYRK_SAMPLE_UNIFORM;
+    a.update_one = p.update == ASYRK_UPDATE_ONE;
+    a.replay = p.mode == ASYRK_REPLAY;
+    a.gamma = gamma;
+    a.trace = p.trace ? s->d_trace : nullptr;
+    HIP_OK(hipEventRecord(s->e0, s->st));
+    HIP_OK(launch_sweep(s->vk, G, a, s->st));
+    HIP_OK(hipEventRecord(s->e1, s->st));
+    HIP_OK(hipEventSynchronize(s->e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
+    *gpu_s += ms * 1e-3;
+    if (p.trace) {
+        std::vector<uint64_t> tr((size_t)R * 3);
+        HIP_OK(hipMemcpy(tr.data(), s->d_trace, tr.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t w = 0; w < R; ++w) {
+            *win_max_ticks = std::max(*win_max_ticks, (double)tr[3 * w]);
+            *win_sum_ticks += (double)tr[3 * w + 1];
+            *win_cnt += (double)tr[3 * w + 2];
+        }
+    }
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweeps, uint64_t seed,
+                         const asyrk_solve_params *pin, asyrk_solve_stats *st) {
+    const double wall0 = now_s();
+    if (!s || !x) return ASYRK_ERR_INVALID_ARG;
+    asyrk_solve_params p;
+    if (pin)
+        p = *pin;
+    else
+        asyrk_solve_params_init(&p);
+    if (!(gamma > 0.0 && gamma < 2.0) || sweeps < 0) return ASYRK_ERR_INVALID_ARG;
+    if (p.mode != ASYRK_ASYNC && p.mode != ASYRK_REPLAY) return ASYRK_ERR_INVALID_ARG;
+    if (p.sampling != ASYRK_SAMPLE_NORM2 && p.sampling != ASYRK_SAMPLE_UNIFORM) return ASYRK_ERR_INVALID_ARG;
+    if (p.update != ASYRK_UPDATE_ALL && p.update != ASYRK_UPDATE_ONE) return ASYRK_ERR_INVALID_ARG;
+    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 2 && p.lanes != 4 && p.lanes != 8 && p.lanes != 16)
+        return ASYRK_ERR_INVALID_ARG;
+    if (p.in_flight < 0 || p.check_every < 1 || !(p.tol >= 0.0) || !std::isfinite(p.tol) || p.ticket0 < 0 ||
+        p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
+        return ASYRK_ERR_INVALID_ARG;
+    if (p.refine && s->vk == ASYRK_F64) return ASYRK_ERR_UNSUPPORTED;
+    if (p.refine && (p.mode == ASYRK_REPLAY || p.update == ASYRK_UPDATE_ONE)) return ASYRK_ERR_UNSUPPORTED;
+    if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
+
+    const int G = p.lanes ? p.lanes : auto_lanes(s);
+    int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
+    if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
+    const bool f32 = iter_is_f32(s);
+    const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind d2h = s->mem == ASYRK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+
+    asyrk_solve_stats S;
+    std::memset(&S, 0, sizeof S);
+    S.final_err = NAN;
+    S.in_flight = R;
+    S.lanes = G;
+    S.tau_design = (double)(R - 1);
+
+    // inputs
+    HIP_OK(hipMemcpyAsync(s->d_x64, x, (size_t)s->n * 8, h2d, s->st));
+    Monitor mon;
+    if (p.x_ref) {
+        mon.use_ref = true;
+        HIP_OK(hipMemcpyAsync(s->d_xref, p.x_ref, (size_t)s->n * 8, h2d, s->st));
+        HIP_OK(launch_sumsq_diff(s->d_xref, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st));
+        asyrk_status rc = fetch_scalar(s, kResidualBlocks, &mon.ref_norm2);
+        if (rc) return rc;
+    } else {
+        HIP_OK(launch_sumsq_diff(s->d_b64, 0, nullptr, s->m, s->d_part, kResidualBlocks, s->st));
+        asyrk_status rc = fetch_scalar(s, kResidualBlocks, &mon.b_norm2);
+        if (rc) return rc;
+    }
+    if (s->rec_b_dirty) {
+        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+        s->rec_b_dirty = false;
+    }
+    if (p.trace) {
+        if (s->trace_cap < R) {
+            (void)hipFree(s->d_trace);
+            s->d_trace = nullptr;
+            s->trace_cap = 0;
+            HIP_OK(hipMalloc((void **)&s->d_trace, (size_t)R * 3 * 8));
+            s->trace_cap = R;
+        }
+    }
+    const bool monitor = p.tol > 0.0 || p.history_cap > 0 || p.cancel != nullptr;
+    double err0 = NAN;
+    auto push_hist = [&](double e) {
+        if (S.history_len < p.history_cap) p.history[S.history_len++] = e;
+    };
+    const double t_setup = now_s();
+
+    double gpu_s = 0.0, wmax = 0.0, wsum = 0.0, wcnt = 0.0;
+    asyrk_status result = ASYRK_OK;
+    int64_t ticket = p.ticket0;
+    int64_t done = 0;
+
+    if (!p.refine) {
+        HIP_OK(launch_cast_to_iter(s->d_x64, s->d_x, f32, s->n, s->st));
+        if (monitor) {
+            asyrk_status rc = monitored_error(s, mon, s->d_x, f32, &err0);
+            if (rc) return rc;
+            push_hist(err0);
+            S.final_err = err0;
+            if (p.tol > 0.0 && err0 <= p.tol) sweeps = 0;
+        }
+        while (done < sweeps) {
+            const int64_t c = std::min<int64_t>(p.check_every, sweeps - done);
+            asyrk_status rc = run_sweeps(s, p, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum,
+                                         &wcnt);
+            if (rc) return rc;
+            ticket += c * s->m;
+            done += c;
+            if (monitor || done == sweeps) {
+                double e = 0.0;
+                rc = monitored_error(s, mon, s->d_x, f32, &e);
+                if (rc) return rc;
+                S.final_err = e;
+                push_hist(e);
+                if (!std::isfinite(e) || (std::isfinite(err0) && err0 > 0 && e > 1e6 * err0)) {
+                    result = ASYRK_ERR_DIVERGED;
+                    break;
+                }
+                if (p.tol > 0.0 && e <= p.tol) break;
+                if (p.cancel && *p.cancel) {
+                    result = ASYRK_ERR_CANCELLED;
+                    break;
+                }
+            }
+        }
+        HIP_OK(launch_iter_to_f64(s->d_x, f32, s->d_x64, s->n, 0, s->st));
+        if (result == ASYRK_OK && p.tol > 0.0 && !(S.final_err <= p.tol)) result = ASYRK_ERR_NOT_CONVERGED;
+    } else {
+        // FP64 iterative refinement: x64 master, FP32 correction d on A d = fp32(b - A x64)
+        const int64_t inner = p.inner_sweeps ? p.inner_sweeps : 20;
+        asyrk_status rc = monitored_error(s, mon, s->d_x64, 0, &err0);
+        if (rc) return rc;
+        push_hist(err0);
+        S.final_err = err0;
+        bool ok = p.tol > 0.0 && err0 <= p.tol;
+        while (!ok && done < sweeps) {
+            // r = b - A x64 into the records' b fields (FP32), d = 0
+            HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, nullptr, 1, s->d_part, kResidualBlocks,
+                                   s->st));
+            s->rec_b_dirty = true;
+            HIP_OK(launch_zero(s->d_x, (int64_t)s->n * 4, s->st));
+            const int64_t c = std::min<int64_t>(inner, sweeps - done);
+            rc = run_sweeps(s, p, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum, &wcnt);
+            if (rc) return rc;
+            ticket += c * s->m;
+            done += c;
+            HIP_OK(launch_iter_to_f64(s->d_x, 1, s->d_x64, s->n, 1, s->st));
+            S.outer_iters++;
+            double e = 0.0;
+            rc = monitored_error(s, mon, s->d_x64, 0, &e);
+            if (rc) return rc;
+            S.final_err = e;
+            push_hist(e);
+            if (!std::isfinite(e) || (err0 > 0 && e > 1e6 * err0)) {
+                result = ASYRK_ERR_DIVERGED;
+                break;
+            }
+            if (p.tol > 0.0 && e <= p.tol) ok = true;
+            if (p.cancel && *p.cancel) {
+                result = ASYRK_ERR_CANCELLED;
+                break;
+            }
+        }
+        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+        s->rec_b_dirty = false;
+        if (result == ASYRK_OK && p.tol > 0.0 && !ok) result = ASYRK_ERR_NOT_CONVERGED;
+    }
+    HIP_OK(hipMemcpyAsync(x, s->d_x64, (size_t)s->n * 8, d2h, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+
+    S.sweeps_done = done;
+    S.row_updates = done * s->m;
+    S.next_ticket = ticket;
+    S.seconds = now_s() - t_setup;
+    (void)wall0;
+    S.sweep_seconds = gpu_s;
+    S.rows_per_s = gpu_s > 0 ? (double)S.row_updates / gpu_s : 0.0;
+    if (p.trace && wcnt > 0) {
+        int clock_khz = 0;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+        const double ns_per_tick = clock_khz > 0 ? 1e6 / clock_khz : 10.0;
+        S.window_ns_mean = wsum / wcnt * ns_per_tick;
+        S.window_ns_max = wmax * ns_per_tick;
+        S.tau_obs_mean = S.window_ns_mean * 1e-9 * S.rows_per_s;
+        S.tau_obs_max = S.window_ns_max * 1e-9 * S.rows_per_s;
+    }
+    if (st) *st = S;
+    return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,659 @@
+// gfx950 kernels of the asynchronous randomized Kaczmarz library.
+//
+// Hot path (sweep_kernel): each group of G lanes is one row worker (Section 3
+// of the paper: every worker draws a row, reads x on the row's support without
+// locking, forms a_i^T x - b_i and writes every coordinate of supp(a_i) with
+// an atomic addition; eq. (2) with step length gamma).  Workers take tickets
+// j = t_begin + w, + R, + 2R, ... so R workers are in flight at once.
+//
+// Memory behaviour:
+//   * row records stream from HBM with 16-byte loads, one unit per lane;
+//   * x is read with agent-scope relaxed atomic loads (global_load sc1) so a
+//     read sees every atomic already performed by any XCD, and written with
+//     no-return global_atomic_add_f32/f64; x (4-16 MB) lives in the caches;
+//   * no LDS and no MFMA: there is no dense contraction in this method.
+#include "internal.h"
+
+namespace asyrk {
+
+// ---------------------------------------------------------------- utilities
+
+template <class T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __uint_as_float(bits << 16); }
+
+__device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
+    if (r.loc == nullptr) {
+        rec = r.rec + (int64_t)i * r.stride;
+        nnz = r.fixed_nnz;
+    } else {
+        const RowLoc l = r.loc[i];
+        rec = r.rec + (int64_t)l.off16 * 16;
+        nnz = (int)l.nnz;
+    }
+}
+
+template <int VK> struct Unit;
+template <> struct Unit<ASYRK_F32> {
+    int c[4];
+    float v[4];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 ci = *reinterpret_cast<const int4 *>(p);
+        const float4 vi = *reinterpret_cast<const float4 *>(p + 16);
+        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
+        v[0] = vi.x; v[1] = vi.y; v[2] = vi.z; v[3] = vi.w;
+    }
+};
+template <> struct Unit<ASYRK_BF16> {
+    int c[8];
+    float v[8];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 c0 = *reinterpret_cast<const int4 *>(p);
+        const int4 c1 = *reinterpret_cast<const int4 *>(p + 16);
+        const uint4 vb = *reinterpret_cast<const uint4 *>(p + 32);
+        c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w;
+        c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
+        v[0] = bf16_to_f32(vb.x & 0xffffu); v[1] = bf16_to_f32(vb.x >> 16);
+        v[2] = bf16_to_f32(vb.y & 0xffffu); v[3] = bf16_to_f32(vb.y >> 16);
+        v[4] = bf16_to_f32(vb.z & 0xffffu); v[5] = bf16_to_f32(vb.z >> 16);
+        v[6] = bf16_to_f32(vb.w & 0xffffu); v[7] = bf16_to_f32(vb.w >> 16);
+    }
+};
+template <> struct Unit<ASYRK_F64> {
+    int c[4];
+    double v[4];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 ci = *reinterpret_cast<const int4 *>(p);
+        const double2 v0 = *reinterpret_cast<const double2 *>(p + 16);
+        const double2 v1 = *reinterpret_cast<const double2 *>(p + 32);
+        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
+        v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
+    }
+};
+
+template <int VK>
+__device__ __forceinline__ typename VT<VK>::hdr_t load_hdr(const uint8_t *rec) {
+    return *reinterpret_cast<const typename VT<VK>::hdr_t *>(rec);
+}
+
+// Entry `pos` of a row record (column, value), read directly.
+template <int VK>
+__device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
+                                           typename VT<VK>::x_t &v) {
+    using T = VT<VK>;
+    const uint8_t *u = rec + T::HB + (int64_t)(pos / T::U) * T::UB;
+    const int e = pos % T::U;
+    c = *reinterpret_cast<const int *>(u + 4 * e);
+    if constexpr (VK == ASYRK_BF16)
+        v = bf16_to_f32(*reinterpret_cast<const uint16_t *>(u + T::COLB + 2 * e));
+    else
+        v = *reinterpret_cast<const typename T::val_t *>(u + T::COLB + T::VB * e);
+}
+
+template <int G, class X>
+__device__ __forceinline__ X group_sum(X v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Units per lane kept in registers: a row of up to G * UPL units is read
+// once; longer rows are read twice (dot pass, then scatter pass).
+template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; };
+
+// ---------------------------------------------------------------- sweep
+
+template <int VK, int G>
+__global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
+    using T = VT<VK>;
+    using X = typename T::x_t;
+    using H = typename T::hdr_t;
+    constexpr int U = T::U;
+    constexpr int UPL = Upl<G>::value;
+
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / G) + (lane / G);
+    if (worker >= a.R) return;  // whole groups leave together
+
+    X *x = reinterpret_cast<X *>(a.x);
+    const X gamma = (X)a.gamma;
+    uint64_t tr_max = 0, tr_sum = 0, tr_cnt = 0;
+
+    for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R) {
+        // a1: ticket -> bucket -> row (alias decision needs the header)
+        const U4 u = draw(j, a.stream_id, a.key0, a.key1);
+        uint32_t i = bucket_of(u.a, u.b, (uint32_t)a.rows.m);
+        const uint8_t *rec;
+        int nnz;
+        locate(a.rows, i, rec, nnz);
+        H h = load_hdr<VK>(rec);
+        int nunits = (nnz + U - 1) / U;
+        // a2: speculative fetch of bucket row's units (the alias is rarely taken)
+        Unit<VK> un[UPL];
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int uu = gl + q * G;
+            if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+        }
+        if (!a.uniform && !(u.c < h.thresh)) {
+            i = (uint32_t)h.alias;
+            locate(a.rows, i, rec, nnz);
+            h = load_hdr<VK>(rec);
+            nunits = (nnz + U - 1) / U;
+#pragma unroll
+            for (int q = 0; q < UPL; ++q) {
+                const int uu = gl + q * G;
+                if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+            }
+        }
+
+        uint64_t t0 = 0;
+        if (a.trace) t0 = wall_clock64();
+
+        // a3: gather-dot over supp(a_i)
+        X acc = (X)0;
+        const bool one_pass = nunits <= G * UPL;
+        if (one_pass) {
+#pragma unroll
+            for (int q = 0; q < UPL; ++q) {
+                const int uu = gl + q * G;
+                if (uu < nunits) {
+#pragma unroll
+                    for (int e = 0; e < U; ++e) {
+                        if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                    }
+                }
+            }
+        } else {
+            for (int base = 0; base < nunits; base += G * UPL) {
+                if (base > 0) {
+#pragma unroll
+                    for (int q = 0; q < UPL; ++q) {
+                        const int uu = base + gl + q * G;
+                        if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < UPL; ++q) {
+                    const int uu = base + gl + q * G;
+                    if (uu < nunits) {
+#pragma unroll
+                        for (int e = 0; e < U; ++e)
+                            if (uu * U + e < nnz)
+                                acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                    }
+                }
+            }
+        }
+        acc = group_sum<G>(acc);
+
+        // a4: step s = gamma * (a_i^T x - b_i) / ||a_i||^2
+        const X r = acc - (X)h.b;
+
+        // a5: lock-free scatter
+        if (!a.update_one) {
+            const X s = gamma * r * (X)h.inv_w;
+            if (one_pass) {
+#pragma unroll
+                for (int q = 0; q < UPL; ++q) {
+                    const int uu = gl + q * G;
+                    if (uu < nunits) {
+#pragma unroll
+                        for (int e = 0; e < U; ++e)
+                            if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                    }
+                }
+            } else {
+                for (int base = 0; base < nunits; base += G * UPL) {
+#pragma unroll
+                    for (int q = 0; q < UPL; ++q) {
+                        const int uu = base + gl + q * G;
+                        if (uu < nunits) {
+                            un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+#pragma unroll
+                            for (int e = 0; e < U; ++e)
+                                if (uu * U + e < nnz)
+                                    unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                        }
+                    }
+                }
+            }
+        } else if (gl == 0) {
+            // Algorithm 1: one coordinate t, step gamma * theta_i
+            const int t = (int)(((uint64_t)u.d * (uint64_t)nnz) >> 32);
+            int c;
+            X v;
+            load_entry<VK>(rec, t, c, v);
+            const X s1 = gamma * (X)nnz * r * (X)h.inv_w;
+            unsafeAtomicAdd(x + c, -s1 * v);
+        }
+
+        if (a.trace) {
+            const uint64_t w = wall_clock64() - t0;
+            tr_max = w > tr_max ? w : tr_max;
+            tr_sum += w;
+            tr_cnt += 1;
+        }
+        if (a.replay) __threadfence();
+    }
+    if (a.trace && gl == 0) {
+        a.trace[3 * worker + 0] = tr_max;
+        a.trace[3 * worker + 1] = tr_sum;
+        a.trace[3 * worker + 2] = tr_cnt;
+    }
+}
+
+template <int VK>
+static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
+    const int64_t threads = a.R * G;
+    const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
+    const int64_t grid = (threads + block - 1) / block;
+    switch (G) {
+        case 1: hipLaunchKernelGGL((sweep_kernel<VK, 1>), dim3(grid), dim3(block), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((sweep_kernel<VK, 2>), dim3(grid), dim3(block), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((sweep_kernel<VK, 4>), dim3(grid), dim3(block), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((sweep_kernel<VK, 8>), dim3(grid), dim3(block), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((sweep_kernel<VK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int vk, int G, const SweepArgs &a, hipStream_t st) {
+    switch (vk) {
+        case ASYRK_F32: return launch_sweep_vk<ASYRK_F32>(G, a, st);
+        case ASYRK_BF16: return launch_sweep_vk<ASYRK_BF16>(G, a, st);
+        case ASYRK_F64: return launch_sweep_vk<ASYRK_F64>(G, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sum of one value per thread into partials[blockIdx.x], fixed order.
+__device__ __forceinline__ void block_sum_store(double v, double *partials) {
+    __shared__ double wsum[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wsum[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += wsum[k];
+        partials[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void finish_sum_kernel(const double *partials, int nparts, double *out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t launch_finish_sum(const double *partials, int nparts, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(256), 0, st, partials, nparts, out);
+    return hipGetLastError();
+}
+
+template <class XI>
+__global__ __launch_bounds__(256) void sumsq_diff_kernel(const XI *x, const double *xr, int64_t n,
+                                                          double *partials) {
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const double d = (double)x[c] - (xr ? xr[c] : 0.0);
+        s += d * d;
+    }
+    block_sum_store(s, partials);
+}
+
+hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int64_t n,
+                             double *partials, int nblocks, hipStream_t st) {
+    if (x_is_f32)
+        hipLaunchKernelGGL(sumsq_diff_kernel<float>, dim3(nblocks), dim3(256), 0, st,
+                           (const float *)x, xr, n, partials);
+    else
+        hipLaunchKernelGGL(sumsq_diff_kernel<double>, dim3(nblocks), dim3(256), 0, st,
+                           (const double *)x, xr, n, partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- residual (FP64)
+// r_i = b_i - sum_k v_k x_{c_k}, stored values promoted exactly to FP64
+// (b64 == nullptr: r = -A x).
+// One group of 4 lanes per row, rows in order (coalesced record stream).
+template <int VK, class XI>
+__global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const double *b64, const XI *x,
+                                                        double *r_out, int write_rec_b, double *partials) {
+    using T = VT<VK>;
+    constexpr int G = 4;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    double sq = 0.0;
+    for (int64_t i = grp; i < rows.m; i += ngrp) {
+        const uint8_t *rec;
+        int nnz;
+        locate(rows, (uint32_t)i, rec, nnz);
+        const int nunits = (nnz + T::U - 1) / T::U;
+        double acc = 0.0;
+        for (int uu = gl; uu < nunits; uu += G) {
+            Unit<VK> un;
+            un.load(rec + T::HB + (int64_t)uu * T::UB);
+#pragma unroll
+            for (int e = 0; e < T::U; ++e)
+                if (uu * T::U + e < nnz) acc = fma((double)un.v[e], (double)x[un.c[e]], acc);
+        }
+        acc = group_sum<G>(acc);
+        const double r = (b64 ? b64[i] : 0.0) - acc;
+        if (gl == 0) {
+            if (r_out) r_out[i] = r;
+            if (write_rec_b) {
+                using HB = typename T::hdr_t;
+                reinterpret_cast<HB *>(const_cast<uint8_t *>(rec))->b = (decltype(HB::b))r;
+            }
+            sq += r * r;
+        }
+    }
+    block_sum_store(sq, partials);
+}
+
+template <int VK>
+static hipError_t launch_residual_vk(const Rows &rows, const double *b64, const void *x, int x_is_f32,
+                                     double *r_out, int write_rec_b, double *partials, int nblocks,
+                                     hipStream_t st) {
+    if (x_is_f32)
+        hipLaunchKernelGGL((residual_kernel<VK, float>), dim3(nblocks), dim3(256), 0, st, rows, b64,
+                           (const float *)x, r_out, write_rec_b, partials);
+    else
+        hipLaunchKernelGGL((residual_kernel<VK, double>), dim3(nblocks), dim3(256), 0, st, rows, b64,
+                           (const double *)x, r_out, write_rec_b, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
+                           double *r_out, int write_rec_b, double *partials, int nblocks,
+                           hipStream_t st) {
+    switch (vk) {
+        case ASYRK_F32: return launch_residual_vk<ASYRK_F32>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
+        case ASYRK_BF16: return launch_residual_vk<ASYRK_BF16>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
+        case ASYRK_F64: return launch_residual_vk<ASYRK_F64>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- record b
+
+template <int VK>
+__global__ __launch_bounds__(256) void set_rec_b_kernel(const Rows rows, const double *b64) {
+    using HB = typename VT<VK>::hdr_t;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows.m; i += stride) {
+        const uint8_t *rec;
+        int nnz;
+        locate(rows, (uint32_t)i, rec, nnz);
+        reinterpret_cast<HB *>(const_cast<uint8_t *>(rec))->b = (decltype(HB::b))b64[i];
+    }
+}
+
+hipError_t launch_set_rec_b(int vk, const Rows &rows, const double *b64, hipStream_t st) {
+    const int grid = (int)((rows.m + 255) / 256 < 8192 ? (rows.m + 255) / 256 : 8192);
+    switch (vk) {
+        case ASYRK_F32: hipLaunchKernelGGL(set_rec_b_kernel<ASYRK_F32>, dim3(grid), dim3(256), 0, st, rows, b64); break;
+        case ASYRK_BF16: hipLaunchKernelGGL(set_rec_b_kernel<ASYRK_BF16>, dim3(grid), dim3(256), 0, st, rows, b64); break;
+        case ASYRK_F64: hipLaunchKernelGGL(set_rec_b_kernel<ASYRK_F64>, dim3(grid), dim3(256), 0, st, rows, b64); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- vectors
+
+template <class XO>
+__global__ __launch_bounds__(256) void cast_to_iter_kernel(const double *x64, XO *xo, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) xo[c] = (XO)x64[c];
+}
+
+template <class XI>
+__global__ __launch_bounds__(256) void iter_to_f64_kernel(const XI *xi, double *x64, int64_t n, int acc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride)
+        x64[c] = acc ? x64[c] + (double)xi[c] : (double)xi[c];
+}
+
+static int vec_grid(int64_t n) {
+    const int64_t g = (n + 255) / 256;
+    return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+hipError_t launch_cast_to_iter(const double *x64, void *xit, int xit_is_f32, int64_t n, hipStream_t st) {
+    if (xit_is_f32)
+        hipLaunchKernelGGL(cast_to_iter_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (float *)xit, n);
+    else
+        hipLaunchKernelGGL(cast_to_iter_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (double *)xit, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_iter_to_f64(const void *xit, int xit_is_f32, double *x64, int64_t n, int accumulate,
+                              hipStream_t st) {
+    if (xit_is_f32)
+        hipLaunchKernelGGL(iter_to_f64_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, (const float *)xit, x64, n, accumulate);
+    else
+        hipLaunchKernelGGL(iter_to_f64_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, (const double *)xit, x64, n, accumulate);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < words; c += stride) p[c] = 0u;
+}
+
+hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st) {
+    const int64_t words = bytes / 4;
+    hipLaunchKernelGGL(zero_kernel, dim3(vec_grid(words)), dim3(256), 0, st, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- power iteration pieces
+
+// z += A^T y: row i adds y_i * a_i into z (FP64 atomics).
+template <int VK>
+__global__ __launch_bounds__(256) void scatter_rows_kernel(const Rows rows, const double *y, double *z) {
+    using T = VT<VK>;
+    constexpr int G = 4;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t i = grp; i < rows.m; i += ngrp) {
+        const uint8_t *rec;
+        int nnz;
+        locate(rows, (uint32_t)i, rec, nnz);
+        const int nunits = (nnz + T::U - 1) / T::U;
+        const double yi = y[i];
+        for (int uu = gl; uu < nunits; uu += G) {
+            Unit<VK> un;
+            un.load(rec + T::HB + (int64_t)uu * T::UB);
+#pragma unroll
+            for (int e = 0; e < T::U; ++e)
+                if (uu * T::U + e < nnz) unsafeAtomicAdd(z + un.c[e], yi * (double)un.v[e]);
+        }
+    }
+}
+
+hipError_t launch_scatter_rows(int vk, const Rows &rows, const double *y, double *z, hipStream_t st) {
+    const int grid = kResidualBlocks;
+    switch (vk) {
+        case ASYRK_F32: hipLaunchKernelGGL(scatter_rows_kernel<ASYRK_F32>, dim3(grid), dim3(256), 0, st, rows, y, z); break;
+        case ASYRK_BF16: hipLaunchKernelGGL(scatter_rows_kernel<ASYRK_BF16>, dim3(grid), dim3(256), 0, st, rows, y, z); break;
+        case ASYRK_F64: hipLaunchKernelGGL(scatter_rows_kernel<ASYRK_F64>, dim3(grid), dim3(256), 0, st, rows, y, z); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(double *v, int64_t n, const double *norm2) {
+    const double s = 1.0 / sqrt(norm2[0]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) v[c] *= s;
+}
+
+hipError_t launch_scale(double *v, int64_t n, const double *norm2, hipStream_t st) {
+    hipLaunchKernelGGL(scale_kernel, dim3(vec_grid(n)), dim3(256), 0, st, v, n, norm2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void random_fill_kernel(double *v, int64_t n, uint32_t k0, uint32_t k1) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const U4 u = draw(c, 0xA5A5A5A5u, k0, k1);
+        v[c] = ((double)u.a + 0.5) * (1.0 / 4294967296.0) - 0.5;
+    }
+}
+
+hipError_t launch_random_fill(double *v, int64_t n, uint32_t k0, uint32_t k1, hipStream_t st) {
+    hipLaunchKernelGGL(random_fill_kernel, dim3(vec_grid(n)), dim3(256), 0, st, v, n, k0, k1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- sampler exposure
+// The exact draw the sweep makes for each ticket, written out for checking.
+
+template <int VK>
+__global__ __launch_bounds__(256) void sample_rows_kernel(const Rows rows, int64_t ticket0, int64_t count,
+                                                           uint32_t k0, uint32_t k1, uint32_t stream_id,
+                                                           int uniform, int32_t *rows_out, int32_t *coords_out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += stride) {
+        const U4 u = draw(ticket0 + q, stream_id, k0, k1);
+        uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+        const uint8_t *rec;
+        int nnz;
+        locate(rows, i, rec, nnz);
+        if (!uniform) {
+            const typename VT<VK>::hdr_t h = load_hdr<VK>(rec);
+            if (!(u.c < h.thresh)) {
+                i = (uint32_t)h.alias;
+                locate(rows, i, rec, nnz);
+            }
+        }
+        rows_out[q] = (int32_t)i;
+        if (coords_out) coords_out[q] = (int32_t)(((uint64_t)u.d * (uint64_t)nnz) >> 32);
+    }
+}
+
+hipError_t launch_sample_rows(int vk, const Rows &rows, int64_t ticket0, int64_t count, uint32_t k0,
+                              uint32_t k1, uint32_t stream_id, int uniform, int32_t *rows_out,
+                              int32_t *coords_out, hipStream_t st) {
+    const int grid = vec_grid(count);
+    switch (vk) {
+        case ASYRK_F32: hipLaunchKernelGGL(sample_rows_kernel<ASYRK_F32>, dim3(grid), dim3(256), 0, st, rows, ticket0, count, k0, k1, stream_id, uniform, rows_out, coords_out); break;
+        case ASYRK_BF16: hipLaunchKernelGGL(sample_rows_kernel<ASYRK_BF16>, dim3(grid), dim3(256), 0, st, rows, ticket0, count, k0, k1, stream_id, uniform, rows_out, coords_out); break;
+        case ASYRK_F64: hipLaunchKernelGGL(sample_rows_kernel<ASYRK_F64>, dim3(grid), dim3(256), 0, st, rows, ticket0, count, k0, k1, stream_id, uniform, rows_out, coords_out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- device ceilings
+
+__global__ __launch_bounds__(256) void probe_copy_kernel(const float4 *src, float4 *dst, int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n4; c += stride) dst[c] = src[c];
+}
+
+// Random accesses to a table of n elements: kind 0 agent-coherent loads, kind 1
+// no-return atomic adds.  Addresses come from a counter hash (no index stream).
+template <class X>
+__global__ __launch_bounds__(256) void probe_scatter_kernel(X *tab, uint32_t n, int64_t count, int kind,
+                                                             X *sink) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    X acc = (X)0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += stride) {
+        uint32_t h = (uint32_t)q * 0x9E3779B1u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        const uint32_t c = (uint32_t)(((uint64_t)h * n) >> 32);
+        if (kind == 0)
+            acc += load_agent(tab + c);
+        else
+            unsafeAtomicAdd(tab + c, (X)1);
+    }
+    if (kind == 0 && acc == (X)-12345.0) sink[0] = acc;  // keeps the loads alive
+}
+
+hipError_t probe_copy(int64_t bytes, int iters, double *gbps) {
+    const int64_t n4 = bytes / 16;
+    float4 *src = nullptr, *dst = nullptr;
+    hipEvent_t e0, e1;
+    hipError_t err = hipMalloc(&src, n4 * 16);
+    if (err != hipSuccess) return err;
+    err = hipMalloc(&dst, n4 * 16);
+    if (err != hipSuccess) { (void)hipFree(src); return err; }
+    (void)hipMemset(src, 0, n4 * 16);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int grid = 256 * 32;
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(grid), dim3(256), 0, 0, src, dst, n4);
+    (void)hipEventRecord(e0, 0);
+    for (int it = 0; it < iters; ++it)
+        hipLaunchKernelGGL(probe_copy_kernel, dim3(grid), dim3(256), 0, 0, src, dst, n4);
+    (void)hipEventRecord(e1, 0);
+    err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *gbps = 2.0 * (double)n4 * 16.0 * iters / (ms * 1e-3) / 1e9;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(src);
+    (void)hipFree(dst);
+    return err == hipSuccess ? hipGetLastError() : err;
+}
+
+hipError_t probe_scatter(int64_t n, int64_t count, int dtype, int kind, int iters, double *per_s) {
+    const size_t esz = dtype == ASYRK_F64 ? 8 : 4;
+    void *tab = nullptr;
+    hipEvent_t e0, e1;
+    hipError_t err = hipMalloc(&tab, (size_t)n * esz + 64);
+    if (err != hipSuccess) return err;
+    (void)hipMemset(tab, 0, (size_t)n * esz + 64);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int grid = 256 * 16;
+    auto launch = [&]() {
+        if (dtype == ASYRK_F64)
+            hipLaunchKernelGGL(probe_scatter_kernel<double>, dim3(grid), dim3(256), 0, 0, (double *)tab,
+                               (uint32_t)n, count, kind, (double *)tab + n);
+        else
+            hipLaunchKernelGGL(probe_scatter_kernel<float>, dim3(grid), dim3(256), 0, 0, (float *)tab,
+                               (uint32_t)n, count, kind, (float *)tab + n);
+    };
+    launch();
+    (void)hipEventRecord(e0, 0);
+    for (int it = 0; it < iters; ++it) launch();
+    (void)hipEventRecord(e1, 0);
+    err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *per_s = (double)count * iters / (ms * 1e-3);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(tab);
+    return err == hipSuccess ? hipGetLastError() : err;
+}
+
+}  // namespace asyrk

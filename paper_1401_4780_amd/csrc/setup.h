@@ -1,0 +1,32 @@
+// Host-side system setup (setup.cpp): validation, row weights, alias table
+// and record packing.  Plain C++, no HIP.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "layout.h"
+
+namespace asyrk {
+
+struct SetupResult {
+    std::vector<double> w;     // ||a_i||^2, FP64 from the stored values
+    int64_t nnz = 0;
+    int64_t mu = 0;            // max row length
+    int64_t nu = 0;            // max column count
+    int64_t fixed_nnz = 0;     // common row length or 0
+    double fro2 = 0.0;         // sum of w
+    int64_t stride = 0;        // record stride (fixed rows)
+    std::vector<RowLoc> loc;   // per-row locators (rows of different length)
+    std::vector<uint8_t> rec;  // packed records
+};
+
+asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const void *vals, int vk, const double *b, SetupResult &out);
+void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
+                 std::vector<int32_t> &alias);
+asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
+                          int vk, const double *b, SetupResult &res);
+
+}  // namespace asyrk

@@ -34,6 +34,7 @@ __all__ = [
     "serving_specs",
     "serving_system",
     "poisson_arrivals",
+    "ragged_rows",
     "bf16_bits_from_f32",
     "f64_from_bf16_bits",
     "DTYPES",
@@ -262,6 +263,31 @@ def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 1
     np.cumsum(lens, out=row_ptr[1:])
     v64 = _normal_rows_normalized(rng, cols.size, row_ptr)
     return _finish(m, n, row_ptr, cols, v64, dtype, rng, x_star_mode="range")
+
+
+def ragged_rows(m: int, n: int, lengths, seed: int, dtype: str = "f64",
+                normalize: bool = False) -> SparseSystem:
+    """Rows of the given lengths (array of m ints, each in [1, n]) with distinct
+    uniform columns and N(0,1) values (left unnormalized by default, so row
+    norms differ); x* ~ N(0,1).  For edge cases: single-entry rows, rows far
+    longer than the rest, lengths that are not multiples of the record unit.
+
+    Draw order: columns (row by row), values, x*.
+    """
+    rng = np.random.default_rng(seed)
+    lens = np.asarray(lengths, dtype=np.int64)
+    if lens.size != m or lens.min() < 1 or lens.max() > n:
+        raise ValueError("lengths must hold m values in [1, n]")
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), dtype=np.int64)
+    for i in range(m):
+        col[row_ptr[i]:row_ptr[i + 1]] = np.sort(rng.choice(n, size=int(lens[i]), replace=False))
+    if normalize:
+        v64 = _normal_rows_normalized(rng, col.size, row_ptr)
+    else:
+        v64 = rng.standard_normal(col.size)
+    return _finish(m, n, row_ptr, col, v64, dtype, rng)
 
 
 # --------------------------------------------------------------------------

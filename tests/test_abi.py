@@ -1,0 +1,158 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+its structs match the Python binding field for field, and every validation
+error is reported before any device call."""
+import ctypes as C
+import re
+import subprocess
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_1401_4780_amd as P
+import synth
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "asyrk.h"
+
+
+def _declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(asyrk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = P.lib()
+    names = _declared_functions()
+    assert "asyrk_create" in names and "asyrk_solve" in names and "asyrk_residual" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert L.asyrk_abi_version() == 1
+
+
+def _c_layout(struct, fields):
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){",
+           f'printf("%zu\\n", sizeof({struct}));']
+    src += [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src += ["return 0;}"]
+    d = Path(__import__("tempfile").mkdtemp())
+    (d / "l.c").write_text("\n".join(src))
+    subprocess.run(["gcc", "-o", str(d / "l"), str(d / "l.c")], check=True)
+    out = subprocess.run([str(d / "l")], capture_output=True, text=True, check=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("cname,pycls", [("asyrk_solve_params", P.SolveParams),
+                                         ("asyrk_solve_stats", P.SolveStats),
+                                         ("asyrk_system_info", P.SystemInfo)])
+def test_struct_layouts_match_binding(cname, pycls):
+    fields = [f for f, _ in pycls._fields_]
+    lay = _c_layout(cname, fields)
+    assert lay[0] == C.sizeof(pycls)
+    assert lay[1:] == [getattr(pycls, f).offset for f in fields]
+
+
+def test_status_strings_and_defaults():
+    L = P.lib()
+    for code in range(9):
+        assert L.asyrk_status_string(code)
+    p = P.SolveParams()
+    L.asyrk_solve_params_init(C.byref(p))
+    assert (p.mode, p.sampling, p.update, p.check_every, p.in_flight, p.lanes) == (0, 0, 0, 1, 0, 0)
+
+
+def _create(rp, col, val, b, n, dtype=P.F32, mem=P.MEM_HOST):
+    h = C.c_void_p()
+    rc = P.lib().asyrk_create(C.byref(h), rp.size - 1, n, rp.ctypes.data, col.ctypes.data,
+                              val.ctypes.data, dtype, b.ctypes.data, mem, None)
+    return rc, h
+
+
+def _good():
+    s = synth.uniform_rows(40, 12, 3, seed=2, dtype="f32", require_full_columns=False)
+    return s.row_ptr.copy(), s.col.copy(), s.val.copy(), s.b.copy(), s.n
+
+
+@pytest.mark.parametrize("case", ["m0", "n0", "rp0", "rp_dec", "col_hi", "col_neg", "col_dup",
+                                  "col_unsorted", "val_nan", "val_inf", "b_nan", "dtype", "mem"])
+def test_invalid_arguments_rejected_before_device(case):
+    rp, col, val, b, n = _good()
+    dtype, mem = P.F32, P.MEM_HOST
+    m_override = None
+    if case == "m0":
+        m_override = 0
+    elif case == "n0":
+        n = 0
+    elif case == "rp0":
+        rp = rp + 1
+    elif case == "rp_dec":
+        rp[5], rp[6] = rp[6], rp[5]
+    elif case == "col_hi":
+        col[7] = n
+    elif case == "col_neg":
+        col[7] = -1
+    elif case == "col_dup":
+        col[4] = col[3]
+    elif case == "col_unsorted":
+        col[3], col[4] = col[4], col[3]
+    elif case == "val_nan":
+        val[9] = np.nan
+    elif case == "val_inf":
+        val[9] = np.inf
+    elif case == "b_nan":
+        b[2] = np.nan
+    elif case == "dtype":
+        dtype = 7
+    elif case == "mem":
+        mem = 5
+    h = C.c_void_p()
+    m = rp.size - 1 if m_override is None else m_override
+    rc = P.lib().asyrk_create(C.byref(h), m, n, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                              dtype, b.ctypes.data, mem, None)
+    assert P.STATUS[rc] == "INVALID_ARG"
+    assert h.value is None
+
+
+@pytest.mark.parametrize("case", ["empty_row", "zero_values"])
+def test_zero_row_rejected(case):
+    rp, col, val, b, n = _good()
+    if case == "zero_values":
+        val[rp[3]:rp[4]] = 0.0
+        rc, _ = _create(rp, col, val, b, n)
+    else:
+        # row 3 loses its entries
+        keep = np.ones(col.size, bool)
+        keep[rp[3]:rp[4]] = False
+        k = rp[4] - rp[3]
+        rp2 = rp.copy()
+        rp2[4:] -= k
+        rc, _ = _create(rp2, col[keep].copy(), val[keep].copy(), b, n)
+    assert P.STATUS[rc] == "ZERO_ROW"
+
+
+def test_null_handles_rejected():
+    L = P.lib()
+    x = np.zeros(4)
+    v = C.c_double()
+    assert P.STATUS[L.asyrk_solve(None, x.ctypes.data, 1.0, 1, 0, None, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_residual(None, x.ctypes.data, None, C.byref(v))] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_create(None, 1, 1, None, None, None, 0, None, 0, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_lambda_max(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_destroy(None)] == "OK"
+    assert P.STATUS[L.asyrk_probe_copy(0, 1, C.byref(v))] == "INVALID_ARG"
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(P, "LIB_PATH", tmp_path / "missing.so")
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(P.LibraryMissing):
+        P.lib()
+
+
+def test_binding_type_checks():
+    rp, col, val, b, n = _good()
+    with pytest.raises(TypeError):
+        P.System(rp, col.astype(np.int64), val, b, n=n)
+    with pytest.raises(TypeError):
+        P.System(rp, col, val, b.astype(np.float32), n=n)

@@ -1,0 +1,70 @@
+"""Full-size checks at the benchmark's shape and launch configuration
+(m = 4,000,000, n = 1,000,000, 20 entries per row, FP32, library-chosen R and
+G), on outputs the oracle can compute one by one and on properties that hold
+at any size:
+
+  * the device's row draws for sampled ticket ranges equal the oracle's, bit
+    for bit (including the tickets of late sweeps);
+  * an asynchronous solve reaches ||x - x*|| / ||x*|| <= 1e-6 and the
+    library's FP64 residual of the result equals the oracle's residual of the
+    same x to 1e-12 relative;
+  * the monitored error never increases by more than the FP32 floor between
+    checks (RK is a contraction in expectation).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1401_4780_amd as P
+import synth
+
+pytestmark = pytest.mark.gpu
+
+M, N, NNZ = 4_000_000, 1_000_000, 20
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    assert torch.cuda.is_available()
+    _say("full-size generate + create")
+    s = synth.uniform_rows(M, N, NNZ, seed=1, dtype="f32")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=N)
+    yield s, sysm, d
+    sysm.close()
+
+
+def test_fullsize_sampler_bitexact(big):
+    s, sysm, d = big
+    _say("full-size sampler")
+    w = oracle.row_weights(s.row_ptr, s.val64)
+    t, a = oracle.alias_build(w)
+    for t0 in (0, 27 * M + 12345, 2**32 - 5000):
+        rows_o = oracle.sample_rows(M, 1, 100_000, ticket0=t0, thresh=t, alias=a)
+        rows_g = sysm.sample_rows(1, 100_000, ticket0=t0).cpu().numpy()
+        assert np.array_equal(rows_g, rows_o), t0
+
+
+def test_fullsize_async_to_1e6_and_residual(big):
+    import torch
+    s, sysm, d = big
+    _say("full-size async solve")
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st = sysm.solve(x, 1.0, 200, 1, tol=1e-6, x_ref=d(s.x_star), history=256)
+    assert st["status"] == "OK", st
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(xh - s.x_star) <= 1.05e-6 * np.linalg.norm(s.x_star)
+    h = st["history"]
+    assert np.all(h[1:] <= h[:-1] * 1.0 + 2e-7)
+    n2_o = oracle.residual(s.row_ptr, s.col, s.val64, s.b, xh)
+    n2_g = sysm.residual(x)
+    assert abs(n2_g - n2_o) <= 1e-12 * n2_o
+    _say(f"full-size: {st['sweeps_done']} sweeps, {st['rows_per_s']:.3e} rows/s, R={st['in_flight']}")

@@ -1,0 +1,340 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Bars (each stated at the assertion):
+  * integer work (row sampling, Algorithm 1 coordinates): bit-exact;
+  * REPLAY in FP64 (one worker, the oracle's exact ticket sequence):
+    ||x_gpu - x_oracle|| <= 1e-12 ||x_oracle||, curve points within 1e-12;
+  * REPLAY in FP32 / BF16 storage (FP32 arithmetic): within 1e-6 of the FP64
+    oracle relative to ||x*||.  Derivation: the FP32 iterate's own floor is
+    about kappa * u32 (kappa = sqrt(lambda_max/lambda_min) ~ 3 for m = 4n,
+    u32 = 6e-8), measured at ~1e-7 on this workload; 1e-6 is 10x that floor;
+  * ASYNC: reaches the tolerance (FP32 1e-6, FP64 1e-10, refinement 1e-10)
+    with a sweep count within 1.5x of the oracle's (plus one check interval).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1401_4780_amd as P
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_system(s, device=True):
+    if device:
+        return P.System(_dev(s.row_ptr), _dev(s.col), _dev(s.val), _dev(s.b), n=s.n,
+                        dtype=s.dtype)
+    return P.System(s.row_ptr, s.col, s.val, s.b, n=s.n, dtype=s.dtype)
+
+
+def oracle_rows(s, seed, count, ticket0=0, stream=0, uniform=False):
+    if uniform:
+        return oracle.sample_rows(s.m, seed, count, ticket0=ticket0, stream=stream, with_u3=True)
+    w = oracle.row_weights(s.row_ptr, s.val64)
+    t, a = oracle.alias_build(w)
+    return oracle.sample_rows(s.m, seed, count, ticket0=ticket0, stream=stream, thresh=t, alias=a,
+                              with_u3=True)
+
+
+def oracle_run(s, gamma, sweeps, seed, **kw):
+    return oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, np.zeros(s.n), gamma, sweeps * s.m,
+                         seed, curve_every=s.m, x_ref=s.x_star, **kw)
+
+
+def gpu_solve(sysm, s, device, **kw):
+    if device:
+        x = _dev(np.zeros(s.n))
+        xr = _dev(s.x_star)
+    else:
+        x = np.zeros(s.n)
+        xr = s.x_star
+    st = sysm.solve(x, x_ref=xr, **kw)
+    xo = x.cpu().numpy() if device else x
+    return xo, st
+
+
+# ------------------------------------------------------------------ sampler
+
+SAMPLER_CASES = {
+    "f64_fixed_unit": lambda: synth.uniform_rows(2000, 500, 10, seed=0, dtype="f64"),
+    "f32_ragged_raw": lambda: synth.ragged_rows(
+        3000, 400, np.random.default_rng(1).integers(1, 60, 3000), seed=1, dtype="f32"),
+    "bf16_fixed_raw": lambda: synth.uniform_rows(1500, 300, 9, seed=2, dtype="bf16",
+                                                  normalize=False, require_full_columns=False),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SAMPLER_CASES))
+@pytest.mark.parametrize("uniform", [False, True])
+def test_sampler_bitexact(case, uniform):
+    s = SAMPLER_CASES[case]()
+    _say(f"sampler {case} uniform={uniform} m={s.m}")
+    sysm = make_system(s, device=False)
+    for seed, stream, t0, cnt in ((0, 0, 0, 200_000), (2**40 + 7, 3, 2**33 - 100, 50_000)):
+        rows_o, u3 = oracle_rows(s, seed, cnt, ticket0=t0, stream=stream, uniform=uniform)
+        rows_g = np.empty(cnt, np.int32)
+        coords_g = np.empty(cnt, np.int32)
+        sysm.sample_rows(seed, cnt, ticket0=t0, stream_id=stream, uniform=uniform, rows_out=rows_g,
+                         coords_out=coords_g)
+        assert np.array_equal(rows_g, rows_o)  # bit-exact
+        theta = np.diff(s.row_ptr)[rows_o].astype(np.uint64)
+        t_o = ((u3.astype(np.uint64) * theta) >> np.uint64(32)).astype(np.int32)
+        assert np.array_equal(coords_g, t_o)
+        if not uniform and case != "f64_fixed_unit":
+            # rows of unequal norm: the alias branch was taken for some tickets
+            buckets = oracle.sample_rows(s.m, seed, cnt, ticket0=t0, stream=stream)
+            assert (rows_o != buckets).mean() > 0.05
+    sysm.close()
+
+
+# ------------------------------------------------------------------ REPLAY, FP64
+
+@pytest.mark.parametrize("gamma", [1.0, 0.5])
+@pytest.mark.parametrize("device", [True, False])
+def test_replay_fp64_small_config(gamma, device):
+    """m=2000, n=500, 10 nnz/row, FP64, 20 sweeps, seed 0: plain RK on one worker."""
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype="f64")
+    _say(f"replay f64 C1 gamma={gamma} device={device}")
+    ref = oracle_run(s, gamma, 20, 0)
+    sysm = make_system(s, device)
+    x, st = gpu_solve(sysm, s, device, gamma=gamma, sweeps=20, seed=0, mode="replay", history=64)
+    assert st["status"] == "OK" and st["sweeps_done"] == 20 and st["in_flight"] == 1
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    h = st["history"]
+    assert h.size == 21
+    assert np.max(np.abs(h - ref["err"])) <= 1e-12
+    sysm.close()
+
+
+def test_replay_fp64_ragged_alias_long_rows():
+    """Rows of 1..37 entries plus a few 300-entry rows (two-pass path), raw
+    N(0,1) rows (norm-weighted sampling takes the alias branch)."""
+    rng = np.random.default_rng(5)
+    lens = rng.integers(1, 38, 700)
+    lens[[3, 100, 555]] = 300
+    s = synth.ragged_rows(700, 400, lens, seed=5, dtype="f64")
+    _say("replay f64 ragged+long rows")
+    ref = oracle_run(s, 0.9, 6, 11)
+    for lanes in (1, 4, 16):
+        sysm = make_system(s, device=True)
+        x, st = gpu_solve(sysm, s, True, gamma=0.9, sweeps=6, seed=11, mode="replay", lanes=lanes,
+                          history=16)
+        assert st["status"] == "OK"
+        assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"]), lanes
+        assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+        sysm.close()
+
+
+def test_replay_bitwise_reproducible_and_resumable():
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype="f64")
+    _say("replay determinism / resume")
+    sysm = make_system(s, device=True)
+    torch = _torch()
+    x1 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    sysm.solve(x1, 1.0, 20, 3, mode="replay")
+    x2 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    sysm.solve(x2, 1.0, 20, 3, mode="replay")
+    assert torch.equal(x1, x2)
+    x3 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    st = sysm.solve(x3, 1.0, 7, 3, mode="replay")
+    sysm.solve(x3, 1.0, 13, 3, mode="replay", ticket0=st["next_ticket"])
+    assert torch.equal(x1, x3)
+    sysm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_replay_fp32_storage_within_fp32_floor(dtype):
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype=dtype)
+    _say(f"replay {dtype} C1 shape")
+    ref = oracle_run(s, 1.0, 20, 0)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, mode="replay", history=32)
+    nx = np.linalg.norm(s.x_star)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-6 * nx
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-6
+    sysm.close()
+
+
+def test_replay_single_coordinate_algorithm1():
+    """Algorithm 1: uniform rows, one coordinate, step gamma*theta_i, gamma = 1/mu."""
+    s = synth.uniform_rows(300, 100, 8, seed=6, dtype="f64", require_full_columns=False)
+    gamma = 1.0 / 8
+    _say("replay algorithm 1")
+    ref = oracle_run(s, gamma, 30, 4, uniform=True, update_one=True)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=gamma, sweeps=30, seed=4, mode="replay",
+                      sampling="uniform", update="one", history=40)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    sysm.close()
+
+
+# ------------------------------------------------------------------ ASYNC
+
+def _sweeps_to(curve, tol):
+    idx = np.nonzero(curve <= tol)[0]
+    return int(idx[0]) if idx.size else None
+
+
+@pytest.mark.parametrize("gamma", [1.0, 0.5])
+@pytest.mark.parametrize("R", [1024, 8192])
+def test_async_fp32_reaches_1e6(gamma, R):
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say(f"async f32 40k x 10k gamma={gamma} R={R}")
+    ref = oracle_run(s, gamma, 60, 1)
+    k_orc = _sweeps_to(ref["err"], 1e-6)
+    assert k_orc is not None
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=gamma, sweeps=200, seed=1, tol=1e-6, in_flight=R,
+                      history=256)
+    assert st["status"] == "OK", st
+    err = np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star)
+    assert err <= 1.05e-6
+    assert st["sweeps_done"] <= math.ceil(1.5 * k_orc) + 1, (st["sweeps_done"], k_orc)
+    sysm.close()
+
+
+def test_async_fp64_reaches_1e10():
+    s = synth.uniform_rows(40_000, 10_000, 16, seed=3, dtype="f64")
+    _say("async f64 to 1e-10")
+    ref = oracle_run(s, 1.0, 80, 2)
+    k_orc = _sweeps_to(ref["err"], 1e-10)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=2, tol=1e-10, in_flight=8192)
+    assert st["status"] == "OK", st
+    assert np.linalg.norm(x - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
+    assert st["sweeps_done"] <= math.ceil(1.5 * k_orc) + 1
+    sysm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_refinement_reaches_1e10(dtype):
+    s = synth.uniform_rows(80_000, 20_000, 16, seed=3, dtype=dtype)
+    _say(f"refinement {dtype} to 1e-10")
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=400, seed=5, tol=1e-10, refine=True,
+                      in_flight=16384, history=64)
+    assert st["status"] == "OK", st
+    assert st["outer_iters"] >= 2
+    # x* is exact for the stored values (b = A x* in FP64 from them)
+    assert np.linalg.norm(x - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
+    # the system's b is intact afterwards: a plain replay matches the oracle again
+    small = oracle_run(s, 1.0, 1, 9)
+    x2, _ = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=9, mode="replay")
+    assert np.linalg.norm(x2 - small["x"]) <= 1e-6 * np.linalg.norm(s.x_star)
+    sysm.close()
+
+
+def test_trace_reports_staleness():
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say("trace tau_obs")
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=3, seed=1, in_flight=4096, trace=True)
+    assert st["window_ns_mean"] > 0 and st["window_ns_max"] >= st["window_ns_mean"]
+    assert 0 < st["tau_obs_mean"] < 1e7 and st["tau_design"] == 4095
+    sysm.close()
+
+
+# ------------------------------------------------------------------ residual, lambda_max, edges
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_residual_matches_oracle(dtype):
+    rng = np.random.default_rng(7)
+    s = synth.ragged_rows(5000, 1200, rng.integers(1, 50, 5000), seed=7, dtype=dtype)
+    _say(f"residual {dtype}")
+    x = rng.standard_normal(s.n)
+    n2_o, r_o = oracle.residual(s.row_ptr, s.col, s.val64, s.b, x, want_r=True)
+    sysm = make_system(s, device=False)
+    r_g = np.empty(s.m)
+    n2_g = sysm.residual(x, r_out=r_g)
+    np.testing.assert_allclose(r_g, r_o, rtol=1e-13, atol=1e-13 * np.abs(r_o).max())
+    assert abs(n2_g - n2_o) <= 1e-12 * n2_o
+    sysm.close()
+
+
+def test_lambda_max_power_iteration():
+    s = synth.uniform_rows(3000, 600, 7, seed=8, dtype="f64")
+    _say("lambda_max")
+    A = s.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    sysm = make_system(s, device=True)
+    lam, tau = sysm.lambda_max(iters=400, seed=1)
+    assert abs(lam - ev[-1]) <= 1e-6 * ev[-1]
+    fro2 = float(np.sum(s.val64 ** 2))
+    assert tau == math.floor(fro2 / (2 * math.e * lam)) - 1
+    assert lam <= np.diff(s.row_ptr).max() * np.bincount(s.col).max()  # lambda_max <= mu nu
+    sysm.close()
+
+
+def test_edge_cases():
+    _say("edge cases")
+    # one row
+    s = synth.ragged_rows(1, 5, [3], seed=1, dtype="f64")
+    ref = oracle_run(s, 1.0, 1, 0)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=0, mode="replay")
+    np.testing.assert_allclose(x, ref["x"], rtol=0, atol=1e-15)
+    sysm.close()
+    # one column: every row is a multiple of e_0
+    s = synth.ragged_rows(50, 1, [1] * 50, seed=2, dtype="f64")
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=0, mode="replay")
+    assert abs(x[0] - s.x_star[0]) <= 1e-14 * abs(s.x_star[0])
+    # zero sweeps leave x unchanged; a met tolerance stops at once
+    s = synth.uniform_rows(500, 100, 5, seed=3, dtype="f32", require_full_columns=False)
+    sysm = make_system(s, device=False)
+    x = s.x_star.copy()
+    st = sysm.solve(x, 1.0, 0, 0)
+    assert np.array_equal(x, s.x_star) and st["sweeps_done"] == 0
+    x = np.zeros(s.n)
+    st = sysm.solve(x, 1.0, 5, 0, tol=10.0, x_ref=s.x_star)
+    assert st["status"] == "OK" and st["sweeps_done"] == 0
+    # budget exhausted / cancelled
+    st = sysm.solve(np.zeros(s.n), 1.0, 2, 0, tol=1e-14, x_ref=s.x_star)
+    assert st["status"] == "NOT_CONVERGED" and st["sweeps_done"] == 2
+    flag = np.ones(1, np.int32)
+    st = sysm.solve(np.zeros(s.n), 1.0, 50, 0, cancel=flag, x_ref=s.x_star)
+    assert st["status"] == "CANCELLED" and st["sweeps_done"] == 1
+    # invalid step length, refinement of an FP64 system
+    with pytest.raises(P.AsyrkError):
+        sysm.solve(np.zeros(s.n), 2.0, 1, 0)
+    sysm.close()
+    s = synth.uniform_rows(200, 50, 4, seed=4, dtype="f64", require_full_columns=False)
+    sysm = make_system(s, device=False)
+    with pytest.raises(P.AsyrkError) as ei:
+        sysm.solve(np.zeros(s.n), 1.0, 1, 0, refine=True)
+    assert ei.value.name == "UNSUPPORTED"
+    sysm.close()
+
+
+def test_set_rhs():
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype="f64")
+    _say("set_rhs")
+    x2 = np.random.default_rng(3).standard_normal(s.n)
+    b2 = s.dense() @ x2
+    sysm = make_system(s, device=False)
+    sysm.set_rhs(b2)
+    x = np.zeros(s.n)
+    st = sysm.solve(x, 1.0, 60, 1, tol=1e-12, x_ref=x2)
+    assert st["status"] == "OK"
+    sysm.close()
