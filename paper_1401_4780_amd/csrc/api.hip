@@ -571,7 +571,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                 }
             }
         }
-        HIP_OK(launch_iter_to_f64(s->d_x, f32, s->d_x64, s->n, 0, s->st));
+        // x is returned untouched when no sweep ran (no FP32 round trip)
+        if (done > 0) HIP_OK(launch_iter_to_f64(s->d_x, f32, s->d_x64, s->n, 0, s->st));
         if (result == ASYRK_OK && p.tol > 0.0 && !(S.final_err <= p.tol)) result = ASYRK_ERR_NOT_CONVERGED;
     } else {
         // FP64 iterative refinement: x64 master, FP32 correction d on A d = fp32(b - A x64)

@@ -196,8 +196,10 @@ def _sweeps_to(curve, tol):
     return int(idx[0]) if idx.size else None
 
 
+# 40k x 10k unit rows: lambda_max ~ (1 + sqrt(n/m))^2 m/n = 9, so Corollary 1
+# admits tau + 1 <= m / (2 e lambda_max) ~ 817 workers.
 @pytest.mark.parametrize("gamma", [1.0, 0.5])
-@pytest.mark.parametrize("R", [1024, 8192])
+@pytest.mark.parametrize("R", [64, 800])
 def test_async_fp32_reaches_1e6(gamma, R):
     s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
     _say(f"async f32 40k x 10k gamma={gamma} R={R}")
@@ -214,13 +216,31 @@ def test_async_fp32_reaches_1e6(gamma, R):
     sysm.close()
 
 
+def test_in_flight_threshold():
+    """Below Corollary 1's bound the error-per-sweep curves merge (Section
+    "Experiments": the workload is nearly independent of the worker count);
+    far above it (16x) progress per sweep collapses."""
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say("in-flight threshold")
+    sysm = make_system(s, device=True)
+    errs = {}
+    for R in (16, 256, 800, 13_000):
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=12, seed=2, in_flight=R)
+        errs[R] = st["final_err"]
+    ref = oracle_run(s, 1.0, 12, 2)["err"][-1]
+    for R in (16, 256, 800):
+        assert errs[R] <= 3.0 * ref, (R, errs[R], ref)
+    assert errs[13_000] >= 100.0 * ref, errs
+    sysm.close()
+
+
 def test_async_fp64_reaches_1e10():
     s = synth.uniform_rows(40_000, 10_000, 16, seed=3, dtype="f64")
     _say("async f64 to 1e-10")
     ref = oracle_run(s, 1.0, 80, 2)
     k_orc = _sweeps_to(ref["err"], 1e-10)
     sysm = make_system(s, device=True)
-    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=2, tol=1e-10, in_flight=8192)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=2, tol=1e-10, in_flight=512)
     assert st["status"] == "OK", st
     assert np.linalg.norm(x - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
     assert st["sweeps_done"] <= math.ceil(1.5 * k_orc) + 1
@@ -233,7 +253,7 @@ def test_refinement_reaches_1e10(dtype):
     _say(f"refinement {dtype} to 1e-10")
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=400, seed=5, tol=1e-10, refine=True,
-                      in_flight=16384, history=64)
+                      in_flight=1024, history=64)
     assert st["status"] == "OK", st
     assert st["outer_iters"] >= 2
     # x* is exact for the stored values (b = A x* in FP64 from them)
@@ -279,7 +299,9 @@ def test_lambda_max_power_iteration():
     ev = np.linalg.eigvalsh(A.T @ A)
     sysm = make_system(s, device=True)
     lam, tau = sysm.lambda_max(iters=400, seed=1)
-    assert abs(lam - ev[-1]) <= 1e-6 * ev[-1]
+    # a Rayleigh quotient never exceeds lambda_max; power iteration closes the
+    # gap slowly when the top eigenvalues cluster (random sparse spectra)
+    assert ev[-1] * (1 - 1e-3) <= lam <= ev[-1] * (1 + 1e-12)
     fro2 = float(np.sum(s.val64 ** 2))
     assert tau == math.floor(fro2 / (2 * math.e * lam)) - 1
     assert lam <= np.diff(s.row_ptr).max() * np.bincount(s.col).max()  # lambda_max <= mu nu
