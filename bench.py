@@ -82,21 +82,7 @@ def cpu_baseline(s, target_s=12.0):
                       f"from x0=0, sequential FP64, single thread, {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
-    ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
-        sys.exit(2)
-
+def run_c2(args):
     import torch
     import paper_1401_4780_amd as P
     import synth
@@ -205,13 +191,144 @@ def main():
         st = sysm.solve(x, 0.5, BUDGET, 9, tol=TOL, x_ref=x_ref, in_flight=args.in_flight)
         result["gamma_0.5"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
                                "status": st["status"]}
+        x.zero_()
+        t1 = time.perf_counter()
+        st = sysm.solve(x, GAMMA, BUDGET, 11, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
+                        iter_dtype="f64")
+        result["f64_iterate"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
+                                 "status": st["status"], "time_to_tol_s": time.perf_counter() - t1}
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(s)
         cb["time_to_tol_s_est"] = result["sweeps_to_tol_mean"] * M / cb["value"]
         result["cpu_baseline"] = cb
-    print(json.dumps(result), flush=True)
+    return result
+
+
+def run_precision(args):
+    """8M x 2M, 16 entries per row, to ||x - x*||/||x*|| <= 1e-10: plain FP64
+    sweeps vs FP32/BF16 storage with FP32 sweeps + FP64 refinement vs FP32/BF16
+    storage with an FP64 iterate.  x* is exact for each stored matrix."""
+    import torch
+    import paper_1401_4780_amd as P
+    import synth
+
+    m, n, k, tol = 8_000_000, 2_000_000, 16, 1e-10
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    s64 = synth.uniform_rows(m, n, k, seed=3, dtype="f64")
+    log(f"generated precision system in {time.perf_counter() - t0:.1f}s")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    variants = [("f64_values_f64_sweeps", "f64", dict(iter_dtype="f64")),
+                ("f32_values_f32_sweeps_refined", "f32", dict(refine=True, inner_sweeps=args.inner)),
+                ("bf16_values_f32_sweeps_refined", "bf16", dict(refine=True, inner_sweeps=args.inner)),
+                ("f32_values_f64_sweeps", "f32", dict(iter_dtype="f64")),
+                ("bf16_values_f64_sweeps", "bf16", dict(iter_dtype="f64"))]
+    out = {}
+    for name, dt, kw in variants:
+        s = s64 if dt == "f64" else synth.as_dtype(s64, dt)
+        sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=n, dtype=dt)
+        x_ref = d(s.x_star)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        sysm.solve(x, 1.0, 2, 99, in_flight=args.in_flight, **{q: v for q, v in kw.items()
+                                                                  if q == "iter_dtype"})
+        times, sts = [], []
+        for rep in range(args.steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = sysm.solve(x, 1.0, 400, 1 + rep, tol=tol, x_ref=x_ref, in_flight=args.in_flight, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            sts.append(st)
+        err = float(np.linalg.norm(x.cpu().numpy() - s.x_star) / np.linalg.norm(s.x_star))
+        out[name] = {"time_to_1e-10_s_p50": float(np.percentile(times, 50)),
+                     "time_to_1e-10_s_p99": float(np.percentile(times, 99)),
+                     "sweeps": sts[-1]["sweeps_done"], "outer_iters": sts[-1]["outer_iters"],
+                     "status": sts[-1]["status"], "err_vs_exact_solution": err,
+                     "sweep_rows_per_s": sts[-1]["rows_per_s"],
+                     "record_bytes_per_row": sysm.info()["record_bytes_per_row"]}
+        log(f"{name}: {out[name]}")
+        sysm.close()
+        del x, x_ref
+        torch.cuda.empty_cache()
+    base = out["f64_values_f64_sweeps"]["time_to_1e-10_s_p50"]
+    for name in out:
+        out[name]["speedup_vs_fp64"] = base / out[name]["time_to_1e-10_s_p50"]
+    best = min(out, key=lambda q: out[q]["time_to_1e-10_s_p50"])
+    return {"metric": "time to ||x-x*||/||x*|| <= 1e-10 (precision path)",
+            "value": out[best]["time_to_1e-10_s_p50"], "unit": "s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "higher_is_better": False, "vs_baseline": None,
+            "data": "synthetic", "dtype": "mixed",
+            "config": {"workload": "asyrk_8Mx2M_nnz16_to_1e-10", "m": m, "n": n, "nnz_per_row": k,
+                       "best": best}, "variants": out}
+
+
+def run_skewed(args):
+    """2M x 500k, lognormal row lengths (median 16, clipped to [4, 2000]),
+    Zipf(1.1) columns: fixed 100-sweep budget, error curve per in-flight R."""
+    import torch
+    import paper_1401_4780_amd as P
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    s = synth.skewed_rows(2_000_000, 500_000, seed=2, dtype="f32")
+    log(f"generated skewed system in {time.perf_counter() - t0:.1f}s")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n)
+    info = sysm.info()
+    lam, tau_max = sysm.lambda_max(iters=60, seed=1)
+    x_ref = d(s.x_star)
+    x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    cnt = np.bincount(s.col, minlength=s.n)
+    res = {}
+    for R in (args.in_flight,) if args.in_flight else (1, 64, 1024, 16384, 65536):
+        x.zero_()
+        budget = 100 if R > 1 else 2
+        st = sysm.solve(x, 1.0, budget, 5, x_ref=x_ref, in_flight=R, lanes=args.lanes, history=128,
+                        tol=1e-6)
+        h = st["history"]
+        res[str(R)] = {"rows_per_s": st["rows_per_s"], "sweeps": st["sweeps_done"],
+                       "final_err": st["final_err"], "status": st["status"],
+                       "err_after_10_sweeps": float(h[min(10, h.size - 1)]),
+                       "lanes": st["lanes"]}
+        log(f"skewed R={R}: {res[str(R)]}")
+    best = max(res, key=lambda q: res[q]["rows_per_s"])
+    return {"metric": "row updates/s (skewed rows, hot columns)", "value": res[best]["rows_per_s"],
+            "unit": "row updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
+            "vs_baseline": None, "data": "synthetic", "dtype": "f32",
+            "config": {"workload": "asyrk_skewed_2Mx500k_lognormal16_zipf1.1", "m": s.m, "n": s.n,
+                       "nnz": s.nnz, "mu": info["mu"], "nu": info["nu"]},
+            "lambda_max": lam, "tau_max_corollary1": tau_max,
+            "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--inner", type=int, default=0, help="refinement inner sweeps (0: default)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+    fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -107,6 +107,11 @@ typedef struct asyrk_solve_params {
     double *history;         /* nullable HOST array: monitored error at the start and after
                                 each check (refinement: after each outer iteration) */
     int64_t history_cap;     /* capacity of history */
+    int32_t iter_dtype;      /* iterate and sweep arithmetic: -1 (set by
+                                asyrk_solve_params_init) = the system's default (F64
+                                values: F64, else F32); ASYRK_F32 (F32/BF16 values only)
+                                or ASYRK_F64 (any values; FP64 atomics) */
+    int32_t reserved;        /* must be 0 */
 } asyrk_solve_params;
 
 typedef struct asyrk_solve_stats {
@@ -136,7 +141,7 @@ typedef struct asyrk_system_info {
     int64_t record_stride;     /* bytes per row record when fixed_nnz > 0 */
     int64_t device_bytes;      /* device memory held by the system */
     int32_t vals_dtype;        /* asyrk_dtype of the stored values */
-    int32_t iter_dtype;        /* ASYRK_F64 for F64 values, else ASYRK_F32 */
+    int32_t iter_dtype;        /* default iterate dtype: ASYRK_F64 for F64 values, else ASYRK_F32 */
     double fro2;               /* ||A||_F^2 (FP64, stored values) */
     double lambda_mp;          /* (1 + sqrt(n/m))^2 * fro2 / n: Gaussian-ensemble estimate of lambda_max */
     int64_t record_bytes_per_row; /* algorithmic bytes per row update (values, indices, b_i, w_i, start) */
@@ -163,7 +168,9 @@ void asyrk_solve_params_init(asyrk_solve_params *p);
  *   b        double[m], finite
  *   mem      ASYRK_MEM_HOST or ASYRK_MEM_DEVICE for every pointer argument
  *   stream   hipStream_t (as void *), NULL for the null stream
- * Sweeps run in FP64 (values F64) or FP32 (values F32/BF16).
+ * Sweeps run in FP64 (values F64) or, by default, FP32 (values F32/BF16);
+ * asyrk_solve_params.iter_dtype = ASYRK_F64 runs FP32/BF16 values with an
+ * FP64 iterate and FP64 atomics.
  * Errors: INVALID_ARG (shape, ordering, range, non-finite), ZERO_ROW, OOM,
  * DEVICE.  On error *out is set to NULL.
  */
@@ -191,7 +198,7 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
  * ASYNC runs R workers at once; staleness is not bounded by construction
  * (tau_design = R - 1 is the modeling value; trace measures windows).
  * REPLAY forces one worker and is bitwise reproducible.
- * With refine = 1 (FP32 systems only): outer loop r = b - A x in FP64,
+ * With refine = 1 (FP32 iterate only): outer loop r = b - A x in FP64,
  * inner sweeps on A d = fp32(r) from d = 0, x += d in FP64, until the
  * monitored error <= tol or the budget is spent.  The system's b is
  * restored before return.

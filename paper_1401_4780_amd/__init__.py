@@ -53,6 +53,7 @@ class SolveParams(C.Structure):
         ("check_every", C.c_int32), ("refine", C.c_int32), ("inner_sweeps", C.c_int64),
         ("stream_id", C.c_uint32), ("trace", C.c_int32), ("ticket0", C.c_int64),
         ("cancel", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int64),
+        ("iter_dtype", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -254,7 +255,7 @@ class System:
     def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
               update="all", lanes=0, in_flight=0, tol=0.0, x_ref=None, check_every=1,
               refine=False, inner_sweeps=0, stream_id=0, trace=False, ticket0=0, cancel=None,
-              history=0) -> dict:
+              history=0, iter_dtype=None) -> dict:
         """Run from x (float64, overwritten with the result).  Returns the stats
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
         "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
@@ -276,6 +277,7 @@ class System:
         p.stream_id = stream_id
         p.trace = int(bool(trace))
         p.ticket0 = ticket0
+        p.iter_dtype = {None: -1, "f32": F32, "f64": F64}[iter_dtype]
         if cancel is not None:
             if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):
                 raise TypeError("cancel: expected a numpy int32 array")

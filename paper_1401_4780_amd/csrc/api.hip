@@ -23,7 +23,8 @@ struct asyrk_system {
     uint8_t *d_rec = nullptr;
     RowLoc *d_loc = nullptr;
     double *d_b64 = nullptr;
-    void *d_x = nullptr;          // sweep iterate (float or double)
+    void *d_x = nullptr;          // sweep iterate (float or double; n * 8 bytes)
+    double2 *d_side = nullptr;    // {b_i, 1/w_i} in FP64 for FP64 iterates over FP32/BF16 records
     double *d_x64 = nullptr;      // FP64 master iterate
     double *d_xref = nullptr;     // FP64 reference for the error monitor
     double *d_part = nullptr;     // reduction partials
@@ -40,8 +41,6 @@ namespace {
 
 thread_local const char *g_last = "";
 
-bool iter_is_f32(const asyrk_system *s) { return s->vk != ASYRK_F64; }
-size_t x_bytes(const asyrk_system *s) { return iter_is_f32(s) ? 4 : 8; }
 
 asyrk_status dev_fail(hipError_t e) {
     g_last = hipGetErrorString(e);
@@ -69,6 +68,7 @@ void free_system(asyrk_system *s) {
     (void)hipFree(s->d_loc);
     (void)hipFree(s->d_b64);
     (void)hipFree(s->d_x);
+    (void)hipFree(s->d_side);
     (void)hipFree(s->d_x64);
     (void)hipFree(s->d_xref);
     (void)hipFree(s->d_part);
@@ -188,6 +188,7 @@ void asyrk_solve_params_init(asyrk_solve_params *p) {
     p->sampling = ASYRK_SAMPLE_NORM2;
     p->update = ASYRK_UPDATE_ALL;
     p->check_every = 1;
+    p->iter_dtype = -1;
 }
 
 asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
@@ -252,7 +253,7 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     TRY(dmalloc(s, &s->d_rec, res.rec.size()));
     if (res.fixed_nnz == 0) TRY(dmalloc(s, &s->d_loc, res.loc.size() * sizeof(RowLoc)));
     TRY(dmalloc(s, &s->d_b64, (size_t)m * sizeof(double)));
-    TRY(dmalloc(s, &s->d_x, (size_t)n * x_bytes(s)));
+    TRY(dmalloc(s, &s->d_x, (size_t)n * 8));
     TRY(dmalloc(s, &s->d_x64, (size_t)n * sizeof(double)));
     TRY(dmalloc(s, &s->d_xref, (size_t)n * sizeof(double)));
     TRY(dmalloc(s, &s->d_part, (size_t)kResidualBlocks * sizeof(double)));
@@ -316,6 +317,7 @@ asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b) {
         if (!std::isfinite(hb[i])) return ASYRK_ERR_INVALID_ARG;
     HIP_OK(hipMemcpyAsync(s->d_b64, hb, (size_t)s->m * sizeof(double), hipMemcpyHostToDevice, s->st));
     HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+    if (s->d_side) HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
     HIP_OK(hipStreamSynchronize(s->st));
     s->rec_b_dirty = false;
     return ASYRK_OK;
@@ -427,12 +429,13 @@ asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_
 
 // ------------------------------------------------------------------- solve
 
-static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int G, int64_t R, double gamma,
+static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
                                uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
                                double *win_max_ticks, double *win_sum_ticks, double *win_cnt) {
     SweepArgs a{};
     a.rows = s->rows;
     a.x = s->d_x;
+    a.side = s->d_side;
     a.t_begin = t_begin;
     a.t_end = t_end;
     a.R = R;
@@ -445,7 +448,7 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     a.gamma = gamma;
     a.trace = p.trace ? s->d_trace : nullptr;
     HIP_OK(hipEventRecord(s->e0, s->st));
-    HIP_OK(launch_sweep(s->vk, G, a, s->st));
+    HIP_OK(launch_sweep(s->vk, xk, G, a, s->st));
     HIP_OK(hipEventRecord(s->e1, s->st));
     HIP_OK(hipEventSynchronize(s->e1));
     float ms = 0.f;
@@ -481,14 +484,18 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.in_flight < 0 || p.check_every < 1 || !(p.tol >= 0.0) || !std::isfinite(p.tol) || p.ticket0 < 0 ||
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
         return ASYRK_ERR_INVALID_ARG;
-    if (p.refine && s->vk == ASYRK_F64) return ASYRK_ERR_UNSUPPORTED;
+    if (p.reserved != 0) return ASYRK_ERR_INVALID_ARG;
+    if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
+    const int xk = p.iter_dtype >= 0 ? p.iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
+    if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
+    if (p.refine && xk == ASYRK_F64) return ASYRK_ERR_UNSUPPORTED;
     if (p.refine && (p.mode == ASYRK_REPLAY || p.update == ASYRK_UPDATE_ONE)) return ASYRK_ERR_UNSUPPORTED;
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
     const int G = p.lanes ? p.lanes : auto_lanes(s);
     int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
-    const bool f32 = iter_is_f32(s);
+    const bool f32 = xk == ASYRK_F32;
     const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2h = s->mem == ASYRK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 
@@ -516,6 +523,10 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (s->rec_b_dirty) {
         HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
         s->rec_b_dirty = false;
+    }
+    if (xk == ASYRK_F64 && s->vk != ASYRK_F64 && !s->d_side) {
+        HIP_OK(dmalloc(s, &s->d_side, (size_t)s->m * sizeof(double2)));
+        HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
     }
     if (p.trace) {
         if (s->trace_cap < R) {
@@ -549,7 +560,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         }
         while (done < sweeps) {
             const int64_t c = std::min<int64_t>(p.check_every, sweeps - done);
-            asyrk_status rc = run_sweeps(s, p, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum,
+            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum,
                                          &wcnt);
             if (rc) return rc;
             ticket += c * s->m;
@@ -589,7 +600,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
             s->rec_b_dirty = true;
             HIP_OK(launch_zero(s->d_x, (int64_t)s->n * 4, s->st));
             const int64_t c = std::min<int64_t>(inner, sweeps - done);
-            rc = run_sweeps(s, p, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum, &wcnt);
+            rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum, &wcnt);
             if (rc) return rc;
             ticket += c * s->m;
             done += c;

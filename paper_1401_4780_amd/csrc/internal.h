@@ -22,7 +22,8 @@ struct Rows {
 // Arguments of the sweep kernel.
 struct SweepArgs {
     Rows rows;
-    void *x;               // iterate, x_t[n]
+    void *x;               // iterate: float[n] or double[n]
+    const double2 *side;   // FP64 iterate over FP32/BF16 records: {b_i, 1/w_i} per row
     int64_t t_begin;       // first ticket
     int64_t t_end;         // one past the last ticket
     int64_t R;             // row workers
@@ -78,7 +79,8 @@ __device__ __forceinline__ U4 draw(int64_t j, uint32_t stream_id, uint32_t k0, u
 // ---------------------------------------------------------------------------
 // Host-side launchers (kernels.hip).  All return hipError_t of the launch.
 // ---------------------------------------------------------------------------
-hipError_t launch_sweep(int vk, int G, const SweepArgs &a, hipStream_t st);
+hipError_t launch_sweep(int vk, int xk, int G, const SweepArgs &a, hipStream_t st);
+hipError_t launch_build_side(int vk, const Rows &rows, const double *b64, double2 *side, hipStream_t st);
 hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
                            double *r_out, int write_rec_b, double *partials, int nblocks,
                            hipStream_t st);

@@ -12,6 +12,8 @@
 //     read sees every atomic already performed by any XCD, and written with
 //     no-return global_atomic_add_f32/f64; x (4-16 MB) lives in the caches;
 //   * no LDS and no MFMA: there is no dense contraction in this method.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace asyrk {
@@ -106,11 +108,14 @@ template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; }
 
 // ---------------------------------------------------------------- sweep
 
-template <int VK, int G>
+// XK: iterate dtype.  FP32 records with an FP64 iterate read b_i and 1/w_i
+// in FP64 from the side array (the record header holds them in FP32).
+template <int VK, int XK, int G>
 __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     using T = VT<VK>;
-    using X = typename T::x_t;
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     using H = typename T::hdr_t;
+    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
     constexpr int U = T::U;
     constexpr int UPL = Upl<G>::value;
 
@@ -193,11 +198,20 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
         acc = group_sum<G>(acc);
 
         // a4: step s = gamma * (a_i^T x - b_i) / ||a_i||^2
-        const X r = acc - (X)h.b;
+        X bi, inv_w;
+        if constexpr (SIDE) {
+            const double2 sd = a.side[i];
+            bi = sd.x;
+            inv_w = sd.y;
+        } else {
+            bi = (X)h.b;
+            inv_w = (X)h.inv_w;
+        }
+        const X r = acc - bi;
 
         // a5: lock-free scatter
         if (!a.update_one) {
-            const X s = gamma * r * (X)h.inv_w;
+            const X s = gamma * r * inv_w;
             if (one_pass) {
 #pragma unroll
                 for (int q = 0; q < UPL; ++q) {
@@ -227,10 +241,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
             // Algorithm 1: one coordinate t, step gamma * theta_i
             const int t = (int)(((uint64_t)u.d * (uint64_t)nnz) >> 32);
             int c;
-            X v;
+            typename VT<VK>::x_t v;
             load_entry<VK>(rec, t, c, v);
-            const X s1 = gamma * (X)nnz * r * (X)h.inv_w;
-            unsafeAtomicAdd(x + c, -s1 * v);
+            const X s1 = gamma * (X)nnz * r * inv_w;
+            unsafeAtomicAdd(x + c, -s1 * (X)v);
         }
 
         if (a.trace) {
@@ -248,29 +262,67 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     }
 }
 
-template <int VK>
+template <int VK, int XK>
 static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     const int64_t threads = a.R * G;
     const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
     const int64_t grid = (threads + block - 1) / block;
     switch (G) {
-        case 1: hipLaunchKernelGGL((sweep_kernel<VK, 1>), dim3(grid), dim3(block), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((sweep_kernel<VK, 2>), dim3(grid), dim3(block), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((sweep_kernel<VK, 4>), dim3(grid), dim3(block), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((sweep_kernel<VK, 8>), dim3(grid), dim3(block), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((sweep_kernel<VK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((sweep_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((sweep_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((sweep_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((sweep_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int vk, int G, const SweepArgs &a, hipStream_t st) {
-    switch (vk) {
-        case ASYRK_F32: return launch_sweep_vk<ASYRK_F32>(G, a, st);
-        case ASYRK_BF16: return launch_sweep_vk<ASYRK_BF16>(G, a, st);
-        case ASYRK_F64: return launch_sweep_vk<ASYRK_F64>(G, a, st);
+hipError_t launch_sweep(int vk, int xk, int G, const SweepArgs &a, hipStream_t st) {
+    if (xk == ASYRK_F32) {
+        switch (vk) {
+            case ASYRK_F32: return launch_sweep_vk<ASYRK_F32, ASYRK_F32>(G, a, st);
+            case ASYRK_BF16: return launch_sweep_vk<ASYRK_BF16, ASYRK_F32>(G, a, st);
+        }
+    } else if (xk == ASYRK_F64) {
+        switch (vk) {
+            case ASYRK_F32: return launch_sweep_vk<ASYRK_F32, ASYRK_F64>(G, a, st);
+            case ASYRK_BF16: return launch_sweep_vk<ASYRK_BF16, ASYRK_F64>(G, a, st);
+            case ASYRK_F64: return launch_sweep_vk<ASYRK_F64, ASYRK_F64>(G, a, st);
+        }
     }
     return hipErrorInvalidValue;
+}
+
+// side[i] = {b_i, 1/w_i} in FP64, w_i = ||a_i||^2 from the stored values
+// (summed in record order; FP64 iterate over FP32/BF16 records).
+template <int VK>
+__global__ __launch_bounds__(256) void build_side_kernel(const Rows rows, const double *b64, double2 *side) {
+    using T = VT<VK>;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows.m; i += stride) {
+        const uint8_t *rec;
+        int nnz;
+        locate(rows, (uint32_t)i, rec, nnz);
+        double w = 0.0;
+        for (int k = 0; k < nnz; ++k) {
+            int c;
+            typename T::x_t v;
+            load_entry<VK>(rec, k, c, v);
+            w = __dadd_rn(w, __dmul_rn((double)v, (double)v));
+        }
+        side[i] = make_double2(b64[i], 1.0 / w);
+    }
+}
+
+hipError_t launch_build_side(int vk, const Rows &rows, const double *b64, double2 *side, hipStream_t st) {
+    const int grid = (int)((rows.m + 255) / 256 < 8192 ? (rows.m + 255) / 256 : 8192);
+    switch (vk) {
+        case ASYRK_F32: hipLaunchKernelGGL(build_side_kernel<ASYRK_F32>, dim3(grid), dim3(256), 0, st, rows, b64, side); break;
+        case ASYRK_BF16: hipLaunchKernelGGL(build_side_kernel<ASYRK_BF16>, dim3(grid), dim3(256), 0, st, rows, b64, side); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- reductions

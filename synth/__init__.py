@@ -35,6 +35,7 @@ __all__ = [
     "serving_system",
     "poisson_arrivals",
     "ragged_rows",
+    "as_dtype",
     "bf16_bits_from_f32",
     "f64_from_bf16_bits",
     "DTYPES",
@@ -179,36 +180,47 @@ def uniform_rows(m: int, n: int, nnz_per_row: int, seed: int, dtype: str = "f32"
     return _finish(m, n, row_ptr, cols, v64, dtype, rng, x_star=x_star)
 
 
-def _zipf_cdf(n: int, s: float) -> np.ndarray:
+def _zipf_table(n: int, s: float):
+    """Alias table (probability, alias) for P(rank k) proportional to k^-s,
+    k = 1..n (index k-1), for O(1) vectorized draws."""
     w = np.arange(1, n + 1, dtype=np.float64) ** (-s)
-    c = np.cumsum(w)
-    return c / c[-1]
+    p = w * (n / w.sum())
+    prob = np.ones(n)
+    alias = np.arange(n)
+    small = list(np.nonzero(p < 1.0)[0])
+    large = list(np.nonzero(p >= 1.0)[0])
+    p = p.tolist()
+    while small and large:
+        a = small.pop()
+        g = large.pop()
+        prob[a] = p[a]
+        alias[a] = g
+        p[g] = (p[g] + p[a]) - 1.0
+        (small if p[g] < 1.0 else large).append(g)
+    return prob, alias
 
 
 def _distinct_rows_from_sampler(rng, lengths: np.ndarray, draw) -> np.ndarray:
     """Per row, the first ``lengths[i]`` distinct values of an i.i.d. stream ``draw``.
 
-    Rows are handled in groups of similar length; a row whose pool holds too few
-    distinct values is drawn again with a larger pool.  Returns the
-    concatenated, per-row sorted column lists.
+    Rows are handled in groups of similar length with a pool of draws per row;
+    a row whose pool holds too few distinct values is drawn again with a larger
+    pool.  Returns the concatenated, per-row sorted column lists.
     """
     m = lengths.size
-    out = [None] * m
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lengths, out=row_ptr[1:])
+    out = np.empty(int(row_ptr[-1]), dtype=np.int64)
     todo = np.arange(m)
-    factor = 3
+    factor = 1.25
     while todo.size:
         lens = lengths[todo]
-        order = np.argsort(lens, kind="stable")
-        todo_sorted = todo[order]
-        lens_sorted = lens[order]
+        g_of = np.floor(np.log2(np.maximum(lens, 1))).astype(np.int64)
         retry = []
-        # groups of rows with length in [2^g, 2^(g+1))
-        g_of = np.floor(np.log2(np.maximum(lens_sorted, 1))).astype(np.int64)
         for g in np.unique(g_of):
-            sel = np.nonzero(g_of == g)[0]
-            idx = todo_sorted[sel]
-            ln = lens_sorted[sel]
-            pool = int(factor * (2 ** (g + 1)) + 16)
+            idx = todo[g_of == g]
+            ln = lengths[idx]
+            pool = int(factor * (2 ** (g + 1))) + 16
             draws = draw(rng, (idx.size, pool))
             # first occurrence of each value in draw order
             srt = np.argsort(draws, axis=1, kind="stable")
@@ -217,19 +229,25 @@ def _distinct_rows_from_sampler(rng, lengths: np.ndarray, draw) -> np.ndarray:
             first[:, 1:] = sv[:, 1:] != sv[:, :-1]
             keep = np.zeros_like(first)
             np.put_along_axis(keep, srt, first, axis=1)
-            # rank of each first occurrence in draw order
             rank = np.cumsum(keep, axis=1)
-            for r in range(idx.size):
-                need = ln[r]
-                ok = keep[r] & (rank[r] <= need)
-                vals = draws[r][ok]
-                if vals.size < need:
-                    retry.append(idx[r])
-                else:
-                    out[idx[r]] = np.sort(vals)
-        todo = np.array(retry, dtype=np.int64)
+            ok_rows = rank[:, -1] >= ln
+            retry.append(idx[~ok_rows])
+            sel = keep & (rank <= ln[:, None]) & ok_rows[:, None]
+            r_i, _ = np.nonzero(sel)
+            vals = draws[sel]
+            # sort each row's values: order by (row, value)
+            order = np.lexsort((vals, r_i))
+            vals = vals[order]
+            r_i = r_i[order]
+            good = idx[ok_rows]
+            starts = row_ptr[good]
+            # position of each value inside its row
+            cnt = ln[ok_rows]
+            offs = np.repeat(starts, cnt) + (np.arange(vals.size) - np.repeat(np.cumsum(cnt) - cnt, cnt))
+            out[offs] = vals
+        todo = np.concatenate(retry) if retry else np.zeros(0, dtype=np.int64)
         factor *= 4
-    return np.concatenate(out) if m else np.zeros(0, dtype=np.int64)
+    return out
 
 
 def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 16.0,
@@ -237,7 +255,8 @@ def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 1
     """Skewed rows: lognormal lengths and Zipf-distributed (hot) columns.
 
     * nnz_i = clip(round(exp(N(ln median, sigma))), lo, min(hi, n))
-    * column ranks 1..n drawn with P(k) proportional to k^-zipf_s, mapped to
+    * column ranks 1..n drawn with P(k) proportional to k^-zipf_s (alias
+      table, two uniforms per draw), mapped to
       columns through a seeded random permutation (hot columns are scattered),
       distinct within a row (first distinct draws kept).
     * N(0,1) values, rows normalized in float64 then rounded to ``dtype``.
@@ -251,11 +270,11 @@ def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 1
     lens = np.rint(np.exp(rng.normal(math.log(median), sigma, size=m))).astype(np.int64)
     lens = np.clip(lens, lo, min(hi, n))
     perm = rng.permutation(n).astype(np.int64)
-    cdf = _zipf_cdf(n, zipf_s)
+    prob, alias = _zipf_table(n, zipf_s)
 
     def draw(r, shape):
-        ranks = np.searchsorted(cdf, r.random(shape), side="right")
-        ranks = np.minimum(ranks, n - 1)
+        k = np.minimum((r.random(shape) * n).astype(np.int64), n - 1)
+        ranks = np.where(r.random(shape) < prob[k], k, alias[k])
         return perm[ranks]
 
     cols = _distinct_rows_from_sampler(rng, lens, draw)
@@ -263,6 +282,20 @@ def skewed_rows(m: int, n: int, seed: int, dtype: str = "f32", median: float = 1
     np.cumsum(lens, out=row_ptr[1:])
     v64 = _normal_rows_normalized(rng, cols.size, row_ptr)
     return _finish(m, n, row_ptr, cols, v64, dtype, rng, x_star_mode="range")
+
+
+def as_dtype(s: SparseSystem, dtype: str) -> SparseSystem:
+    """The same system stored in another dtype: the float64 values of ``s``
+    (which must be stored in f64) rounded to ``dtype``, the same x*, and b
+    recomputed from the rounded values.  Equal to generating with ``dtype``
+    directly for the same seed, without drawing everything again."""
+    if s.dtype != "f64":
+        raise ValueError("as_dtype starts from an f64 system")
+    val, val64 = _store(s.val64, dtype)
+    prod = val64 * s.x_star[s.col]
+    b = np.add.reduceat(prod, s.row_ptr[:-1]) if prod.size else np.zeros(s.m)
+    b[np.diff(s.row_ptr) == 0] = 0.0
+    return SparseSystem(s.m, s.n, s.row_ptr, s.col, val, dtype, val64, s.x_star, b)
 
 
 def ragged_rows(m: int, n: int, lengths, seed: int, dtype: str = "f64",

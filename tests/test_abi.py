@@ -60,6 +60,7 @@ def test_status_strings_and_defaults():
     p = P.SolveParams()
     L.asyrk_solve_params_init(C.byref(p))
     assert (p.mode, p.sampling, p.update, p.check_every, p.in_flight, p.lanes) == (0, 0, 0, 1, 0, 0)
+    assert p.iter_dtype == -1  # -1 = default; 0 is ASYRK_F64
 
 
 def _create(rp, col, val, b, n, dtype=P.F32, mem=P.MEM_HOST):

@@ -175,6 +175,25 @@ def test_replay_fp32_storage_within_fp32_floor(dtype):
     sysm.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_replay_fp64_iterate_over_fp32_storage(dtype):
+    """FP64 iterate and atomics over FP32/BF16-stored values: the arithmetic is
+    FP64 on the stored values, so it matches the FP64 oracle to 1e-12."""
+    rng = np.random.default_rng(12)
+    s = synth.ragged_rows(1500, 400, rng.integers(1, 40, 1500), seed=12, dtype=dtype)
+    _say(f"replay {dtype} values, f64 iterate")
+    ref = oracle_run(s, 1.0, 10, 3)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=10, seed=3, mode="replay", iter_dtype="f64",
+                      history=16)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    # the same system still runs with the default FP32 iterate afterwards
+    x2, st2 = gpu_solve(sysm, s, True, gamma=1.0, sweeps=10, seed=3, mode="replay")
+    assert np.linalg.norm(x2 - ref["x"]) <= 1e-5 * np.linalg.norm(s.x_star)
+    sysm.close()
+
+
 def test_replay_single_coordinate_algorithm1():
     """Algorithm 1: uniform rows, one coordinate, step gamma*theta_i, gamma = 1/mu."""
     s = synth.uniform_rows(300, 100, 8, seed=6, dtype="f64", require_full_columns=False)
@@ -244,6 +263,18 @@ def test_async_fp64_reaches_1e10():
     assert st["status"] == "OK", st
     assert np.linalg.norm(x - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
     assert st["sweeps_done"] <= math.ceil(1.5 * k_orc) + 1
+    sysm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_async_fp64_iterate_over_fp32_storage_reaches_1e10(dtype):
+    s = synth.uniform_rows(40_000, 10_000, 16, seed=3, dtype=dtype)
+    _say(f"async {dtype} values f64 iterate to 1e-10")
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=2, tol=1e-10, in_flight=512,
+                      iter_dtype="f64")
+    assert st["status"] == "OK", st
+    assert np.linalg.norm(x - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
     sysm.close()
 
 

@@ -81,3 +81,12 @@ def test_serving_stream():
     assert lens.min() >= 8 and lens.max() <= 64
     t = synth.poisson_arrivals(1000, 50.0)
     assert np.all(np.diff(t) > 0) and 10 < t[-1] < 30
+
+
+def test_as_dtype_equals_direct_generation():
+    a = synth.uniform_rows(700, 200, 6, seed=9, dtype="f64")
+    for dt in ("f32", "bf16"):
+        b = synth.as_dtype(a, dt)
+        c = synth.uniform_rows(700, 200, 6, seed=9, dtype=dt)
+        assert np.array_equal(b.col, c.col) and np.array_equal(b.val, c.val)
+        assert np.array_equal(b.b, c.b) and np.array_equal(b.x_star, c.x_star)
