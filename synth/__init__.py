@@ -340,36 +340,61 @@ def serving_specs(count: int = 10_000, seed: int = 4, m_lo: int = 1_000, m_hi: i
     return np.stack([m, n], axis=1)
 
 
-def serving_system(request_id: int, m: int, n: int, seed: int = 4, dtype: str = "f32",
-                   nnz_lo: int = 8, nnz_hi: int = 64) -> SparseSystem:
-    """One serving request: nnz/row uniform in {nnz_lo..nnz_hi} (capped at n),
-    distinct uniform columns, N(0,1) values, unit rows, x* ~ N(0,1).
+_SG_LIB = None
+_HERE = __import__("pathlib").Path(__file__).resolve().parent
 
-    Seeded by (seed, request_id) so each request is reproducible on its own.
+
+def build_serving_gen():
+    """Compile serving_gen.c into synth/_build/libservinggen.so (always rebuilds)."""
+    import os
+    import subprocess
+    out = _HERE / "_build"
+    out.mkdir(exist_ok=True)
+    lib = out / "libservinggen.so"
+    tmp = out / f"libservinggen.so.tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", str(_HERE / "serving_gen.c"),
+                    "-o", str(tmp), "-lm"], check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
+def _sg():
+    global _SG_LIB
+    if _SG_LIB is None:
+        import ctypes as C
+        lib = _HERE / "_build" / "libservinggen.so"
+        if not lib.exists() or lib.stat().st_mtime < (_HERE / "serving_gen.c").stat().st_mtime:
+            build_serving_gen()
+        L = C.CDLL(str(lib))
+        P = C.c_void_p
+        L.sg_lengths.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int, P]
+        L.sg_lengths.restype = C.c_int64
+        L.sg_fill.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, P, P, P, P, P, P]
+        L.sg_fill.restype = None
+        _SG_LIB = L
+    return _SG_LIB
+
+
+def serving_system(request_id: int, m: int, n: int, seed: int = 4,
+                   nnz_lo: int = 8, nnz_hi: int = 64) -> SparseSystem:
+    """One serving request (FP32 values), generated in C (``serving_gen.c``):
+    row lengths uniform in {nnz_lo..nnz_hi} (capped at n), distinct uniform
+    columns, N(0,1) values, unit rows, x* ~ N(0,1), b = A x* in FP64.
+
+    Seeded by (seed, request_id) so each request is reproducible on its own;
+    the C call releases the GIL, so threads generate requests in parallel.
     """
-    rng = np.random.default_rng([seed, request_id])
-    hi = min(nnz_hi, n)
-    lo = min(nnz_lo, hi)
-    lens = rng.integers(lo, hi + 1, size=m).astype(np.int64)
-    cols = []
+    L = _sg()
     row_ptr = np.zeros(m + 1, dtype=np.int64)
-    np.cumsum(lens, out=row_ptr[1:])
-    for k in np.unique(lens):
-        sel = np.nonzero(lens == k)[0]
-        c = _distinct_uniform_cols(rng, sel.size, n, int(k))
-        cols.append((sel, c))
-    col = np.empty(int(row_ptr[-1]), dtype=np.int64)
-    for sel, c in cols:
-        starts = row_ptr[sel]
-        idx = starts[:, None] + np.arange(c.shape[1])[None, :]
-        col[idx.reshape(-1)] = c.reshape(-1)
-    counts = np.bincount(col, minlength=n)
-    if counts.min() == 0:
-        # fill an empty column by moving one entry of a row that holds a column
-        # seen more than once; rare for these shapes
-        raise RuntimeError("serving system with an empty column; change request id")
-    v64 = _normal_rows_normalized(rng, col.size, row_ptr)
-    return _finish(m, n, row_ptr, col, v64, dtype, rng)
+    nnz = int(L.sg_lengths(seed, request_id, m, n, nnz_lo, nnz_hi, row_ptr.ctypes.data))
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float32)
+    val64 = np.empty(nnz, dtype=np.float64)
+    x_star = np.empty(n, dtype=np.float64)
+    b = np.empty(m, dtype=np.float64)
+    L.sg_fill(seed, request_id, m, n, row_ptr.ctypes.data, col.ctypes.data, val.ctypes.data,
+              val64.ctypes.data, x_star.ctypes.data, b.ctypes.data)
+    return SparseSystem(m, n, row_ptr, col, val, "f32", val64, x_star, b)
 
 
 def poisson_arrivals(count: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
