@@ -42,7 +42,7 @@ R_SWEEP = (1024, 2048, 4096, 8192, 16384, 32768, 65536)
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h", "layout.h", "api.hip", "setup.cpp"):
+    for f in ("kernels.hip", "device.h", "internal.h", "layout.h", "api.hip", "setup.cpp"):
         h.update((ROOT / "paper_1401_4780_amd" / "csrc" / f).read_bytes())
     return h.hexdigest()[:16]
 
@@ -311,6 +311,105 @@ def run_skewed(args):
             "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
 
 
+def run_serving(args):
+    """Poisson stream of independent systems (m log-uniform in [1k, 200k],
+    n = m/4, 8..64 entries per row, FP32 values, FP64 refinement to 1e-8
+    relative residual) through the continuous-batching server; arrival rate
+    swept as a fraction of the measured saturation throughput."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    import paper_1401_4780_amd as P
+    import synth
+
+    tol = 1e-8
+    n_req = args.requests
+    rates = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
+    specs = synth.serving_specs(n_req * (len(rates) + 1), seed=4)
+    pool = ThreadPoolExecutor(16)
+
+    def gen(rid):
+        m, n = (int(v) for v in specs[rid])
+        return synth.serving_system(rid, m, n)
+
+    srv = P.Server(budget_bytes=64 << 30)
+
+    def drive(first, count, arrivals):
+        """Submit requests first..first+count-1 at their arrival times (seconds
+        after t0) from a thread pool; run rounds until all finished."""
+        systems = list(pool.map(gen, range(first, first + count)))
+        t0 = P.now() + 0.05
+        ids = [None] * count
+        sub_pool = ThreadPoolExecutor(8)
+
+        def submit(k):
+            delay = t0 + arrivals[k] - P.now()
+            if delay > 0:
+                time.sleep(delay)
+            s = systems[k]
+            ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=tol, seed=first + k)
+
+        futs = [sub_pool.submit(submit, k) for k in range(count)]
+        done, lat, sweeps, bad = {}, [], [], 0
+        while len(done) < count:
+            active, queued = srv.progress()
+            if active == 0 and queued == 0:
+                time.sleep(0.0005)
+            for k in range(count):
+                if k in done or ids[k] is None:
+                    continue
+                r = srv.poll(ids[k])
+                if r is not None:
+                    status, st, _ = r
+                    done[k] = st
+                    lat.append(st["t_done"] - (t0 + arrivals[k]))
+                    sweeps.append(st["sweeps"])
+                    bad += status != "OK" or st["rel_residual"] > tol
+        for f in futs:
+            f.result()
+        t_end = max(st["t_done"] for st in done.values())
+        sub_pool.shutdown()
+        return {"solves_per_s": count / (t_end - t0), "latency_s_p50": float(np.percentile(lat, 50)),
+                "latency_s_p99": float(np.percentile(lat, 99)), "mean_sweeps": float(np.mean(sweeps)),
+                "failed": int(bad)}
+
+    # saturation: every request present at t = 0
+    sat = drive(0, n_req, np.zeros(n_req))
+    log(f"serving saturation: {sat}")
+    sweep = {}
+    for q, f in enumerate(rates):
+        rate = f * sat["solves_per_s"]
+        arr = synth.poisson_arrivals(n_req, rate, seed=5 + q)
+        sweep[str(f)] = dict(drive(n_req * (q + 1), n_req, arr), offered_per_s=rate)
+        log(f"serving load {f}: {sweep[str(f)]}")
+    st = srv.stats()
+    srv.close()
+
+    # baseline: the same kind of requests one at a time, plain FP64 sweeps
+    dev = torch.device("cuda:0")
+    nb = min(40, n_req)
+    base_sys = list(pool.map(gen, range(nb)))
+    t0 = time.perf_counter()
+    for s in base_sys:
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n)
+        x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+        sysm.solve(x, 1.0, 400, 1, tol=tol, iter_dtype="f64")
+        sysm.close()
+    torch.cuda.synchronize()
+    base = nb / (time.perf_counter() - t0)
+    return {"metric": "solves/s and p50/p99 solve latency (serving)", "value": sat["solves_per_s"],
+            "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
+            "vs_baseline": None, "data": "synthetic", "dtype": "f32 sweeps, f64 refinement",
+            "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8",
+                       "requests_per_point": n_req, "budget_GiB": 64, "tol": tol},
+            "saturation": sat, "by_load": sweep,
+            "sequential_fp64_solves_per_s": base,
+            "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
+            "server_stats": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +418,8 @@ def main():
     ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--inner", type=int, default=0, help="refinement inner sweeps (0: default)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed", "serving"])
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
     args = ap.parse_args()
@@ -327,7 +427,8 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
         sys.exit(2)
-    fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed}[args.workload]
+    fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed,
+          "serving": run_serving}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

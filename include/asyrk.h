@@ -59,7 +59,8 @@ typedef enum asyrk_status {
     ASYRK_ERR_NOT_CONVERGED = 5, /* tol > 0 and the sweep budget ran out; x and stats are valid */
     ASYRK_ERR_DIVERGED = 6,      /* the monitored error became non-finite or grew 1e6-fold */
     ASYRK_ERR_CANCELLED = 7,     /* the cancel flag was set; x holds the last checked iterate */
-    ASYRK_ERR_UNSUPPORTED = 8    /* a valid combination this build does not implement */
+    ASYRK_ERR_UNSUPPORTED = 8,   /* a valid combination this build does not implement */
+    ASYRK_PENDING = 9            /* asyrk_server_poll: the request has not finished yet */
 } asyrk_status;
 
 typedef enum asyrk_dtype { ASYRK_F64 = 0, ASYRK_F32 = 1, ASYRK_BF16 = 2 } asyrk_dtype;
@@ -145,6 +146,9 @@ typedef struct asyrk_system_info {
     double fro2;               /* ||A||_F^2 (FP64, stored values) */
     double lambda_mp;          /* (1 + sqrt(n/m))^2 * fro2 / n: Gaussian-ensemble estimate of lambda_max */
     int64_t record_bytes_per_row; /* algorithmic bytes per row update (values, indices, b_i, w_i, start) */
+    double max_col_norm2;      /* max_j ||column j||^2, a lower bound on lambda_max */
+    int64_t default_in_flight; /* R used when in_flight = 0: Corollary 1's bound with
+                                  lambda = max(lambda_mp, max_col_norm2), in [1, 65536] */
 } asyrk_system_info;
 
 /* Version of this ABI (ASYRK_ABI_VERSION). */
@@ -246,6 +250,81 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
 asyrk_status asyrk_probe_copy(int64_t bytes, int32_t iters, double *gbps);
 asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_t kind,
                                  int32_t iters, double *per_s);
+
+/* ------------------------------------------------------------------------
+ * Serving: many independent systems with continuous batching.
+ *
+ * Each request is a consistent system with FP32 values, solved to
+ * ||b - A x|| <= tol ||b|| by FP32 asynchronous sweeps (row workers bounded by
+ * the system's own Corollary 1 limit) inside an FP64 refinement loop
+ * (r = b - A x, d from A d = fp32(r), x += d).  One progress() call runs one
+ * round over every active system in one packed launch per phase; requests
+ * that arrive meanwhile are admitted as slots, workers and device memory
+ * free up.  A request's result does not depend on what else is in the batch
+ * beyond the nondeterminism of asynchronous execution.
+ * Threads: submit/poll/stats may be called from any thread; progress from one
+ * thread at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct asyrk_server asyrk_server;
+
+typedef struct asyrk_server_config {
+    int64_t budget_bytes;  /* device memory for resident systems (one arena), default 64 GiB */
+    int32_t max_slots;     /* systems active at once, default 1024 */
+    int32_t inner_sweeps;  /* FP32 sweeps per round (refinement inner solve), default 10 */
+    int64_t max_workers;   /* row workers over all active systems, default 65536 */
+    int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
+    int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */
+    double gamma;          /* step length in (0, 2), default 1 */
+} asyrk_server_config;
+
+typedef struct asyrk_request_stats {
+    int64_t m, n, nnz;
+    int64_t in_flight;     /* R_s */
+    int64_t sweeps;        /* FP32 sweeps run */
+    int32_t rounds;        /* refinement rounds */
+    int32_t status;        /* ASYRK_OK, ASYRK_ERR_NOT_CONVERGED or ASYRK_ERR_DIVERGED */
+    double rel_residual;   /* ||b - A x|| / ||b|| of the returned x (FP64) */
+    double t_submit, t_admit, t_done;  /* asyrk_now() clock, seconds */
+} asyrk_request_stats;
+
+typedef struct asyrk_server_stats {
+    int64_t submitted, admitted, completed, active, queued, rounds, row_updates, arena_used;
+    double gpu_seconds;    /* time of the rounds on the GPU (HIP events) */
+} asyrk_server_stats;
+
+/* Defaults for asyrk_server_config. */
+void asyrk_server_config_init(asyrk_server_config *c);
+
+/* Create a server (its own non-blocking HIP stream; allocates the arena).
+ * Errors: INVALID_ARG, OOM, DEVICE. */
+asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg);
+
+/* Destroy a server and every request it holds (NULL is accepted). */
+asyrk_status asyrk_server_destroy(asyrk_server *s);
+
+/* Queue one request: HOST arrays (CSR as in asyrk_create, FP32 values, FP64
+ * b), tol > 0 on ||b - A x||/||b||, Philox seed.  The arrays are copied
+ * (packed on the calling thread); *request_id receives its id.
+ * Errors: INVALID_ARG, ZERO_ROW, OOM (larger than the whole budget). */
+asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const float *vals, const double *b, double tol,
+                                 uint64_t seed, int64_t *request_id);
+
+/* Admit what fits, run one round, retire finished requests.  n_active /
+ * n_queued (nullable) receive the counts after the round.  Errors: DEVICE. */
+asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued);
+
+/* Result of a finished request: x_out (nullable, HOST double[n]) and stats
+ * (nullable).  Returns the request's final status, ASYRK_PENDING while it is
+ * queued or active, INVALID_ARG for an unknown or already-polled id. */
+asyrk_status asyrk_server_poll(asyrk_server *s, int64_t request_id, double *x_out,
+                               asyrk_request_stats *st);
+
+/* Counters of the server. */
+asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out);
+
+/* The host clock the server's timestamps use (steady clock, seconds). */
+double asyrk_now(void);
 
 #ifdef __cplusplus
 }

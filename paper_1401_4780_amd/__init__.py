@@ -20,8 +20,8 @@ from pathlib import Path
 
 import numpy as np
 
-__all__ = ["System", "AsyrkError", "LibraryMissing", "lib", "library_path", "probe_copy",
-           "probe_scatter", "STATUS", "F64", "F32", "BF16"]
+__all__ = ["System", "Server", "AsyrkError", "LibraryMissing", "lib", "library_path", "probe_copy",
+           "probe_scatter", "now", "STATUS", "F64", "F32", "BF16"]
 
 LIB_PATH = Path(__file__).resolve().parent / "_build" / "libasyrk.so"
 
@@ -31,7 +31,7 @@ ASYNC, REPLAY = 0, 1
 SAMPLE_NORM2, SAMPLE_UNIFORM = 0, 1
 UPDATE_ALL, UPDATE_ONE = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "ZERO_ROW", 3: "OOM", 4: "DEVICE", 5: "NOT_CONVERGED",
-          6: "DIVERGED", 7: "CANCELLED", 8: "UNSUPPORTED"}
+          6: "DIVERGED", 7: "CANCELLED", 8: "UNSUPPORTED", 9: "PENDING"}
 _SOFT = {5, 6, 7}  # statuses after which x and the stats are still valid
 
 
@@ -74,6 +74,32 @@ class SystemInfo(C.Structure):
         ("fixed_nnz", C.c_int64), ("record_stride", C.c_int64), ("device_bytes", C.c_int64),
         ("vals_dtype", C.c_int32), ("iter_dtype", C.c_int32), ("fro2", C.c_double),
         ("lambda_mp", C.c_double), ("record_bytes_per_row", C.c_int64),
+        ("max_col_norm2", C.c_double), ("default_in_flight", C.c_int64),
+    ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [
+        ("budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("inner_sweeps", C.c_int32),
+        ("max_workers", C.c_int64), ("max_rounds", C.c_int32), ("use_graph", C.c_int32),
+        ("gamma", C.c_double),
+    ]
+
+
+class RequestStats(C.Structure):
+    _fields_ = [
+        ("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64), ("in_flight", C.c_int64),
+        ("sweeps", C.c_int64), ("rounds", C.c_int32), ("status", C.c_int32),
+        ("rel_residual", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+        ("t_done", C.c_double),
+    ]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+        ("active", C.c_int64), ("queued", C.c_int64), ("rounds", C.c_int64),
+        ("row_updates", C.c_int64), ("arena_used", C.c_int64), ("gpu_seconds", C.c_double),
     ]
 
 
@@ -109,9 +135,21 @@ def lib():
     L.asyrk_lambda_max.argtypes = [P, i32, u64, P, P]
     L.asyrk_probe_copy.argtypes = [i64, i32, P]
     L.asyrk_probe_scatter.argtypes = [i64, i64, i32, i32, i32, P]
+    L.asyrk_server_config_init.argtypes = [P]
+    L.asyrk_server_config_init.restype = None
+    L.asyrk_server_create.argtypes = [P, P]
+    L.asyrk_server_destroy.argtypes = [P]
+    L.asyrk_server_submit.argtypes = [P, i64, i64, P, P, P, P, dbl, u64, P]
+    L.asyrk_server_progress.argtypes = [P, P, P]
+    L.asyrk_server_poll.argtypes = [P, i64, P, P]
+    L.asyrk_server_stats_get.argtypes = [P, P]
+    L.asyrk_now.argtypes = []
+    L.asyrk_now.restype = dbl
     for name in ("asyrk_create", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
-                 "asyrk_probe_copy", "asyrk_probe_scatter"):
+                 "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_server_create",
+                 "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
+                 "asyrk_server_poll", "asyrk_server_stats_get"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -299,6 +337,79 @@ class System:
         if not math.isfinite(out["final_err"]):
             out["final_err"] = float("nan")
         return out
+
+
+def now() -> float:
+    """The server's clock (steady clock, seconds)."""
+    return lib().asyrk_now()
+
+
+class Server:
+    """Continuous-batching solve server (asyrk_server_*): submit systems with
+    FP32 values from any thread, drive rounds with progress() from one thread,
+    collect results with poll()."""
+
+    def __init__(self, **cfg):
+        L = lib()
+        c = ServerConfig()
+        L.asyrk_server_config_init(C.byref(c))
+        for k, v in cfg.items():
+            if k == "use_graph":
+                v = int(bool(v))
+            setattr(c, k, v)
+        h = C.c_void_p()
+        _check(L.asyrk_server_create(C.byref(h), C.byref(c)), "asyrk_server_create")
+        self._h = h
+        self.config = {f: getattr(c, f) for f, _ in ServerConfig._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().asyrk_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, row_ptr, col, val, b, *, n, tol=1e-8, seed=0) -> int:
+        for a, kind, name in ((row_ptr, "int64", "row_ptr"), (col, "int32", "col"),
+                              (val, "float32", "val"), (b, "float64", "b")):
+            _expect(a, False, kind, name)
+        rid = C.c_int64()
+        _check(lib().asyrk_server_submit(self._h, row_ptr.shape[0] - 1, int(n), _ptr(row_ptr), _ptr(col),
+                                         _ptr(val), _ptr(b), float(tol), int(seed), C.byref(rid)),
+               "asyrk_server_submit")
+        return rid.value
+
+    def progress(self):
+        """One round; returns (active, queued) afterwards."""
+        a, q = C.c_int32(), C.c_int32()
+        _check(lib().asyrk_server_progress(self._h, C.byref(a), C.byref(q)), "asyrk_server_progress")
+        return a.value, q.value
+
+    def poll(self, request_id, n=None):
+        """None while pending; else (status, stats dict, x) and the request is released."""
+        st = RequestStats()
+        x = np.empty(int(n), dtype=np.float64) if n is not None else None
+        rc = lib().asyrk_server_poll(self._h, int(request_id), _ptr(x), C.byref(st))
+        if rc == 9:
+            return None
+        if rc not in (0, 5, 6):
+            _check(rc, "asyrk_server_poll")
+        return STATUS[rc], {f: getattr(st, f) for f, _ in RequestStats._fields_}, x
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().asyrk_server_stats_get(self._h, C.byref(st)), "asyrk_server_stats_get")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
 
 
 def probe_copy(nbytes=1 << 30, iters=20) -> float:

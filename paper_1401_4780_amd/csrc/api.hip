@@ -18,7 +18,7 @@ struct asyrk_system {
     int32_t mem = ASYRK_MEM_HOST;
     hipStream_t st = nullptr;
     int64_t mu = 0, nu = 0, fixed_nnz = 0, stride = 0;
-    double fro2 = 0.0;
+    double fro2 = 0.0, max_col_norm2 = 0.0;
     Rows rows{};
     uint8_t *d_rec = nullptr;
     RowLoc *d_loc = nullptr;
@@ -121,8 +121,12 @@ double lambda_mp(const asyrk_system *s) {
     return (1.0 + r) * (1.0 + r) * s->fro2 / (double)s->n;
 }
 
+// Corollary 1: tau + 1 <= ||A||_F^2 / (2 e lambda_max), with lambda_max
+// estimated by max(Gaussian-ensemble estimate, largest column norm^2); the
+// latter is a lower bound that dominates for skewed (hot-column) matrices.
 int64_t auto_in_flight(const asyrk_system *s) {
-    const double tmax = std::floor(s->fro2 / (2.0 * M_E * lambda_mp(s)));
+    const double lam = std::max(lambda_mp(s), s->max_col_norm2);
+    const double tmax = std::floor(s->fro2 / (2.0 * M_E * lam));
     int64_t R = (int64_t)tmax;
     if (R < 1) R = 1;
     if (R > 65536) R = 65536;
@@ -175,6 +179,7 @@ const char *asyrk_status_string(asyrk_status s) {
         case ASYRK_ERR_DIVERGED: return "iteration diverged";
         case ASYRK_ERR_CANCELLED: return "cancelled";
         case ASYRK_ERR_UNSUPPORTED: return "unsupported combination";
+        case ASYRK_PENDING: return "request pending";
     }
     return "unknown status";
 }
@@ -243,6 +248,7 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     s->fixed_nnz = res.fixed_nnz;
     s->stride = res.stride;
     s->fro2 = res.fro2;
+    s->max_col_norm2 = res.max_col_norm2;
 
     hipError_t e = hipSuccess;
 #define TRY(expr)                       \
@@ -304,6 +310,8 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
     const int sc = s->vk == ASYRK_F64 ? 8 : 4;  // b_i and w_i in the sweep dtype, 4-byte start
     info->record_bytes_per_row =
         (int64_t)std::llround((double)s->nnz / (double)s->m * (4 + g.VB)) + 2 * sc + 4;
+    info->max_col_norm2 = s->max_col_norm2;
+    info->default_in_flight = auto_in_flight(s);
     return ASYRK_OK;
 }
 

@@ -1,0 +1,235 @@
+// Device-side building blocks of the sweep, shared by the single-system
+// kernels (kernels.hip) and the packed serving kernels (server.hip).
+#pragma once
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace asyrk {
+
+// ---------------------------------------------------------------- utilities
+
+template <class T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __uint_as_float(bits << 16); }
+
+__device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
+    if (r.loc == nullptr) {
+        rec = r.rec + (int64_t)i * r.stride;
+        nnz = r.fixed_nnz;
+    } else {
+        const RowLoc l = r.loc[i];
+        rec = r.rec + (int64_t)l.off16 * 16;
+        nnz = (int)l.nnz;
+    }
+}
+
+template <int VK> struct Unit;
+template <> struct Unit<ASYRK_F32> {
+    int c[4];
+    float v[4];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 ci = *reinterpret_cast<const int4 *>(p);
+        const float4 vi = *reinterpret_cast<const float4 *>(p + 16);
+        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
+        v[0] = vi.x; v[1] = vi.y; v[2] = vi.z; v[3] = vi.w;
+    }
+};
+template <> struct Unit<ASYRK_BF16> {
+    int c[8];
+    float v[8];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 c0 = *reinterpret_cast<const int4 *>(p);
+        const int4 c1 = *reinterpret_cast<const int4 *>(p + 16);
+        const uint4 vb = *reinterpret_cast<const uint4 *>(p + 32);
+        c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w;
+        c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
+        v[0] = bf16_to_f32(vb.x & 0xffffu); v[1] = bf16_to_f32(vb.x >> 16);
+        v[2] = bf16_to_f32(vb.y & 0xffffu); v[3] = bf16_to_f32(vb.y >> 16);
+        v[4] = bf16_to_f32(vb.z & 0xffffu); v[5] = bf16_to_f32(vb.z >> 16);
+        v[6] = bf16_to_f32(vb.w & 0xffffu); v[7] = bf16_to_f32(vb.w >> 16);
+    }
+};
+template <> struct Unit<ASYRK_F64> {
+    int c[4];
+    double v[4];
+    __device__ __forceinline__ void load(const uint8_t *p) {
+        const int4 ci = *reinterpret_cast<const int4 *>(p);
+        const double2 v0 = *reinterpret_cast<const double2 *>(p + 16);
+        const double2 v1 = *reinterpret_cast<const double2 *>(p + 32);
+        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
+        v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
+    }
+};
+
+template <int VK>
+__device__ __forceinline__ typename VT<VK>::hdr_t load_hdr(const uint8_t *rec) {
+    return *reinterpret_cast<const typename VT<VK>::hdr_t *>(rec);
+}
+
+// Entry `pos` of a row record (column, value), read directly.
+template <int VK>
+__device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
+                                           typename VT<VK>::x_t &v) {
+    using T = VT<VK>;
+    const uint8_t *u = rec + T::HB + (int64_t)(pos / T::U) * T::UB;
+    const int e = pos % T::U;
+    c = *reinterpret_cast<const int *>(u + 4 * e);
+    if constexpr (VK == ASYRK_BF16)
+        v = bf16_to_f32(*reinterpret_cast<const uint16_t *>(u + T::COLB + 2 * e));
+    else
+        v = *reinterpret_cast<const typename T::val_t *>(u + T::COLB + T::VB * e);
+}
+
+template <int G, class X>
+__device__ __forceinline__ X group_sum(X v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Units per lane kept in registers: a row of up to G * UPL units is read
+// once; longer rows are read twice (dot pass, then scatter pass).
+template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; };
+
+// ---------------------------------------------------------------- sweep
+
+// One ticket of one worker (a group of G lanes): draw the row, fetch its
+// record, gather-dot, step, atomic scatter.  XK: iterate dtype.  FP32 records
+// with an FP64 iterate read b_i and 1/w_i in FP64 from the side array (the
+// record header holds them in FP32).  Returns the read-to-write window in
+// clock ticks when `trace` is set.
+template <int VK, int XK, int G, int UPL = Upl<G>::value>
+__device__ __forceinline__ uint64_t process_ticket(
+    const Rows &rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
+    const double2 *side, int64_t j, uint32_t stream_id, uint32_t k0, uint32_t k1, int uniform,
+    int update_one, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl,
+    int trace) {
+    using T = VT<VK>;
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    using H = typename T::hdr_t;
+    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
+    constexpr int U = T::U;
+
+    // a1: ticket -> bucket -> row (alias decision needs the header)
+    const U4 u = draw(j, stream_id, k0, k1);
+    uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+    const uint8_t *rec;
+    int nnz;
+    locate(rows, i, rec, nnz);
+    H h = load_hdr<VK>(rec);
+    int nunits = (nnz + U - 1) / U;
+    // a2: speculative fetch of the bucket row's units (the alias is rarely taken)
+    Unit<VK> un[UPL];
+#pragma unroll
+    for (int q = 0; q < UPL; ++q) {
+        const int uu = gl + q * G;
+        if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+    }
+    if (!uniform && !(u.c < h.thresh)) {
+        i = (uint32_t)h.alias;
+        locate(rows, i, rec, nnz);
+        h = load_hdr<VK>(rec);
+        nunits = (nnz + U - 1) / U;
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int uu = gl + q * G;
+            if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+        }
+    }
+
+    uint64_t t0 = 0;
+    if (trace) t0 = wall_clock64();
+
+    // a3: gather-dot over supp(a_i)
+    X acc = (X)0;
+    const bool one_pass = nunits <= G * UPL;
+    if (one_pass) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int uu = gl + q * G;
+            if (uu < nunits) {
+#pragma unroll
+                for (int e = 0; e < U; ++e) {
+                    if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                }
+            }
+        }
+    } else {
+        for (int base = 0; base < nunits; base += G * UPL) {
+            if (base > 0) {
+#pragma unroll
+                for (int q = 0; q < UPL; ++q) {
+                    const int uu = base + gl + q * G;
+                    if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < UPL; ++q) {
+                const int uu = base + gl + q * G;
+                if (uu < nunits) {
+#pragma unroll
+                    for (int e = 0; e < U; ++e)
+                        if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                }
+            }
+        }
+    }
+    acc = group_sum<G>(acc);
+
+    // a4: step s = gamma * (a_i^T x - b_i) / ||a_i||^2
+    X bi, inv_w;
+    if constexpr (SIDE) {
+        const double2 sd = side[i];
+        bi = sd.x;
+        inv_w = sd.y;
+    } else {
+        bi = (X)h.b;
+        inv_w = (X)h.inv_w;
+    }
+    const X r = acc - bi;
+
+    // a5: lock-free scatter
+    if (!update_one) {
+        const X s = gamma * r * inv_w;
+        if (one_pass) {
+#pragma unroll
+            for (int q = 0; q < UPL; ++q) {
+                const int uu = gl + q * G;
+                if (uu < nunits) {
+#pragma unroll
+                    for (int e = 0; e < U; ++e)
+                        if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                }
+            }
+        } else {
+            for (int base = 0; base < nunits; base += G * UPL) {
+#pragma unroll
+                for (int q = 0; q < UPL; ++q) {
+                    const int uu = base + gl + q * G;
+                    if (uu < nunits) {
+                        un[q].load(rec + T::HB + (int64_t)uu * T::UB);
+#pragma unroll
+                        for (int e = 0; e < U; ++e)
+                            if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                    }
+                }
+            }
+        }
+    } else if (gl == 0) {
+        // Algorithm 1: one coordinate t, step gamma * theta_i
+        const int t = (int)(((uint64_t)u.d * (uint64_t)nnz) >> 32);
+        int c;
+        typename VT<VK>::x_t v;
+        load_entry<VK>(rec, t, c, v);
+        const X s1 = gamma * (X)nnz * r * inv_w;
+        unsafeAtomicAdd(x + c, -s1 * (X)v);
+    }
+    return trace ? wall_clock64() - t0 : 0;
+}
+
+}  // namespace asyrk

@@ -12,113 +12,13 @@
 //     read sees every atomic already performed by any XCD, and written with
 //     no-return global_atomic_add_f32/f64; x (4-16 MB) lives in the caches;
 //   * no LDS and no MFMA: there is no dense contraction in this method.
-#include <type_traits>
-
-#include "internal.h"
+#include "device.h"
 
 namespace asyrk {
 
-// ---------------------------------------------------------------- utilities
-
-template <class T>
-__device__ __forceinline__ T load_agent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __uint_as_float(bits << 16); }
-
-__device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
-    if (r.loc == nullptr) {
-        rec = r.rec + (int64_t)i * r.stride;
-        nnz = r.fixed_nnz;
-    } else {
-        const RowLoc l = r.loc[i];
-        rec = r.rec + (int64_t)l.off16 * 16;
-        nnz = (int)l.nnz;
-    }
-}
-
-template <int VK> struct Unit;
-template <> struct Unit<ASYRK_F32> {
-    int c[4];
-    float v[4];
-    __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 ci = *reinterpret_cast<const int4 *>(p);
-        const float4 vi = *reinterpret_cast<const float4 *>(p + 16);
-        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
-        v[0] = vi.x; v[1] = vi.y; v[2] = vi.z; v[3] = vi.w;
-    }
-};
-template <> struct Unit<ASYRK_BF16> {
-    int c[8];
-    float v[8];
-    __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 c0 = *reinterpret_cast<const int4 *>(p);
-        const int4 c1 = *reinterpret_cast<const int4 *>(p + 16);
-        const uint4 vb = *reinterpret_cast<const uint4 *>(p + 32);
-        c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w;
-        c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
-        v[0] = bf16_to_f32(vb.x & 0xffffu); v[1] = bf16_to_f32(vb.x >> 16);
-        v[2] = bf16_to_f32(vb.y & 0xffffu); v[3] = bf16_to_f32(vb.y >> 16);
-        v[4] = bf16_to_f32(vb.z & 0xffffu); v[5] = bf16_to_f32(vb.z >> 16);
-        v[6] = bf16_to_f32(vb.w & 0xffffu); v[7] = bf16_to_f32(vb.w >> 16);
-    }
-};
-template <> struct Unit<ASYRK_F64> {
-    int c[4];
-    double v[4];
-    __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 ci = *reinterpret_cast<const int4 *>(p);
-        const double2 v0 = *reinterpret_cast<const double2 *>(p + 16);
-        const double2 v1 = *reinterpret_cast<const double2 *>(p + 32);
-        c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
-        v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
-    }
-};
-
-template <int VK>
-__device__ __forceinline__ typename VT<VK>::hdr_t load_hdr(const uint8_t *rec) {
-    return *reinterpret_cast<const typename VT<VK>::hdr_t *>(rec);
-}
-
-// Entry `pos` of a row record (column, value), read directly.
-template <int VK>
-__device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
-                                           typename VT<VK>::x_t &v) {
-    using T = VT<VK>;
-    const uint8_t *u = rec + T::HB + (int64_t)(pos / T::U) * T::UB;
-    const int e = pos % T::U;
-    c = *reinterpret_cast<const int *>(u + 4 * e);
-    if constexpr (VK == ASYRK_BF16)
-        v = bf16_to_f32(*reinterpret_cast<const uint16_t *>(u + T::COLB + 2 * e));
-    else
-        v = *reinterpret_cast<const typename T::val_t *>(u + T::COLB + T::VB * e);
-}
-
-template <int G, class X>
-__device__ __forceinline__ X group_sum(X v) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// Units per lane kept in registers: a row of up to G * UPL units is read
-// once; longer rows are read twice (dot pass, then scatter pass).
-template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; };
-
-// ---------------------------------------------------------------- sweep
-
-// XK: iterate dtype.  FP32 records with an FP64 iterate read b_i and 1/w_i
-// in FP64 from the side array (the record header holds them in FP32).
 template <int VK, int XK, int G>
 __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
-    using T = VT<VK>;
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
-    using H = typename T::hdr_t;
-    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
-    constexpr int U = T::U;
-    constexpr int UPL = Upl<G>::value;
-
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -128,127 +28,11 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     X *x = reinterpret_cast<X *>(a.x);
     const X gamma = (X)a.gamma;
     uint64_t tr_max = 0, tr_sum = 0, tr_cnt = 0;
-
     for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R) {
-        // a1: ticket -> bucket -> row (alias decision needs the header)
-        const U4 u = draw(j, a.stream_id, a.key0, a.key1);
-        uint32_t i = bucket_of(u.a, u.b, (uint32_t)a.rows.m);
-        const uint8_t *rec;
-        int nnz;
-        locate(a.rows, i, rec, nnz);
-        H h = load_hdr<VK>(rec);
-        int nunits = (nnz + U - 1) / U;
-        // a2: speculative fetch of bucket row's units (the alias is rarely taken)
-        Unit<VK> un[UPL];
-#pragma unroll
-        for (int q = 0; q < UPL; ++q) {
-            const int uu = gl + q * G;
-            if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
-        }
-        if (!a.uniform && !(u.c < h.thresh)) {
-            i = (uint32_t)h.alias;
-            locate(a.rows, i, rec, nnz);
-            h = load_hdr<VK>(rec);
-            nunits = (nnz + U - 1) / U;
-#pragma unroll
-            for (int q = 0; q < UPL; ++q) {
-                const int uu = gl + q * G;
-                if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
-            }
-        }
-
-        uint64_t t0 = 0;
-        if (a.trace) t0 = wall_clock64();
-
-        // a3: gather-dot over supp(a_i)
-        X acc = (X)0;
-        const bool one_pass = nunits <= G * UPL;
-        if (one_pass) {
-#pragma unroll
-            for (int q = 0; q < UPL; ++q) {
-                const int uu = gl + q * G;
-                if (uu < nunits) {
-#pragma unroll
-                    for (int e = 0; e < U; ++e) {
-                        if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
-                    }
-                }
-            }
-        } else {
-            for (int base = 0; base < nunits; base += G * UPL) {
-                if (base > 0) {
-#pragma unroll
-                    for (int q = 0; q < UPL; ++q) {
-                        const int uu = base + gl + q * G;
-                        if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < UPL; ++q) {
-                    const int uu = base + gl + q * G;
-                    if (uu < nunits) {
-#pragma unroll
-                        for (int e = 0; e < U; ++e)
-                            if (uu * U + e < nnz)
-                                acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
-                    }
-                }
-            }
-        }
-        acc = group_sum<G>(acc);
-
-        // a4: step s = gamma * (a_i^T x - b_i) / ||a_i||^2
-        X bi, inv_w;
-        if constexpr (SIDE) {
-            const double2 sd = a.side[i];
-            bi = sd.x;
-            inv_w = sd.y;
-        } else {
-            bi = (X)h.b;
-            inv_w = (X)h.inv_w;
-        }
-        const X r = acc - bi;
-
-        // a5: lock-free scatter
-        if (!a.update_one) {
-            const X s = gamma * r * inv_w;
-            if (one_pass) {
-#pragma unroll
-                for (int q = 0; q < UPL; ++q) {
-                    const int uu = gl + q * G;
-                    if (uu < nunits) {
-#pragma unroll
-                        for (int e = 0; e < U; ++e)
-                            if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
-                    }
-                }
-            } else {
-                for (int base = 0; base < nunits; base += G * UPL) {
-#pragma unroll
-                    for (int q = 0; q < UPL; ++q) {
-                        const int uu = base + gl + q * G;
-                        if (uu < nunits) {
-                            un[q].load(rec + T::HB + (int64_t)uu * T::UB);
-#pragma unroll
-                            for (int e = 0; e < U; ++e)
-                                if (uu * U + e < nnz)
-                                    unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
-                        }
-                    }
-                }
-            }
-        } else if (gl == 0) {
-            // Algorithm 1: one coordinate t, step gamma * theta_i
-            const int t = (int)(((uint64_t)u.d * (uint64_t)nnz) >> 32);
-            int c;
-            typename VT<VK>::x_t v;
-            load_entry<VK>(rec, t, c, v);
-            const X s1 = gamma * (X)nnz * r * inv_w;
-            unsafeAtomicAdd(x + c, -s1 * (X)v);
-        }
-
+        const uint64_t w = process_ticket<VK, XK, G>(a.rows, x, a.side, j, a.stream_id, a.key0, a.key1,
+                                                     a.uniform, a.update_one, gamma, gl,
+                                                     a.trace != nullptr);
         if (a.trace) {
-            const uint64_t w = wall_clock64() - t0;
             tr_max = w > tr_max ? w : tr_max;
             tr_sum += w;
             tr_cnt += 1;

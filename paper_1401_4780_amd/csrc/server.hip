@@ -1,0 +1,579 @@
+// Serving engine: many independent consistent systems solved concurrently on
+// one GPU with continuous batching.
+//
+//   submit()   (any thread)  validate + pack a request on the caller's thread,
+//                            queue it.
+//   progress() (one thread)  one round:
+//       retire  requests whose FP64 relative residual met their tolerance
+//               (or whose round budget ran out): copy x out, free its memory;
+//       admit   queued requests while a slot, the worker budget and the
+//               device-memory budget allow (first-fit arena: no device
+//               allocation or free in the loop);
+//       run     one packed launch per phase over every active system:
+//               zero d -> FP32 asynchronous sweeps on A d = fp32(r) ->
+//               x += d (FP64) -> r = b - A x (FP64, also written as the next
+//               round's FP32 right-hand side) -> per-system ||r||^2.
+//               The four launches are captured once in a hipGraph (fixed
+//               grids; kernels read the device slot table).
+//   poll()     (any thread)  fetch a finished request's x and statistics.
+//
+// Each system runs R_s row workers with R_s bounded by its own Corollary 1
+// limit (tau + 1 <= ||A||_F^2 / (2 e lambda)), so small systems take few
+// workers and the GPU is filled by packing many systems into one launch.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "device.h"
+#include "setup.h"
+
+using namespace asyrk;
+
+namespace {
+
+constexpr int kSrvG = 8;             // lanes per row in the packed sweep; 2 units per lane keep
+                                     // rows of up to 64 FP32 entries in registers
+constexpr int kVecBlocks = 2048;     // grid of the flat vector/residual kernels
+
+struct SlotDesc {
+    Rows rows;
+    double *b64;
+    double *x64;
+    float *d;
+    int64_t n;
+    int64_t R;        // row workers of this system
+    int64_t w_off;    // first global worker
+    int64_t row_off;  // first global row
+    int64_t col_off;  // first global column
+    int64_t t_begin, t_end;
+    uint32_t key0, key1;
+    float gamma;
+    int32_t pad;
+};
+
+struct TableHead {
+    int32_t nact;
+    int32_t pad;
+    int64_t total_workers, total_rows, total_cols;
+};
+
+// binary search: last slot s with off(s) <= q
+template <class F>
+__device__ __forceinline__ int find_slot(int nact, int64_t q, F off) {
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off(mid) <= q)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, const SlotDesc *sl, double *norm2) {
+    const int nact = th->nact;
+    const int64_t total = th->total_cols;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < nact) norm2[tid] = 0.0;
+    for (int64_t q = tid; q < total; q += stride) {
+        const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
+        sl[s].d[q - sl[s].col_off] = 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void srv_sweep_kernel(const TableHead *th, const SlotDesc *sl) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kSrvG - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / kSrvG) + (lane / kSrvG);
+    if (worker >= th->total_workers) return;
+    const int s = find_slot(th->nact, worker, [&](int k) { return sl[k].w_off; });
+    const SlotDesc &d = sl[s];
+    const int64_t w = worker - d.w_off;
+    for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
+        process_ticket<ASYRK_F32, ASYRK_F32, kSrvG, 2>(d.rows, d.d, nullptr, j, 0u, d.key0, d.key1, 0, 0,
+                                                       d.gamma, gl, 0);
+}
+
+__global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, const SlotDesc *sl) {
+    const int nact = th->nact;
+    const int64_t total = th->total_cols;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+        const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
+        const int64_t c = q - sl[s].col_off;
+        sl[s].x64[c] += (double)sl[s].d[c];
+    }
+}
+
+// r = b - A x64 in FP64 (4 lanes per row); fp32(r) becomes the record's b for
+// the next round; ||r||^2 accumulates per system.
+__global__ __launch_bounds__(256) void srv_residual_kernel(const TableHead *th, const SlotDesc *sl, double *norm2) {
+    using T = VT<ASYRK_F32>;
+    constexpr int G = 4;
+    const int nact = th->nact;
+    const int64_t total = th->total_rows;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
+    for (int64_t q = grp; q < total; q += ngrp) {
+        const int s = find_slot(nact, q, [&](int k) { return sl[k].row_off; });
+        const SlotDesc &d = sl[s];
+        const int64_t i = q - d.row_off;
+        const uint8_t *rec;
+        int nnz;
+        locate(d.rows, (uint32_t)i, rec, nnz);
+        const int nunits = (nnz + T::U - 1) / T::U;
+        double acc = 0.0;
+        for (int uu = gl; uu < nunits; uu += G) {
+            Unit<ASYRK_F32> un;
+            un.load(rec + T::HB + (int64_t)uu * T::UB);
+#pragma unroll
+            for (int e = 0; e < T::U; ++e)
+                if (uu * T::U + e < nnz) acc = fma((double)un.v[e], d.x64[un.c[e]], acc);
+        }
+        acc = group_sum<G>(acc);
+        const double r = d.b64[i] - acc;
+        if (gl == 0) {
+            reinterpret_cast<HdrF32 *>(const_cast<uint8_t *>(rec))->b = (float)r;
+            unsafeAtomicAdd(norm2 + s, r * r);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- arena
+
+struct Arena {
+    uint8_t *base = nullptr;
+    int64_t size = 0, used = 0;
+    std::map<int64_t, int64_t> free_;  // offset -> length
+
+    static int64_t round_up(int64_t b) { return (b + 255) / 256 * 256; }
+    int64_t alloc(int64_t bytes) {
+        bytes = round_up(std::max<int64_t>(bytes, 256));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                used += bytes;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = round_up(std::max<int64_t>(bytes, 256));
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Request {
+    int64_t id = 0;
+    int64_t m = 0, n = 0, nnz = 0;
+    double tol = 1e-8, b_norm2 = 0.0, fro2 = 0.0, lam = 0.0;
+    uint64_t seed = 0;
+    SetupResult pack;
+    std::vector<double> b64;
+    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+    // active state
+    int slot = -1;
+    int64_t R = 1;
+    int64_t off_rec = -1, off_loc = -1, off_b = -1, off_x = -1, off_d = -1;
+    int64_t bytes = 0;
+    int64_t ticket = 0;
+    int32_t rounds = 0;
+    int64_t sweeps = 0;
+    double rel = 1.0;
+    int32_t status = ASYRK_OK;
+    std::vector<double> x;  // result
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct asyrk_server {
+    asyrk_server_config cfg{};
+    hipStream_t st = nullptr;
+    Arena arena;
+    TableHead *d_head = nullptr;
+    SlotDesc *d_slots = nullptr;
+    double *d_norm2 = nullptr;
+    TableHead *h_head = nullptr;   // pinned
+    SlotDesc *h_slots = nullptr;   // pinned
+    double *h_norm2 = nullptr;     // pinned
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int sweep_blocks = 0;
+
+    std::mutex mu;
+    std::deque<std::unique_ptr<Request>> queue;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> done;
+    std::unordered_set<int64_t> live;  // submitted and not yet polled
+    int64_t next_id = 1;
+
+    std::vector<std::unique_ptr<Request>> active;  // progress() thread only
+    int64_t workers_in_use = 0;
+    asyrk_server_stats stats{};
+};
+
+namespace {
+
+thread_local const char *g_srv_last = "";
+
+asyrk_status srv_fail(hipError_t e) {
+    g_srv_last = hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? ASYRK_ERR_OOM : ASYRK_ERR_DEVICE;
+}
+
+#define SRV_OK(expr)                                  \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return srv_fail(_e);    \
+    } while (0)
+
+int64_t request_bytes(const Request &r) {
+    return Arena::round_up((int64_t)r.pack.rec.size()) + Arena::round_up((int64_t)r.pack.loc.size() * 8) +
+           Arena::round_up(r.m * 8) + Arena::round_up(r.n * 8) + Arena::round_up(r.n * 4) + 5 * 256;
+}
+
+hipError_t launch_round(asyrk_server *s, hipStream_t st) {
+    const int wblocks = kVecBlocks;
+    hipLaunchKernelGGL(srv_zero_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+    hipLaunchKernelGGL(srv_sweep_kernel, dim3(s->sweep_blocks), dim3(256), 0, st, s->d_head, s->d_slots);
+    hipLaunchKernelGGL(srv_axpy_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots);
+    hipLaunchKernelGGL(srv_residual_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+    return hipGetLastError();
+}
+
+void free_server(asyrk_server *s) {
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    (void)hipFree(s->arena.base);
+    (void)hipFree(s->d_head);
+    (void)hipFree(s->d_slots);
+    (void)hipFree(s->d_norm2);
+    if (s->h_head) (void)hipHostFree(s->h_head);
+    if (s->h_slots) (void)hipHostFree(s->h_slots);
+    if (s->h_norm2) (void)hipHostFree(s->h_norm2);
+    if (s->e0) (void)hipEventDestroy(s->e0);
+    if (s->e1) (void)hipEventDestroy(s->e1);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void asyrk_server_config_init(asyrk_server_config *c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->budget_bytes = (int64_t)64 << 30;
+    c->max_slots = 1024;
+    c->max_workers = (int64_t)1 << 16;
+    c->inner_sweeps = 10;
+    c->max_rounds = 60;
+    c->gamma = 1.0;
+    c->use_graph = 1;
+}
+
+asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
+    if (!out) return ASYRK_ERR_INVALID_ARG;
+    *out = nullptr;
+    asyrk_server_config cfg;
+    if (cfg_in)
+        cfg = *cfg_in;
+    else
+        asyrk_server_config_init(&cfg);
+    if (cfg.budget_bytes < (1 << 20) || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
+        cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
+        !(cfg.gamma > 0.0 && cfg.gamma < 2.0))
+        return ASYRK_ERR_INVALID_ARG;
+    asyrk_server *s = new (std::nothrow) asyrk_server();
+    if (!s) return ASYRK_ERR_OOM;
+    s->cfg = cfg;
+    hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->arena.base, (size_t)cfg.budget_bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_head, sizeof(TableHead));
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_slots, sizeof(SlotDesc) * cfg.max_slots);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->d_norm2, sizeof(double) * cfg.max_slots);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_head, sizeof(TableHead), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_slots, sizeof(SlotDesc) * cfg.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_norm2, sizeof(double) * cfg.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&s->e0);
+    if (e == hipSuccess) e = hipEventCreate(&s->e1);
+    if (e != hipSuccess) {
+        free_server(s);
+        return srv_fail(e);
+    }
+    s->arena.size = cfg.budget_bytes;
+    s->arena.free_[0] = cfg.budget_bytes;
+    s->sweep_blocks = (int)((cfg.max_workers * kSrvG + 255) / 256);
+    std::memset(s->h_head, 0, sizeof(TableHead));
+    if (cfg.use_graph) {
+        // capture the four phases once; they read the slot table, so the same
+        // graph serves every round whatever systems are active
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_round(s, s->st);
+            e = hipStreamEndCapture(s->st, &g);
+            if (e == hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            free_server(s);
+            return srv_fail(e);
+        }
+    }
+    *out = s;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_destroy(asyrk_server *s) {
+    free_server(s);
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const int64_t *row_ptr,
+                                 const int32_t *col_idx, const float *vals, const double *b, double tol,
+                                 uint64_t seed, int64_t *request_id) {
+    if (!s || !request_id || !(tol > 0.0) || !std::isfinite(tol)) return ASYRK_ERR_INVALID_ARG;
+    auto r = std::unique_ptr<Request>(new (std::nothrow) Request());
+    if (!r) return ASYRK_ERR_OOM;
+    asyrk_status rc = validate_system(m, n, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack);
+    if (rc) return rc;
+    rc = pack_records(m, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack);
+    if (rc) return rc;
+    r->m = m;
+    r->n = n;
+    r->nnz = r->pack.nnz;
+    r->tol = tol;
+    r->seed = seed;
+    r->b64.assign(b, b + m);
+    double bn = 0.0;
+    for (int64_t i = 0; i < m; ++i) bn += b[i] * b[i];
+    r->b_norm2 = bn;
+    r->fro2 = r->pack.fro2;
+    const double q = std::sqrt((double)n / (double)m);
+    r->lam = std::max((1.0 + q) * (1.0 + q) * r->fro2 / (double)n, r->pack.max_col_norm2);
+    r->bytes = request_bytes(*r);
+    if (r->bytes > s->cfg.budget_bytes) return ASYRK_ERR_OOM;
+    r->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    *request_id = r->id;
+    s->live.insert(r->id);
+    s->queue.push_back(std::move(r));
+    s->stats.submitted++;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
+    if (!s) return ASYRK_ERR_INVALID_ARG;
+    const asyrk_server_config &cfg = s->cfg;
+    // ---- admit
+    for (;;) {
+        std::unique_ptr<Request> r;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->queue.empty() || (int)s->active.size() >= cfg.max_slots) break;
+            Request &f = *s->queue.front();
+            int64_t R = (int64_t)std::floor(f.fro2 / (2.0 * M_E * f.lam));
+            R = std::max<int64_t>(1, std::min<int64_t>(R, cfg.max_workers / 4));
+            if (s->workers_in_use + R > cfg.max_workers) break;
+            f.R = R;
+            const int64_t off = s->arena.alloc(f.bytes);
+            if (off < 0) break;  // wait for memory
+            r = std::move(s->queue.front());
+            s->queue.pop_front();
+            r->off_rec = off;
+        }
+        Request &q = *r;
+        int64_t o = q.off_rec + Arena::round_up((int64_t)q.pack.rec.size());
+        q.off_loc = o;
+        o += Arena::round_up((int64_t)q.pack.loc.size() * 8);
+        q.off_b = o;
+        o += Arena::round_up(q.m * 8);
+        q.off_x = o;
+        o += Arena::round_up(q.n * 8);
+        q.off_d = o;
+        uint8_t *base = s->arena.base;
+        SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.pack.rec.size(), hipMemcpyHostToDevice, s->st));
+        if (!q.pack.loc.empty())
+            SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8, hipMemcpyHostToDevice,
+                                  s->st));
+        SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->st));
+        SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->st));
+        q.t_admit = now_s();
+        q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
+        s->workers_in_use += q.R;
+        s->active.push_back(std::move(r));
+        s->stats.admitted++;
+    }
+    if (s->active.empty()) {
+        if (n_active) *n_active = 0;
+        if (n_queued) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            *n_queued = (int32_t)s->queue.size();
+        }
+        return ASYRK_OK;
+    }
+    // ---- slot table
+    TableHead &h = *s->h_head;
+    h.nact = (int32_t)s->active.size();
+    int64_t wo = 0, ro = 0, co = 0;
+    uint8_t *base = s->arena.base;
+    for (int k = 0; k < h.nact; ++k) {
+        Request &q = *s->active[k];
+        SlotDesc &d = s->h_slots[k];
+        d.rows.rec = base + q.off_rec;
+        d.rows.loc = q.pack.loc.empty() ? nullptr : reinterpret_cast<const RowLoc *>(base + q.off_loc);
+        d.rows.stride = q.pack.stride;
+        d.rows.fixed_nnz = (int32_t)q.pack.fixed_nnz;
+        d.rows.m = (int32_t)q.m;
+        d.b64 = reinterpret_cast<double *>(base + q.off_b);
+        d.x64 = reinterpret_cast<double *>(base + q.off_x);
+        d.d = reinterpret_cast<float *>(base + q.off_d);
+        d.n = q.n;
+        d.R = q.R;
+        d.w_off = wo;
+        d.row_off = ro;
+        d.col_off = co;
+        d.t_begin = q.ticket;
+        d.t_end = q.ticket + (int64_t)cfg.inner_sweeps * q.m;
+        d.key0 = (uint32_t)q.seed;
+        d.key1 = (uint32_t)(q.seed >> 32);
+        d.gamma = (float)cfg.gamma;
+        wo += q.R;
+        ro += q.m;
+        co += q.n;
+    }
+    h.total_workers = wo;
+    h.total_rows = ro;
+    h.total_cols = co;
+    SRV_OK(hipMemcpyAsync(s->d_head, s->h_head, sizeof(TableHead), hipMemcpyHostToDevice, s->st));
+    SRV_OK(hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(SlotDesc) * h.nact, hipMemcpyHostToDevice, s->st));
+    // ---- run one round
+    SRV_OK(hipEventRecord(s->e0, s->st));
+    if (s->graph)
+        SRV_OK(hipGraphLaunch(s->graph, s->st));
+    else
+        SRV_OK(launch_round(s, s->st));
+    SRV_OK(hipEventRecord(s->e1, s->st));
+    SRV_OK(hipMemcpyAsync(s->h_norm2, s->d_norm2, sizeof(double) * h.nact, hipMemcpyDeviceToHost, s->st));
+    SRV_OK(hipStreamSynchronize(s->st));
+    float ms = 0.f;
+    SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
+    s->stats.gpu_seconds += ms * 1e-3;
+    s->stats.rounds++;
+    // ---- bookkeeping and retirement
+    std::vector<std::unique_ptr<Request>> keep;
+    for (int k = 0; k < h.nact; ++k) {
+        std::unique_ptr<Request> &r = s->active[k];
+        r->ticket += (int64_t)cfg.inner_sweeps * r->m;
+        r->sweeps += cfg.inner_sweeps;
+        r->rounds++;
+        s->stats.row_updates += (int64_t)cfg.inner_sweeps * r->m;
+        const double nr = s->h_norm2[k];
+        r->rel = r->b_norm2 > 0 ? std::sqrt(nr / r->b_norm2) : std::sqrt(nr);
+        const bool conv = r->rel <= r->tol;
+        const bool bad = !std::isfinite(r->rel);
+        if (conv || bad || r->rounds >= cfg.max_rounds) {
+            r->status = conv ? ASYRK_OK : (bad ? ASYRK_ERR_DIVERGED : ASYRK_ERR_NOT_CONVERGED);
+            r->x.resize(r->n);
+            SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, s->st));
+            SRV_OK(hipStreamSynchronize(s->st));
+            r->t_done = now_s();
+            s->workers_in_use -= r->R;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->arena.release(r->off_rec, r->bytes);
+            r->pack = SetupResult();  // drop the packed copy
+            s->stats.completed++;
+            s->done[r->id] = std::move(r);
+        } else {
+            keep.push_back(std::move(r));
+        }
+    }
+    s->active.swap(keep);
+    if (n_active) *n_active = (int32_t)s->active.size();
+    if (n_queued) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        *n_queued = (int32_t)s->queue.size();
+    }
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_poll(asyrk_server *s, int64_t request_id, double *x_out, asyrk_request_stats *st) {
+    if (!s) return ASYRK_ERR_INVALID_ARG;
+    std::unique_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->done.find(request_id);
+        if (it == s->done.end()) return s->live.count(request_id) ? ASYRK_PENDING : ASYRK_ERR_INVALID_ARG;
+        r = std::move(it->second);
+        s->done.erase(it);
+        s->live.erase(request_id);
+    }
+    if (x_out) std::memcpy(x_out, r->x.data(), r->n * 8);
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->m = r->m;
+        st->n = r->n;
+        st->nnz = r->nnz;
+        st->rounds = r->rounds;
+        st->in_flight = r->R;
+        st->sweeps = r->sweeps;
+        st->rel_residual = r->rel;
+        st->t_submit = r->t_submit;
+        st->t_admit = r->t_admit;
+        st->t_done = r->t_done;
+        st->status = r->status;
+    }
+    return (asyrk_status)r->status;
+}
+
+asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out) {
+    if (!s || !out) return ASYRK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->active = (int64_t)s->active.size();
+    out->queued = (int64_t)s->queue.size();
+    out->arena_used = s->arena.used;
+    return ASYRK_OK;
+}
+
+double asyrk_now(void) { return now_s(); }
+
+}  // extern "C"

@@ -104,8 +104,14 @@ asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const
     out.mu = 0;
     for (int t = 0; t < tix; ++t) out.mu = std::max(out.mu, mu_t[t]);
     std::vector<int32_t> cnt(n, 0);
-    for (int64_t k = 0; k < nnz; ++k) cnt[col[k]]++;
+    std::vector<double> cn2(n, 0.0);
+    for (int64_t k = 0; k < nnz; ++k) {
+        const double v = promote(vals, vk, k);
+        cnt[col[k]]++;
+        cn2[col[k]] += v * v;
+    }
     out.nu = *std::max_element(cnt.begin(), cnt.end());
+    out.max_col_norm2 = *std::max_element(cn2.begin(), cn2.end());
     out.fixed_nnz = row_ptr[1] - row_ptr[0];
     for (int64_t i = 1; i < m && out.fixed_nnz > 0; ++i)
         if (row_ptr[i + 1] - row_ptr[i] != out.fixed_nnz) out.fixed_nnz = 0;

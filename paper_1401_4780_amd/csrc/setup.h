@@ -17,6 +17,7 @@ struct SetupResult {
     int64_t nu = 0;            // max column count
     int64_t fixed_nnz = 0;     // common row length or 0
     double fro2 = 0.0;         // sum of w
+    double max_col_norm2 = 0.0;  // max_j ||column j||^2
     int64_t stride = 0;        // record stride (fixed rows)
     std::vector<RowLoc> loc;   // per-row locators (rows of different length)
     std::vector<uint8_t> rec;  // packed records

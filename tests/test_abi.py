@@ -45,7 +45,10 @@ def _c_layout(struct, fields):
 
 @pytest.mark.parametrize("cname,pycls", [("asyrk_solve_params", P.SolveParams),
                                          ("asyrk_solve_stats", P.SolveStats),
-                                         ("asyrk_system_info", P.SystemInfo)])
+                                         ("asyrk_system_info", P.SystemInfo),
+                                         ("asyrk_server_config", P.ServerConfig),
+                                         ("asyrk_request_stats", P.RequestStats),
+                                         ("asyrk_server_stats", P.ServerStats)])
 def test_struct_layouts_match_binding(cname, pycls):
     fields = [f for f, _ in pycls._fields_]
     lay = _c_layout(cname, fields)
@@ -55,7 +58,7 @@ def test_struct_layouts_match_binding(cname, pycls):
 
 def test_status_strings_and_defaults():
     L = P.lib()
-    for code in range(9):
+    for code in range(10):
         assert L.asyrk_status_string(code)
     p = P.SolveParams()
     L.asyrk_solve_params_init(C.byref(p))
@@ -142,6 +145,23 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_lambda_max(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_destroy(None)] == "OK"
     assert P.STATUS[L.asyrk_probe_copy(0, 1, C.byref(v))] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_server_create(None, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_server_progress(None, None, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_server_poll(None, 1, None, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_server_destroy(None)] == "OK"
+
+
+def test_server_config_validation():
+    L = P.lib()
+    c = P.ServerConfig()
+    L.asyrk_server_config_init(C.byref(c))
+    assert c.budget_bytes == 64 << 30 and c.use_graph == 1 and c.max_workers == 65536
+    for field, bad in (("gamma", 2.0), ("max_slots", 0), ("inner_sweeps", 0), ("budget_bytes", 10)):
+        d = P.ServerConfig()
+        L.asyrk_server_config_init(C.byref(d))
+        setattr(d, field, bad)
+        h = C.c_void_p()
+        assert P.STATUS[L.asyrk_server_create(C.byref(h), C.byref(d))] == "INVALID_ARG"
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -1,0 +1,125 @@
+"""Serving engine on the GPU: continuous batching of independent systems.
+
+Each result is checked against the FP64 residual of its own system (tolerance
+1e-8 relative, computed here on the CPU with scipy) and against its exact x*
+(error bound kappa * tol with kappa ~ 3 for m = 4n, checked at 1e-7).  The
+same system solved alone and inside a mix agrees within twice that bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_1401_4780_amd as P
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _systems(ids, sizes):
+    return [synth.serving_system(rid, m, m // 4) for rid, m in zip(ids, sizes)]
+
+
+def _rel_res(s, x):
+    A = sp.csr_matrix((s.val64, s.col, s.row_ptr), shape=(s.m, s.n))
+    return np.linalg.norm(s.b - A @ x) / np.linalg.norm(s.b)
+
+
+def _run_all(srv, systems, seeds=None, max_rounds=400):
+    ids = [srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL,
+                      seed=(seeds[k] if seeds else k)) for k, s in enumerate(systems)]
+    out = {}
+    for _ in range(max_rounds):
+        srv.progress()
+        for k, rid in enumerate(ids):
+            if k in out:
+                continue
+            r = srv.poll(rid, n=systems[k].n)
+            if r is not None:
+                out[k] = r
+        if len(out) == len(ids):
+            break
+    assert len(out) == len(ids), "server did not drain"
+    return [out[k] for k in range(len(ids))]
+
+
+def _check(s, res):
+    status, st, x = res
+    assert status == "OK", st
+    assert st["rel_residual"] <= TOL
+    assert _rel_res(s, x) <= 1.05 * TOL  # the FP64 residual of the returned x
+    assert np.linalg.norm(x - s.x_star) <= 1e-7 * np.linalg.norm(s.x_star)
+    assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_server_solves_a_mixed_stream(use_graph):
+    _say(f"server mixed stream graph={use_graph}")
+    sizes = [1000, 1500, 4000, 12000, 30000, 2000, 800, 60000, 5000, 1000]
+    systems = _systems(range(100, 110), sizes)
+    with P.Server(budget_bytes=1 << 30, use_graph=use_graph) as srv:
+        res = _run_all(srv, systems)
+        for s, r in zip(systems, res):
+            _check(s, r)
+        st = srv.stats()
+        assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
+
+
+def test_result_alone_equals_result_in_mix():
+    _say("server alone vs mix")
+    target = synth.serving_system(7, 20000, 5000)
+    others = _systems(range(200, 215), [3000 + 1000 * k for k in range(15)])
+    with P.Server(budget_bytes=1 << 30) as srv:
+        alone = _run_all(srv, [target], seeds=[42])[0]
+    with P.Server(budget_bytes=1 << 30) as srv:
+        mixed = _run_all(srv, others[:7] + [target] + others[7:],
+                         seeds=list(range(7)) + [42] + list(range(7, 15)))
+    _check(target, alone)
+    for s, r in zip(others[:7] + [target] + others[7:], mixed):
+        _check(s, r)
+    xa, xm = alone[2], mixed[7][2]
+    assert np.linalg.norm(xa - xm) <= 2e-7 * np.linalg.norm(target.x_star)
+
+
+def test_budget_admission_and_continuous_batching():
+    """A budget that holds about two systems: the rest wait in the queue and
+    are admitted as memory frees up, while new requests keep arriving."""
+    _say("server budget admission")
+    systems = _systems(range(300, 310), [20000] * 10)
+    one = 20000 * (16 + 36 * 8) + 20000 * 16 + 5000 * 12  # about one system's footprint
+    with P.Server(budget_bytes=int(2.5 * one) + (1 << 20)) as srv:
+        ids = [srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
+               for k, s in enumerate(systems[:5])]
+        active, queued = srv.progress()
+        assert active <= 2 and queued >= 3
+        assert srv.poll(ids[-1], n=systems[4].n) is None  # still queued: pending
+        ids += [srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=5 + k)
+                for k, s in enumerate(systems[5:])]
+        out = {}
+        for _ in range(2000):
+            srv.progress()
+            for k, rid in enumerate(ids):
+                if k not in out:
+                    r = srv.poll(rid, n=systems[k].n)
+                    if r is not None:
+                        out[k] = r
+            if len(out) == len(ids):
+                break
+        assert len(out) == len(ids)
+        for k, s in enumerate(systems):
+            _check(s, out[k])
+        assert srv.stats()["arena_used"] == 0
+        with pytest.raises(P.AsyrkError):
+            srv.poll(ids[0])  # already collected
+        big = synth.serving_system(1, 200000, 50000)
+        with pytest.raises(P.AsyrkError) as ei:
+            srv.submit(big.row_ptr, big.col, big.val, big.b, n=big.n)
+        assert ei.value.name == "OOM"
