@@ -103,6 +103,11 @@ def run_c2(args):
     log(f"setup {setup_s:.1f}s stride={info['record_stride']} device_bytes={info['device_bytes']}")
     x_ref = d(s.x_star)
     x = torch.zeros(N, dtype=torch.float64, device=dev)
+    tuned = None
+    if args.lanes == 0:
+        best, rates = sysm.autotune(GAMMA, in_flight=args.in_flight)
+        tuned = {"best_lanes": best, "rows_per_s_by_lanes": rates}
+        log(f"autotune: G={best} {rates}")
 
     def solve(seed, R=args.in_flight):
         x.zero_()
@@ -156,6 +161,7 @@ def run_c2(args):
         "all_converged": ok,
         "final_err_max": max(st["final_err"] for st in sts),
         "kernel_rows_per_s": rows / kern_s,
+        "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
@@ -197,6 +203,13 @@ def run_c2(args):
                         iter_dtype="f64")
         result["f64_iterate"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
                                  "status": st["status"], "time_to_tol_s": time.perf_counter() - t1}
+        x.zero_()
+        t1 = time.perf_counter()
+        st = sysm.solve(x, GAMMA, BUDGET, 12, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
+                        order="slices")
+        result["slices_without_replacement"] = {
+            "sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"], "status": st["status"],
+            "time_to_tol_s": time.perf_counter() - t1}
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -112,8 +112,22 @@ typedef struct asyrk_solve_params {
                                 asyrk_solve_params_init) = the system's default (F64
                                 values: F64, else F32); ASYRK_F32 (F32/BF16 values only)
                                 or ASYRK_F64 (any values; FP64 atomics) */
-    int32_t reserved;        /* must be 0 */
+    int32_t order;           /* 0: each ticket draws its row (with replacement, default);
+                                1: the paper's experimental scheme: worker w owns rows
+                                [w L, (w+1) L), L = ceil(m / R), and visits each of
+                                them once per sweep in a keyed permutation (see
+                                "Slice permutation"); needs UPDATE_ALL and ticket0 a
+                                multiple of m */
 } asyrk_solve_params;
+
+/* Slice permutation (order = 1), for sweep s (= ticket / m) and worker w:
+ *   (u0,u1,u2,u3) = Philox4x32-10(counter = (s mod 2^32, s div 2^32, w, 0x5C4E3D2B), key = seed)
+ *   position k of the worker's L_w rows maps to start_w + P(k), where P walks
+ *   y = k through  y <- ((y ^ (y >> h)) * (u0 | 1) + u1) & mask,
+ *                  y <- ((y ^ (y >> h)) * (u2 | 1) + u3) & mask
+ *   (32-bit arithmetic; b = smallest width with 2^b >= L_w, mask = 2^b - 1,
+ *   h = (b + 1) / 2) until y < L_w.  REPLAY (one worker) visits all m rows in
+ *   that order each sweep. */
 
 typedef struct asyrk_solve_stats {
     int64_t sweeps_done;       /* sweeps (m tickets each) performed */
@@ -236,6 +250,18 @@ asyrk_status asyrk_sample_rows(asyrk_system *s, uint64_t seed, uint32_t stream_i
  */
 asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
                               double *tau_max_out);
+
+/*
+ * Autotuner: times one sweep (at least 2^21 tickets) from x = 0 for each
+ * lane-group width G in {1, 2, 4, 8, 16} on this system, at in_flight workers
+ * (0 = the default R) and the given iterate dtype (-1 = default), and keeps
+ * the fastest G for later solves with lanes = 0.  best_lanes (nullable)
+ * receives it; rows_per_s (nullable, double[5]) the rate of each candidate.
+ * The system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,
+ * DEVICE.
+ */
+asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
+                            int32_t *best_lanes, double *rows_per_s);
 
 /*
  * Device ceilings used to read the roofline (no system needed):

@@ -64,7 +64,9 @@ def _load():
     lib.orc_residual.argtypes = [i64, P, P, P, P, P, P]
     lib.orc_residual.restype = f64
     lib.orc_rk_run.argtypes = [i64, i64, P, P, P, P, P, f64, u64, u32, i32, i32, i64, i64, i64,
-                               i64, P, P, P, P]
+                               i64, P, P, P, P, i32, i64]
+    lib.orc_slice_order.argtypes = [i64, i64, u64, i64, P]
+    lib.orc_slice_order.restype = i32
     lib.orc_rk_run.restype = i32
     lib.orc_rk_apply_rows.argtypes = [i64, i64, P, P, P, P, P, f64, P, P, i64]
     lib.orc_rk_apply_rows.restype = i32
@@ -146,8 +148,17 @@ def residual(row_ptr, col, val, b, x, want_r=False):
     return (n2, r) if want_r else n2
 
 
+def slice_order(m, workers, seed, sweep) -> np.ndarray:
+    """Row order of sweep ``sweep`` in the slice scheme with ``workers`` slices."""
+    lib = _load()
+    out = np.zeros(m, dtype=np.int32)
+    _check(lib.orc_slice_order(m, workers, seed, sweep, _p(out)))
+    return out
+
+
 def rk_run(row_ptr, col, val, b, n, x0, gamma, nsteps, seed, *, stream=0, uniform=False,
-           update_one=False, tau=0, ticket0=0, curve_every=0, x_ref=None, want_rows=False):
+           update_one=False, tau=0, ticket0=0, curve_every=0, x_ref=None, want_rows=False,
+           slices=False, workers=1):
     """Sequential RK (eq. (2) with step length gamma) for ``nsteps`` tickets.
 
     Returns a dict with ``x`` and, as requested, ``err`` (||x-x_ref||/||x_ref||),
@@ -168,7 +179,8 @@ def rk_run(row_ptr, col, val, b, n, x0, gamma, nsteps, seed, *, stream=0, unifor
     xr = None if x_ref is None else _c(x_ref, np.float64)
     rc = lib.orc_rk_run(m, n, _p(rp), _p(cl), _p(v), _p(bb), _p(x), float(gamma), seed, stream,
                         int(uniform), int(update_one), int(tau), int(ticket0), int(nsteps),
-                        int(curve_every), _p(xr), _p(err), _p(res), _p(rows))
+                        int(curve_every), _p(xr), _p(err), _p(res), _p(rows), int(slices),
+                        int(workers))
     _check(rc)
     out = {"x": x}
     if err is not None:

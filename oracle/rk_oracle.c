@@ -25,6 +25,8 @@
  *                       single-coordinate update of Algorithm 1; optional
  *                       forced read delay tau (the model k(j) >= j - tau of
  *                       eq. (3)), reading x_{j-tau} and writing x_j.
+ *   orc_slice_order     one sweep's row order in the paper's experimental
+ *                       scheme (row slices per worker, reshuffled each scan).
  *   orc_residual        ||b - A x||^2, sequential.
  *
  * Parity status of each function is stated on it.
@@ -200,6 +202,73 @@ int orc_sample_rows(int64_t m, uint64_t seed, uint32_t stream, const uint64_t *t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Row order of one sweep of the paper's experimental scheme (Section
+ * "Experiments": equal row slices per thread, each slice visited in order,
+ * the order reshuffled after each scan).  Worker w of R owns rows
+ * [w L, min(m, (w+1) L)), L = ceil(m / R).  Its permutation for sweep s:
+ * u = Philox(counter (s lo, s hi, w, 0x5C4E3D2B), key = seed); b = smallest
+ * width with 2^b >= L_w, mask = 2^b - 1, h = (b + 1) / 2; position k goes
+ * through  y = ((y ^ (y >> h)) * (u0 | 1) + u1) & mask,
+ *          y = ((y ^ (y >> h)) * (u2 | 1) + u3) & mask
+ * (32-bit wrapping arithmetic) until y < L_w.  The R workers are serialized
+ * round-robin: position k of every worker before position k + 1.  Pinned by:
+ * every sweep is a permutation of the rows, every slice's rows stay in their
+ * slice, and the slice scheme converges to the same limit
+ * (tests/test_oracle_slices.py).                                           */
+static uint32_t orc_slice_perm(uint32_t k, uint32_t len, const uint32_t *u)
+{
+    uint32_t width = 0, mask, half, y = k;
+    if (len <= 1)
+        return 0;
+    while (width < 32 && ((uint64_t)1 << width) < (uint64_t)len)
+        ++width;
+    mask = width >= 32 ? 0xffffffffu : (uint32_t)(((uint64_t)1 << width) - 1u);
+    half = (width + 1) / 2;
+    do {
+        y = ((y ^ (y >> half)) * (u[0] | 1u) + u[1]) & mask;
+        y = ((y ^ (y >> half)) * (u[2] | 1u) + u[3]) & mask;
+    } while (y >= len);
+    return y;
+}
+
+int orc_slice_order(int64_t m, int64_t workers, uint64_t seed, int64_t sweep, int32_t *rows_out)
+{
+    int64_t L, w, k, q = 0, kmax;
+    uint32_t key[2];
+    uint32_t *u;
+    if (m <= 0 || workers <= 0)
+        return ORC_ERR_ARG;
+    L = (m + workers - 1) / workers;
+    key[0] = (uint32_t)(seed & 0xffffffffull);
+    key[1] = (uint32_t)(seed >> 32);
+    u = (uint32_t *)malloc((size_t)workers * 4 * sizeof(uint32_t));
+    if (!u)
+        return ORC_ERR_NOMEM;
+    for (w = 0; w < workers; ++w) {
+        uint32_t ctr[4];
+        ctr[0] = (uint32_t)((uint64_t)sweep & 0xffffffffull);
+        ctr[1] = (uint32_t)((uint64_t)sweep >> 32);
+        ctr[2] = (uint32_t)w;
+        ctr[3] = 0x5C4E3D2Bu;
+        orc_philox4x32_10(ctr, key, u + 4 * w);
+    }
+    kmax = L;
+    for (k = 0; k < kmax; ++k) {
+        for (w = 0; w < workers; ++w) {
+            int64_t start = w * L, len;
+            if (start >= m)
+                continue;
+            len = (m - start < L) ? m - start : L;
+            if (k >= len)
+                continue;
+            rows_out[q++] = (int32_t)(start + orc_slice_perm((uint32_t)k, (uint32_t)len, u + 4 * w));
+        }
+    }
+    free(u);
+    return q == m ? ORC_OK : ORC_ERR_ARG;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ||b - A x||^2 with r_i = b_i - sum_k v_k x_{c_k} (CSR order), summed over i
  * in order.  r_out may be NULL.  Pinned against scipy's sparse product.     */
 double orc_residual(int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
@@ -260,9 +329,11 @@ int orc_rk_run(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                const double *val, const double *b, double *x, double gamma,
                uint64_t seed, uint32_t stream, int sampling_uniform, int update_one,
                int64_t tau, int64_t ticket0, int64_t nsteps, int64_t curve_every,
-               const double *x_ref, double *err_curve, double *res_curve, int32_t *rows_out)
+               const double *x_ref, double *err_curve, double *res_curve, int32_t *rows_out,
+               int slices, int64_t workers)
 {
     double *w = NULL, *corr = NULL, *pend_s = NULL;
+    int32_t *sweep_rows = NULL;
     uint64_t *thresh = NULL;
     int32_t *alias = NULL, *mark = NULL;
     int64_t *pend_row = NULL, *pend_t = NULL;
@@ -272,6 +343,8 @@ int orc_rk_run(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
     int rc = ORC_OK;
 
     if (m <= 0 || n <= 0 || m > 0x7fffffffll || n > 0x7fffffffll || nsteps < 0 || tau < 0 || !(gamma > 0.0))
+        return ORC_ERR_ARG;
+    if (slices && (update_one || workers <= 0 || ticket0 % m != 0))
         return ORC_ERR_ARG;
     w = (double *)malloc((size_t)m * sizeof(double));
     if (!w)
@@ -312,9 +385,23 @@ int orc_rk_run(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
         }
     }
 
+    if (slices) {
+        sweep_rows = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        if (!sweep_rows) { rc = ORC_ERR_NOMEM; goto done; }
+    }
     for (j = 0; j < nsteps; ++j) {
         uint32_t u3 = 0;
-        int64_t i = orc_draw(&sp, ticket0 + j, &u3);
+        int64_t i;
+        if (slices) {
+            int64_t t = ticket0 + j;
+            if (j == 0 || t % m == 0) {
+                rc = orc_slice_order(m, workers, seed, t / m, sweep_rows);
+                if (rc != ORC_OK) goto done;
+            }
+            i = sweep_rows[t % m];
+        } else {
+            i = orc_draw(&sp, ticket0 + j, &u3);
+        }
         int64_t beg = row_ptr[i], end = row_ptr[i + 1], k;
         double p = 0.0, r, s;
         if (rows_out) rows_out[j] = (int32_t)i;
@@ -374,6 +461,7 @@ int orc_rk_run(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
         }
     }
 done:
+    free(sweep_rows);
     free(w); free(thresh); free(alias); free(corr); free(mark);
     free(pend_s); free(pend_row); free(pend_t);
     return rc;

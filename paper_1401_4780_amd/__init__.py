@@ -53,7 +53,7 @@ class SolveParams(C.Structure):
         ("check_every", C.c_int32), ("refine", C.c_int32), ("inner_sweeps", C.c_int64),
         ("stream_id", C.c_uint32), ("trace", C.c_int32), ("ticket0", C.c_int64),
         ("cancel", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int64),
-        ("iter_dtype", C.c_int32), ("reserved", C.c_int32),
+        ("iter_dtype", C.c_int32), ("order", C.c_int32),
     ]
 
 
@@ -133,6 +133,7 @@ def lib():
     L.asyrk_residual.argtypes = [P, P, P, P]
     L.asyrk_sample_rows.argtypes = [P, u64, u32, i32, i64, i64, P, P]
     L.asyrk_lambda_max.argtypes = [P, i32, u64, P, P]
+    L.asyrk_autotune.argtypes = [P, dbl, i32, i64, P, P]
     L.asyrk_probe_copy.argtypes = [i64, i32, P]
     L.asyrk_probe_scatter.argtypes = [i64, i64, i32, i32, i32, P]
     L.asyrk_server_config_init.argtypes = [P]
@@ -147,7 +148,7 @@ def lib():
     L.asyrk_now.restype = dbl
     for name in ("asyrk_create", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
-                 "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_server_create",
+                 "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
                  "asyrk_server_poll", "asyrk_server_stats_get"):
         getattr(L, name).restype = C.c_int
@@ -289,11 +290,20 @@ class System:
                "asyrk_lambda_max")
         return lam.value, tau.value
 
+    def autotune(self, gamma=1.0, iter_dtype=None, in_flight=0):
+        """Time one sweep per lane-group width; the fastest becomes the default.
+        Returns (best G, {G: rows/s})."""
+        best = C.c_int32()
+        rates = (C.c_double * 5)()
+        _check(lib().asyrk_autotune(self._h, float(gamma), {None: -1, "f32": F32, "f64": F64}[iter_dtype],
+                                    int(in_flight), C.byref(best), rates), "asyrk_autotune")
+        return best.value, dict(zip((1, 2, 4, 8, 16), list(rates)))
+
     # -- the method
     def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
               update="all", lanes=0, in_flight=0, tol=0.0, x_ref=None, check_every=1,
               refine=False, inner_sweeps=0, stream_id=0, trace=False, ticket0=0, cancel=None,
-              history=0, iter_dtype=None) -> dict:
+              history=0, iter_dtype=None, order="replacement") -> dict:
         """Run from x (float64, overwritten with the result).  Returns the stats
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
         "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
@@ -316,6 +326,7 @@ class System:
         p.trace = int(bool(trace))
         p.ticket0 = ticket0
         p.iter_dtype = {None: -1, "f32": F32, "f64": F64}[iter_dtype]
+        p.order = {"replacement": 0, "slices": 1}[order]
         if cancel is not None:
             if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):
                 raise TypeError("cancel: expected a numpy int32 array")

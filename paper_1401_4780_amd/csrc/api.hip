@@ -34,6 +34,7 @@ struct asyrk_system {
     int64_t trace_cap = 0;
     int64_t device_bytes = 0;
     bool rec_b_dirty = false;
+    int tuned_G[2] = {0, 0};      // autotuned lanes per row for F64 / F32 iterates (0 = none)
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
@@ -161,6 +162,10 @@ double now_s() {
 }
 
 }  // namespace
+
+static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
+                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
+                               double *win_max_ticks, double *win_sum_ticks, double *win_cnt);
 
 // =========================================================================
 
@@ -421,6 +426,45 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
     return ASYRK_OK;
 }
 
+asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
+                            int32_t *best_lanes, double *rows_per_s_out) {
+    if (!s || !(gamma > 0.0 && gamma < 2.0) || in_flight < 0) return ASYRK_ERR_INVALID_ARG;
+    if (iter_dtype != -1 && iter_dtype != ASYRK_F32 && iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
+    const int xk = iter_dtype >= 0 ? iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
+    if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
+    if (s->rec_b_dirty) {
+        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+        s->rec_b_dirty = false;
+    }
+    if (xk == ASYRK_F64 && s->vk != ASYRK_F64 && !s->d_side) {
+        HIP_OK(dmalloc(s, &s->d_side, (size_t)s->m * sizeof(double2)));
+        HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
+    }
+    asyrk_solve_params p;
+    asyrk_solve_params_init(&p);
+    const int64_t R = in_flight ? in_flight : auto_in_flight(s);
+    // at least one sweep and at least 2M tickets per candidate
+    const int64_t tickets = std::max<int64_t>(s->m, (int64_t)2 << 20);
+    const int cands[5] = {1, 2, 4, 8, 16};
+    int best = 0;
+    double best_rate = 0.0;
+    for (int G : cands) {
+        HIP_OK(launch_zero(s->d_x, s->n * 8, s->st));
+        double gpu_s = 0.0, a = 0, b = 0, c = 0;
+        asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &a, &b, &c);
+        if (rc) return rc;
+        const double rate = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = G;
+        }
+        if (rows_per_s_out) rows_per_s_out[G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4] = rate;
+    }
+    s->tuned_G[xk == ASYRK_F32 ? 1 : 0] = best;
+    if (best_lanes) *best_lanes = best;
+    return ASYRK_OK;
+}
+
 asyrk_status asyrk_probe_copy(int64_t bytes, int32_t iters, double *gbps) {
     if (bytes < 16 || iters < 1 || !gbps) return ASYRK_ERR_INVALID_ARG;
     HIP_OK(probe_copy(bytes, iters, gbps));
@@ -455,14 +499,18 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     a.replay = p.mode == ASYRK_REPLAY;
     a.gamma = gamma;
     a.trace = p.trace ? s->d_trace : nullptr;
+    a.slices = p.order;
     HIP_OK(hipEventRecord(s->e0, s->st));
-    HIP_OK(launch_sweep(s->vk, xk, G, a, s->st));
+    if (p.order == 1)
+        HIP_OK(launch_sweep_slices(s->vk, xk, G, a, s->st));
+    else
+        HIP_OK(launch_sweep(s->vk, xk, G, a, s->st));
     HIP_OK(hipEventRecord(s->e1, s->st));
     HIP_OK(hipEventSynchronize(s->e1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
     *gpu_s += ms * 1e-3;
-    if (p.trace) {
+    if (p.trace && p.order == 0) {
         std::vector<uint64_t> tr((size_t)R * 3);
         HIP_OK(hipMemcpy(tr.data(), s->d_trace, tr.size() * 8, hipMemcpyDeviceToHost));
         for (int64_t w = 0; w < R; ++w) {
@@ -492,7 +540,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.in_flight < 0 || p.check_every < 1 || !(p.tol >= 0.0) || !std::isfinite(p.tol) || p.ticket0 < 0 ||
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
         return ASYRK_ERR_INVALID_ARG;
-    if (p.reserved != 0) return ASYRK_ERR_INVALID_ARG;
+    if (p.order != 0 && p.order != 1) return ASYRK_ERR_INVALID_ARG;
+    if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
+    if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
     if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
     const int xk = p.iter_dtype >= 0 ? p.iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
     if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
@@ -500,7 +550,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.refine && (p.mode == ASYRK_REPLAY || p.update == ASYRK_UPDATE_ONE)) return ASYRK_ERR_UNSUPPORTED;
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
-    const int G = p.lanes ? p.lanes : auto_lanes(s);
+    const int tuned = s->tuned_G[xk == ASYRK_F32 ? 1 : 0];
+    const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s));
     int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     const bool f32 = xk == ASYRK_F32;
@@ -594,8 +645,12 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         if (done > 0) HIP_OK(launch_iter_to_f64(s->d_x, f32, s->d_x64, s->n, 0, s->st));
         if (result == ASYRK_OK && p.tol > 0.0 && !(S.final_err <= p.tol)) result = ASYRK_ERR_NOT_CONVERGED;
     } else {
-        // FP64 iterative refinement: x64 master, FP32 correction d on A d = fp32(b - A x64)
-        const int64_t inner = p.inner_sweeps ? p.inner_sweeps : 20;
+        // FP64 iterative refinement: x64 master, FP32 correction d on A d = fp32(b - A x64).
+        // inner_sweeps > 0: that many sweeps per inner solve.  inner_sweeps = 0:
+        // the inner solve stops when its own relative residual ||r32 - A d|| /
+        // ||r32|| is <= 1e-6 or stops improving (the FP32 floor), at most 40.
+        const bool adaptive = p.inner_sweeps == 0;
+        const int64_t inner = adaptive ? 40 : p.inner_sweeps;
         asyrk_status rc = monitored_error(s, mon, s->d_x64, 0, &err0);
         if (rc) return rc;
         push_hist(err0);
@@ -607,11 +662,34 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                                    s->st));
             s->rec_b_dirty = true;
             HIP_OK(launch_zero(s->d_x, (int64_t)s->n * 4, s->st));
-            const int64_t c = std::min<int64_t>(inner, sweeps - done);
-            rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum, &wcnt);
-            if (rc) return rc;
-            ticket += c * s->m;
-            done += c;
+            const int64_t budget = std::min<int64_t>(inner, sweeps - done);
+            if (!adaptive) {
+                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + budget * s->m, &gpu_s, &wmax, &wsum,
+                                &wcnt);
+                if (rc) return rc;
+                ticket += budget * s->m;
+                done += budget;
+            } else {
+                double r0 = 0.0, prev = 1.0;
+                HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, nullptr, 0, s->d_part, kResidualBlocks,
+                                       s->st, 1));
+                rc = fetch_scalar(s, kResidualBlocks, &r0);
+                if (rc) return rc;
+                for (int64_t k = 0; k < budget; ++k) {
+                    rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + s->m, &gpu_s, &wmax, &wsum, &wcnt);
+                    if (rc) return rc;
+                    ticket += s->m;
+                    done += 1;
+                    double rk = 0.0;
+                    HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, nullptr, 0, s->d_part,
+                                           kResidualBlocks, s->st, 1));
+                    rc = fetch_scalar(s, kResidualBlocks, &rk);
+                    if (rc) return rc;
+                    const double rel = r0 > 0 ? std::sqrt(rk / r0) : 0.0;
+                    if (!std::isfinite(rel) || rel <= 1e-6 || rel > 0.5 * prev) break;
+                    prev = rel;
+                }
+            }
             HIP_OK(launch_iter_to_f64(s->d_x, 1, s->d_x64, s->n, 1, s->st));
             S.outer_iters++;
             double e = 0.0;

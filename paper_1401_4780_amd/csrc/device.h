@@ -103,21 +103,27 @@ template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; }
 // with an FP64 iterate read b_i and 1/w_i in FP64 from the side array (the
 // record header holds them in FP32).  Returns the read-to-write window in
 // clock ticks when `trace` is set.
-template <int VK, int XK, int G, int UPL = Upl<G>::value>
+// Row i of a sweep given directly (no sampling): used by the slice scheme.
+// `alias_ok` = false keeps row i whatever its header says.
+template <int VK, int XK, int G, int UPL = Upl<G>::value, bool SAMPLED = true>
 __device__ __forceinline__ uint64_t process_ticket(
     const Rows &rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
     const double2 *side, int64_t j, uint32_t stream_id, uint32_t k0, uint32_t k1, int uniform,
     int update_one, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl,
-    int trace) {
+    int trace, uint32_t given_row = 0) {
     using T = VT<VK>;
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     using H = typename T::hdr_t;
     constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
     constexpr int U = T::U;
 
-    // a1: ticket -> bucket -> row (alias decision needs the header)
-    const U4 u = draw(j, stream_id, k0, k1);
-    uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+    // a1: ticket -> bucket -> row (alias decision needs the header); or a given row
+    U4 u{0u, 0u, 0u, 0u};
+    uint32_t i = given_row;
+    if constexpr (SAMPLED) {
+        u = draw(j, stream_id, k0, k1);
+        i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+    }
     const uint8_t *rec;
     int nnz;
     locate(rows, i, rec, nnz);
@@ -130,7 +136,7 @@ __device__ __forceinline__ uint64_t process_ticket(
         const int uu = gl + q * G;
         if (uu < nunits) un[q].load(rec + T::HB + (int64_t)uu * T::UB);
     }
-    if (!uniform && !(u.c < h.thresh)) {
+    if (SAMPLED && !uniform && !(u.c < h.thresh)) {
         i = (uint32_t)h.alias;
         locate(rows, i, rec, nnz);
         h = load_hdr<VK>(rec);
@@ -230,6 +236,25 @@ __device__ __forceinline__ uint64_t process_ticket(
         unsafeAtomicAdd(x + c, -s1 * (X)v);
     }
     return trace ? wall_clock64() - t0 : 0;
+}
+
+// Keyed bijection of [0, L) for the slice scheme: with b the smallest width
+// such that 2^b >= L, mask = 2^b - 1 and h = (b + 1) / 2, apply
+//   y <- ((y ^ (y >> h)) * (u0 | 1) + u1) & mask
+//   y <- ((y ^ (y >> h)) * (u2 | 1) + u3) & mask
+// (each step is a bijection of [0, 2^b)) until y < L (cycle walking).
+// (u0..u3) = Philox4x32-10(counter (sweep lo, sweep hi, worker, 0x5C4E3D2B), key = seed).
+__device__ __forceinline__ uint32_t slice_perm(uint32_t k, uint32_t L, const U4 &u) {
+    if (L <= 1) return 0;
+    const uint32_t b = 32 - __clz(L - 1);
+    const uint32_t mask = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+    const uint32_t h = (b + 1) / 2;
+    uint32_t y = k;
+    do {
+        y = ((y ^ (y >> h)) * (u.a | 1u) + u.b) & mask;
+        y = ((y ^ (y >> h)) * (u.c | 1u) + u.d) & mask;
+    } while (y >= L);
+    return y;
 }
 
 }  // namespace asyrk

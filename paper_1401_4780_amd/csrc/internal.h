@@ -34,6 +34,8 @@ struct SweepArgs {
     int32_t replay;        // 1: wait for the scatter before the next read
     double gamma;
     uint64_t *trace;       // nullable: per worker {max window, sum window, count} in clock ticks
+    int32_t slices;        // 1: without-replacement slice scheme (t_begin, t_end are sweep multiples)
+    int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -80,10 +82,11 @@ __device__ __forceinline__ U4 draw(int64_t j, uint32_t stream_id, uint32_t k0, u
 // Host-side launchers (kernels.hip).  All return hipError_t of the launch.
 // ---------------------------------------------------------------------------
 hipError_t launch_sweep(int vk, int xk, int G, const SweepArgs &a, hipStream_t st);
+hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStream_t st);
 hipError_t launch_build_side(int vk, const Rows &rows, const double *b64, double2 *side, hipStream_t st);
 hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
                            double *r_out, int write_rec_b, double *partials, int nblocks,
-                           hipStream_t st);
+                           hipStream_t st, int rhs_from_rec = 0);
 hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int64_t n,
                              double *partials, int nblocks, hipStream_t st);
 hipError_t launch_finish_sum(const double *partials, int nparts, double *out, hipStream_t st);

@@ -46,6 +46,69 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     }
 }
 
+// Without-replacement slice scheme (the paper's experiments): worker w owns
+// rows [w L, min(m, (w + 1) L)), L = ceil(m / R), and visits them in a fresh
+// keyed permutation every sweep; one launch covers sweeps
+// t_begin / m .. t_end / m - 1.
+template <int VK, int XK, int G>
+__global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / G) + (lane / G);
+    if (worker >= a.R) return;
+    const int64_t m = a.rows.m;
+    const int64_t L = (m + a.R - 1) / a.R;
+    const int64_t start = worker * L;
+    const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
+    if (Lw == 0) return;
+    X *x = reinterpret_cast<X *>(a.x);
+    const X gamma = (X)a.gamma;
+    for (int64_t sw = a.t_begin / m; sw < a.t_end / m; ++sw) {
+        const U4 u = philox4x32_10((uint32_t)((uint64_t)sw & 0xffffffffu), (uint32_t)((uint64_t)sw >> 32),
+                                   (uint32_t)worker, 0x5C4E3D2Bu, a.key0, a.key1);
+        for (int64_t k = 0; k < Lw; ++k) {
+            const uint32_t i = (uint32_t)(start + slice_perm((uint32_t)k, (uint32_t)Lw, u));
+            process_ticket<VK, XK, G, Upl<G>::value, false>(a.rows, x, a.side, 0, 0u, 0u, 0u, 1, 0, gamma, gl, 0,
+                                                             i);
+            if (a.replay) __threadfence();
+        }
+    }
+}
+
+template <int VK, int XK>
+static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
+    const int64_t threads = a.R * G;
+    const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
+    const int64_t grid = (threads + block - 1) / block;
+    switch (G) {
+        case 1: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStream_t st) {
+    if (xk == ASYRK_F32) {
+        switch (vk) {
+            case ASYRK_F32: return launch_slices_vk<ASYRK_F32, ASYRK_F32>(G, a, st);
+            case ASYRK_BF16: return launch_slices_vk<ASYRK_BF16, ASYRK_F32>(G, a, st);
+        }
+    } else if (xk == ASYRK_F64) {
+        switch (vk) {
+            case ASYRK_F32: return launch_slices_vk<ASYRK_F32, ASYRK_F64>(G, a, st);
+            case ASYRK_BF16: return launch_slices_vk<ASYRK_BF16, ASYRK_F64>(G, a, st);
+            case ASYRK_F64: return launch_slices_vk<ASYRK_F64, ASYRK_F64>(G, a, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int VK, int XK>
 static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     const int64_t threads = a.R * G;
@@ -169,11 +232,13 @@ hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int6
 
 // ---------------------------------------------------------------- residual (FP64)
 // r_i = b_i - sum_k v_k x_{c_k}, stored values promoted exactly to FP64
-// (b64 == nullptr: r = -A x).
+// (b64 == nullptr: r = -A x; rhs_from_rec: b_i is the record header's b,
+// i.e. the right-hand side the sweeps currently solve for).
 // One group of 4 lanes per row, rows in order (coalesced record stream).
 template <int VK, class XI>
 __global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const double *b64, const XI *x,
-                                                        double *r_out, int write_rec_b, double *partials) {
+                                                        double *r_out, int write_rec_b, double *partials,
+                                                        int rhs_from_rec) {
     using T = VT<VK>;
     constexpr int G = 4;
     const int gl = threadIdx.x & (G - 1);
@@ -194,7 +259,9 @@ __global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const do
                 if (uu * T::U + e < nnz) acc = fma((double)un.v[e], (double)x[un.c[e]], acc);
         }
         acc = group_sum<G>(acc);
-        const double r = (b64 ? b64[i] : 0.0) - acc;
+        double bi = b64 ? b64[i] : 0.0;
+        if (rhs_from_rec) bi = (double)load_hdr<VK>(rec).b;
+        const double r = bi - acc;
         if (gl == 0) {
             if (r_out) r_out[i] = r;
             if (write_rec_b) {
@@ -210,23 +277,23 @@ __global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const do
 template <int VK>
 static hipError_t launch_residual_vk(const Rows &rows, const double *b64, const void *x, int x_is_f32,
                                      double *r_out, int write_rec_b, double *partials, int nblocks,
-                                     hipStream_t st) {
+                                     int rhs_from_rec, hipStream_t st) {
     if (x_is_f32)
         hipLaunchKernelGGL((residual_kernel<VK, float>), dim3(nblocks), dim3(256), 0, st, rows, b64,
-                           (const float *)x, r_out, write_rec_b, partials);
+                           (const float *)x, r_out, write_rec_b, partials, rhs_from_rec);
     else
         hipLaunchKernelGGL((residual_kernel<VK, double>), dim3(nblocks), dim3(256), 0, st, rows, b64,
-                           (const double *)x, r_out, write_rec_b, partials);
+                           (const double *)x, r_out, write_rec_b, partials, rhs_from_rec);
     return hipGetLastError();
 }
 
 hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
                            double *r_out, int write_rec_b, double *partials, int nblocks,
-                           hipStream_t st) {
+                           hipStream_t st, int rhs_from_rec) {
     switch (vk) {
-        case ASYRK_F32: return launch_residual_vk<ASYRK_F32>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
-        case ASYRK_BF16: return launch_residual_vk<ASYRK_BF16>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
-        case ASYRK_F64: return launch_residual_vk<ASYRK_F64>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, st);
+        case ASYRK_F32: return launch_residual_vk<ASYRK_F32>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
+        case ASYRK_BF16: return launch_residual_vk<ASYRK_BF16>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
+        case ASYRK_F64: return launch_residual_vk<ASYRK_F64>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
     }
     return hipErrorInvalidValue;
 }

@@ -278,13 +278,13 @@ def test_async_fp64_iterate_over_fp32_storage_reaches_1e10(dtype):
     sysm.close()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_refinement_reaches_1e10(dtype):
+@pytest.mark.parametrize("dtype,inner", [("f32", 0), ("bf16", 0), ("f32", 12)])
+def test_refinement_reaches_1e10(dtype, inner):
     s = synth.uniform_rows(80_000, 20_000, 16, seed=3, dtype=dtype)
-    _say(f"refinement {dtype} to 1e-10")
+    _say(f"refinement {dtype} inner={inner} to 1e-10")
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=400, seed=5, tol=1e-10, refine=True,
-                      in_flight=1024, history=64)
+                      in_flight=1024, history=64, inner_sweeps=inner)
     assert st["status"] == "OK", st
     assert st["outer_iters"] >= 2
     # x* is exact for the stored values (b = A x* in FP64 from them)
@@ -390,4 +390,55 @@ def test_set_rhs():
     x = np.zeros(s.n)
     st = sysm.solve(x, 1.0, 60, 1, tol=1e-12, x_ref=x2)
     assert st["status"] == "OK"
+    sysm.close()
+
+
+# ------------------------------------------------------------------ slice scheme, autotuner
+
+def test_replay_slices_matches_oracle():
+    """One worker, every row once per sweep in the keyed order: 1e-12 vs the oracle."""
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype="f64")
+    _say("replay slices")
+    ref = oracle_run(s, 1.0, 10, 5, slices=True, workers=1)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=10, seed=5, mode="replay", order="slices",
+                      history=16)
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    # resuming at a sweep boundary continues the same sequence
+    torch = _torch()
+    x3 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    st = sysm.solve(x3, 1.0, 4, 5, mode="replay", order="slices")
+    sysm.solve(x3, 1.0, 6, 5, mode="replay", order="slices", ticket0=st["next_ticket"])
+    assert np.linalg.norm(x3.cpu().numpy() - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    with pytest.raises(P.AsyrkError):
+        sysm.solve(x3, 1.0, 1, 5, order="slices", ticket0=7)
+    with pytest.raises(P.AsyrkError):
+        sysm.solve(x3, 1.0, 1, 5, order="slices", update="one")
+    sysm.close()
+
+
+@pytest.mark.parametrize("R", [64, 800])
+def test_async_slices_reaches_1e6(R):
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say(f"async slices R={R}")
+    ref = oracle_run(s, 1.0, 60, 1, slices=True, workers=R)
+    k_orc = _sweeps_to(ref["err"], 1e-6)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=R, order="slices")
+    assert st["status"] == "OK", st
+    assert np.linalg.norm(x - s.x_star) <= 1.05e-6 * np.linalg.norm(s.x_star)
+    assert st["sweeps_done"] <= math.ceil(1.5 * k_orc) + 1, (st["sweeps_done"], k_orc)
+    sysm.close()
+
+
+def test_autotune_picks_a_lane_width():
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say("autotune")
+    sysm = make_system(s, device=True)
+    best, rates = sysm.autotune(in_flight=800)
+    assert best in (1, 2, 4, 8, 16) and all(r > 0 for r in rates.values())
+    assert rates[best] == max(rates.values())
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
+    assert st["lanes"] == best and st["status"] == "OK"
     sysm.close()
