@@ -303,24 +303,27 @@ def run_skewed(args):
     x = torch.zeros(s.n, dtype=torch.float64, device=dev)
     cnt = np.bincount(s.col, minlength=s.n)
     res = {}
-    for R in (args.in_flight,) if args.in_flight else (1, 64, 1024, 16384, 65536):
+    R0 = info["default_in_flight"]  # Corollary 1 with lambda >= max column norm^2
+    sweeps = 5
+    for R in (args.in_flight,) if args.in_flight else (R0, 4 * R0, 64, 1024, 16384, 65536):
         x.zero_()
-        budget = 100 if R > 1 else 2
-        st = sysm.solve(x, 1.0, budget, 5, x_ref=x_ref, in_flight=R, lanes=args.lanes, history=128,
-                        tol=1e-6)
+        st = sysm.solve(x, 1.0, sweeps, 5, x_ref=x_ref, in_flight=R, lanes=args.lanes, history=16)
         h = st["history"]
         res[str(R)] = {"rows_per_s": st["rows_per_s"], "sweeps": st["sweeps_done"],
-                       "final_err": st["final_err"], "status": st["status"],
-                       "err_after_10_sweeps": float(h[min(10, h.size - 1)]),
-                       "lanes": st["lanes"]}
+                       "err_after_sweeps": st["final_err"], "status": st["status"],
+                       "err_curve": [float(v) for v in h], "lanes": st["lanes"]}
         log(f"skewed R={R}: {res[str(R)]}")
-    best = max(res, key=lambda q: res[q]["rows_per_s"])
+    converging = {q: v for q, v in res.items() if np.isfinite(v["err_after_sweeps"])
+                  and v["err_after_sweeps"] < v["err_curve"][0]}
+    best = max(converging or res, key=lambda q: res[q]["rows_per_s"])
     return {"metric": "row updates/s (skewed rows, hot columns)", "value": res[best]["rows_per_s"],
             "unit": "row updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
             "vs_baseline": None, "data": "synthetic", "dtype": "f32",
             "config": {"workload": "asyrk_skewed_2Mx500k_lognormal16_zipf1.1", "m": s.m, "n": s.n,
-                       "nnz": s.nnz, "mu": info["mu"], "nu": info["nu"]},
-            "lambda_max": lam, "tau_max_corollary1": tau_max,
+                       "nnz": s.nnz, "mu": info["mu"], "nu": info["nu"], "sweeps": sweeps,
+                       "best_converging_in_flight": best},
+            "lambda_max": lam, "tau_max_corollary1": tau_max, "default_in_flight": R0,
+            "max_col_norm2": info["max_col_norm2"],
             "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
 
 
@@ -346,7 +349,7 @@ def run_serving(args):
         m, n = (int(v) for v in specs[rid])
         return synth.serving_system(rid, m, n)
 
-    srv = P.Server(budget_bytes=64 << 30)
+    srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}))
 
     def drive(first, count, arrivals):
         """Submit requests first..first+count-1 at their arrival times (seconds
@@ -416,7 +419,8 @@ def run_serving(args):
             "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
             "vs_baseline": None, "data": "synthetic", "dtype": "f32 sweeps, f64 refinement",
             "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8",
-                       "requests_per_point": n_req, "budget_GiB": 64, "tol": tol},
+                       "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
+                       "inner_sweeps_per_round": srv.config["inner_sweeps"]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,

@@ -93,7 +93,9 @@ typedef struct asyrk_solve_params {
     int32_t mode;            /* asyrk_mode, default ASYNC */
     int32_t sampling;        /* asyrk_sampling, default NORM2 */
     int32_t update;          /* asyrk_update, default ALL */
-    int32_t lanes;           /* lanes per row G in {1,2,4,8,16}; 0 = choose */
+    int32_t lanes;           /* lanes per row G in {1,2,4,8,16,32,64}; 0 = autotuned value if
+                                any, else a rule of thumb (a whole wave per row when
+                                R <= 256 workers) */
     int64_t in_flight;       /* R, row workers in flight (tau_design = R - 1); 0 = choose */
     double tol;              /* stop when the monitored error <= tol; 0 = run every sweep */
     const double *x_ref;     /* nullable, length n: monitor ||x - x_ref||/||x_ref||;
@@ -196,6 +198,22 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
                           const int32_t *col_idx, const void *vals, int32_t vals_dtype,
                           const double *b, int32_t mem, void *stream);
 
+/*
+ * Least squares for an inconsistent A x = b through the consistent augmented
+ * system of the paper's Section "Extension to Inconsistent Systems":
+ *     [ 0      phi A^T ] [x]   [phi A^T b]
+ *     [ A     -zeta I  ] [y] = [    0    ]
+ * (size n + m; zeta, phi > 0; the paper's best choice is phi = 1 and
+ * zeta = sigma_min(A) / sqrt(2)).  Arguments as in asyrk_create for A and b;
+ * the created system's unknown is z = (x, y) and its x block equals
+ * zeta * x_LS, so the least-squares solution is z[0:n] / zeta.  Entries
+ * phi * a_ij and -zeta are rounded to vals_dtype.  Errors as asyrk_create;
+ * ZERO_ROW also for an empty column of A.
+ */
+asyrk_status asyrk_create_augmented(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                                    const int32_t *col_idx, const void *vals, int32_t vals_dtype,
+                                    const double *b, double zeta, double phi, int32_t mem, void *stream);
+
 /* Release every device and host resource of the system (NULL is accepted). */
 asyrk_status asyrk_destroy(asyrk_system *s);
 
@@ -296,7 +314,7 @@ typedef struct asyrk_server asyrk_server;
 typedef struct asyrk_server_config {
     int64_t budget_bytes;  /* device memory for resident systems (one arena), default 64 GiB */
     int32_t max_slots;     /* systems active at once, default 1024 */
-    int32_t inner_sweeps;  /* FP32 sweeps per round (refinement inner solve), default 10 */
+    int32_t inner_sweeps;  /* FP32 sweeps per round (refinement inner solve), default 8 */
     int64_t max_workers;   /* row workers over all active systems, default 65536 */
     int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
     int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */

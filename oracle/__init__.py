@@ -209,3 +209,27 @@ def apply_rows(row_ptr, col, val, b, x0, gamma, rows, coords=None):
     _check(lib.orc_rk_apply_rows(rp.size - 1, x.size, _p(rp), _p(cl), _p(v), _p(bb), _p(x),
                                  float(gamma), _p(rr), _p(cc), rr.size))
     return x
+
+
+def augmented_system(row_ptr, col, val, b, n, zeta, phi=1.0):
+    """The consistent augmented system of the paper's Section "Extension to
+    Inconsistent Systems" for least squares min ||A x - b||:
+
+        [ 0      phi A^T ] [x]   [phi A^T b]
+        [ A     -zeta I  ] [y] = [    0    ]
+
+    in CSR (float64), unknowns z = (x, y) of length n + m.  From the second
+    block y = A x / zeta, and the first gives A^T A x = zeta A^T b, so the
+    least-squares solution is x / zeta.  Built with scipy's sparse blocks.
+    Returns (row_ptr, col, val, b_aug)."""
+    import scipy.sparse as sp
+    rp = _c(row_ptr, np.int64)
+    m = rp.size - 1
+    A = sp.csr_matrix((_c(val, np.float64), _c(col, np.int32), rp), shape=(m, n))
+    top = sp.hstack([sp.csr_matrix((n, n)), phi * A.T.tocsr()])
+    bot = sp.hstack([A, -zeta * sp.identity(m, format="csr")])
+    M = sp.vstack([top, bot]).tocsr()
+    M.sort_indices()
+    M.eliminate_zeros()
+    b_aug = np.concatenate([phi * (A.T @ _c(b, np.float64)), np.zeros(m)])
+    return M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.float64), b_aug

@@ -126,6 +126,7 @@ def lib():
     L.asyrk_solve_params_init.argtypes = [P]
     L.asyrk_solve_params_init.restype = None
     L.asyrk_create.argtypes = [P, i64, i64, P, P, P, i32, P, i32, P]
+    L.asyrk_create_augmented.argtypes = [P, i64, i64, P, P, P, i32, P, dbl, dbl, i32, P]
     L.asyrk_destroy.argtypes = [P]
     L.asyrk_set_rhs.argtypes = [P, P]
     L.asyrk_system_info_get.argtypes = [P, P]
@@ -146,7 +147,7 @@ def lib():
     L.asyrk_server_stats_get.argtypes = [P, P]
     L.asyrk_now.argtypes = []
     L.asyrk_now.restype = dbl
-    for name in ("asyrk_create", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
+    for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
@@ -212,7 +213,10 @@ class System:
     ``b`` float64[m].  All numpy (host) or all torch CUDA tensors (device).
     """
 
-    def __init__(self, row_ptr, col, val, b, *, n=None, dtype=None, stream=None):
+    def __init__(self, row_ptr, col, val, b, *, n=None, dtype=None, stream=None, augmented=None):
+        """augmented=(zeta, phi): build the paper's consistent augmented system
+        for least squares of an inconsistent A x = b (size n + m); the
+        least-squares x is then z[:n] / zeta (see least_squares_x)."""
         L = lib()
         self.device = _is_torch(row_ptr) and row_ptr.is_cuda
         _expect(row_ptr, self.device, "int64", "row_ptr")
@@ -228,11 +232,24 @@ class System:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
         h = C.c_void_p()
-        rc = L.asyrk_create(C.byref(h), self.m, self.n, _ptr(row_ptr), _ptr(col), _ptr(val),
-                            self.vals_dtype, _ptr(b), MEM_DEVICE if self.device else MEM_HOST,
-                            stream)
-        _check(rc, "asyrk_create")
+        mem = MEM_DEVICE if self.device else MEM_HOST
+        if augmented is None:
+            rc = L.asyrk_create(C.byref(h), self.m, self.n, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                self.vals_dtype, _ptr(b), mem, stream)
+            _check(rc, "asyrk_create")
+        else:
+            zeta, phi = augmented
+            rc = L.asyrk_create_augmented(C.byref(h), self.m, self.n, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                          self.vals_dtype, _ptr(b), float(zeta), float(phi), mem, stream)
+            _check(rc, "asyrk_create_augmented")
+            self.a_shape = (self.m, self.n)
+            self.zeta = float(zeta)
+            self.m = self.n = self.m + self.n
         self._h = h
+
+    def least_squares_x(self, z):
+        """x_LS = z[:n] / zeta for a system built with augmented=(zeta, phi)."""
+        return z[: self.a_shape[1]] / self.zeta
 
     # -- lifetime
     def close(self):

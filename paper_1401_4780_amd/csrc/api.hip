@@ -109,11 +109,13 @@ asyrk_status fetch_scalar(asyrk_system *s, int nparts, double *host_out) {
     return ASYRK_OK;
 }
 
-int auto_lanes(const asyrk_system *s) {
+int auto_lanes(const asyrk_system *s, int64_t R) {
     const Geom g = geom_of(s->vk);
     const double units = ((double)s->nnz / (double)s->m) / g.U;
     int G = 1;
     while (G < 16 && G < units / 2.0) G *= 2;
+    // with few workers, lanes are free: a whole wave per row (long rows too)
+    if (R * 64 <= 256 * 64) G = 64;
     return G;
 }
 
@@ -166,6 +168,9 @@ double now_s() {
 static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
                                uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
                                double *win_max_ticks, double *win_sum_ticks, double *win_cnt);
+static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, const int64_t *rp,
+                                     const int32_t *cl, const uint8_t *vl, int32_t vals_dtype, const double *bb,
+                                     int32_t mem, void *stream);
 
 // =========================================================================
 
@@ -234,8 +239,14 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     rc = to_host(&tmp_for_copy, mem, b, (size_t)m, b_buf, bb);
     if (rc) return rc;
 
+    return create_from_host(out, m, n, rp, cl, vl, vals_dtype, bb, mem, stream);
+}
+
+static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, const int64_t *rp,
+                                     const int32_t *cl, const uint8_t *vl, int32_t vals_dtype, const double *bb,
+                                     int32_t mem, void *stream) {
     SetupResult res;
-    rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, res);
+    asyrk_status rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, res);
     if (rc) return rc;
     rc = pack_records(m, rp, cl, vl, vals_dtype, bb, res);
     if (rc) return rc;
@@ -244,7 +255,7 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     if (!s) return ASYRK_ERR_OOM;
     s->m = m;
     s->n = n;
-    s->nnz = nnz;
+    s->nnz = res.nnz;
     s->vk = vals_dtype;
     s->mem = mem;
     s->st = (hipStream_t)stream;
@@ -294,6 +305,45 @@ fail:
 asyrk_status asyrk_destroy(asyrk_system *s) {
     free_system(s);
     return ASYRK_OK;
+}
+
+asyrk_status asyrk_create_augmented(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                                    const int32_t *col_idx, const void *vals, int32_t vals_dtype, const double *b,
+                                    double zeta, double phi, int32_t mem, void *stream) {
+    if (!out) return ASYRK_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (mem != ASYRK_MEM_HOST && mem != ASYRK_MEM_DEVICE) return ASYRK_ERR_INVALID_ARG;
+    if (m < 1 || n < 1 || m > INT32_MAX || n > INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    if (vals_dtype != ASYRK_F64 && vals_dtype != ASYRK_F32 && vals_dtype != ASYRK_BF16)
+        return ASYRK_ERR_INVALID_ARG;
+    if (!row_ptr || !b || !col_idx || !vals) return ASYRK_ERR_INVALID_ARG;
+    asyrk_system tmp_for_copy;
+    std::vector<int64_t> rp_buf;
+    std::vector<int32_t> col_buf;
+    std::vector<uint8_t> val_buf;
+    std::vector<double> b_buf;
+    const int64_t *rp = nullptr;
+    const int32_t *cl = nullptr;
+    const uint8_t *vl = nullptr;
+    const double *bb = nullptr;
+    asyrk_status rc = to_host(&tmp_for_copy, mem, row_ptr, (size_t)m + 1, rp_buf, rp);
+    if (rc) return rc;
+    if (rp[0] != 0 || rp[m] < 0 || rp[m] >= INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    const Geom g = geom_of(vals_dtype);
+    rc = to_host(&tmp_for_copy, mem, col_idx, (size_t)rp[m], col_buf, cl);
+    if (rc) return rc;
+    rc = to_host(&tmp_for_copy, mem, static_cast<const uint8_t *>(vals), (size_t)rp[m] * g.VB, val_buf, vl);
+    if (rc) return rc;
+    rc = to_host(&tmp_for_copy, mem, b, (size_t)m, b_buf, bb);
+    if (rc) return rc;
+    SetupResult chk;  // A itself must be a valid CSR with no zero row
+    rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, chk);
+    if (rc) return rc;
+    AugCSR aug;
+    rc = build_augmented(m, n, rp, cl, vl, vals_dtype, bb, zeta, phi, aug);
+    if (rc) return rc;
+    return create_from_host(out, n + m, n + m, aug.row_ptr.data(), aug.col.data(), aug.vals.data(), vals_dtype,
+                            aug.b.data(), mem, stream);
 }
 
 asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *info) {
@@ -535,7 +585,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.mode != ASYRK_ASYNC && p.mode != ASYRK_REPLAY) return ASYRK_ERR_INVALID_ARG;
     if (p.sampling != ASYRK_SAMPLE_NORM2 && p.sampling != ASYRK_SAMPLE_UNIFORM) return ASYRK_ERR_INVALID_ARG;
     if (p.update != ASYRK_UPDATE_ALL && p.update != ASYRK_UPDATE_ONE) return ASYRK_ERR_INVALID_ARG;
-    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 2 && p.lanes != 4 && p.lanes != 8 && p.lanes != 16)
+    if (p.lanes != 0 && p.lanes != 1 && p.lanes != 2 && p.lanes != 4 && p.lanes != 8 && p.lanes != 16 &&
+        p.lanes != 32 && p.lanes != 64)
         return ASYRK_ERR_INVALID_ARG;
     if (p.in_flight < 0 || p.check_every < 1 || !(p.tol >= 0.0) || !std::isfinite(p.tol) || p.ticket0 < 0 ||
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
@@ -551,8 +602,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
     const int tuned = s->tuned_G[xk == ASYRK_F32 ? 1 : 0];
-    const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s));
     int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
+    const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     const bool f32 = xk == ASYRK_F32;
     const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;

@@ -88,6 +88,8 @@ static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
         case 4: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
         case 8: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
         case 16: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -120,6 +122,8 @@ static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
         case 4: hipLaunchKernelGGL((sweep_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
         case 8: hipLaunchKernelGGL((sweep_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
         case 16: hipLaunchKernelGGL((sweep_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((sweep_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((sweep_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

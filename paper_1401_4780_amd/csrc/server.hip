@@ -128,27 +128,46 @@ __global__ __launch_bounds__(256) void srv_residual_kernel(const TableHead *th, 
     const int gl = threadIdx.x & (G - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int64_t ngrp = (int64_t)gridDim.x * blockDim.x / G;
-    for (int64_t q = grp; q < total; q += ngrp) {
-        const int s = find_slot(nact, q, [&](int k) { return sl[k].row_off; });
-        const SlotDesc &d = sl[s];
-        const int64_t i = q - d.row_off;
-        const uint8_t *rec;
-        int nnz;
-        locate(d.rows, (uint32_t)i, rec, nnz);
-        const int nunits = (nnz + T::U - 1) / T::U;
-        double acc = 0.0;
-        for (int uu = gl; uu < nunits; uu += G) {
-            Unit<ASYRK_F32> un;
-            un.load(rec + T::HB + (int64_t)uu * T::UB);
+    // every wave runs the same trip count so the wave-wide sums below see all lanes
+    const int64_t wave0 = (grp / (64 / G)) * (64 / G);
+    for (int64_t qb = wave0; qb < total; qb += ngrp) {
+        const int64_t q = qb + (grp - wave0);
+        const bool live = q < total;
+        int s = -1;
+        double r2 = 0.0;
+        if (live) {
+            s = find_slot(nact, q, [&](int k) { return sl[k].row_off; });
+            const SlotDesc &d = sl[s];
+            const int64_t i = q - d.row_off;
+            const uint8_t *rec;
+            int nnz;
+            locate(d.rows, (uint32_t)i, rec, nnz);
+            const int nunits = (nnz + T::U - 1) / T::U;
+            double acc = 0.0;
+            for (int uu = gl; uu < nunits; uu += G) {
+                Unit<ASYRK_F32> un;
+                un.load(rec + T::HB + (int64_t)uu * T::UB);
 #pragma unroll
-            for (int e = 0; e < T::U; ++e)
-                if (uu * T::U + e < nnz) acc = fma((double)un.v[e], d.x64[un.c[e]], acc);
+                for (int e = 0; e < T::U; ++e)
+                    if (uu * T::U + e < nnz) acc = fma((double)un.v[e], d.x64[un.c[e]], acc);
+            }
+            acc = group_sum<G>(acc);
+            const double r = d.b64[i] - acc;
+            if (gl == 0) {
+                reinterpret_cast<HdrF32 *>(const_cast<uint8_t *>(rec))->b = (float)r;
+                r2 = r * r;
+            }
         }
-        acc = group_sum<G>(acc);
-        const double r = d.b64[i] - acc;
-        if (gl == 0) {
-            reinterpret_cast<HdrF32 *>(const_cast<uint8_t *>(rec))->b = (float)r;
-            unsafeAtomicAdd(norm2 + s, r * r);
+        // one atomic per wave when all its rows belong to one system
+        const int s0 = __shfl(s, 0);
+        const bool same = __all(!live || s == s0);
+        if (same) {
+            double w = r2;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+            if ((threadIdx.x & 63) == 0 && s0 >= 0) unsafeAtomicAdd(norm2 + s0, w);
+        } else if (live && gl == 0) {
+            unsafeAtomicAdd(norm2 + s, r2);
         }
     }
 }
@@ -301,7 +320,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->budget_bytes = (int64_t)64 << 30;
     c->max_slots = 1024;
     c->max_workers = (int64_t)1 << 16;
-    c->inner_sweeps = 10;
+    c->inner_sweeps = 8;
     c->max_rounds = 60;
     c->gamma = 1.0;
     c->use_graph = 1;

@@ -164,6 +164,75 @@ void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
     // leftovers keep thresh = 2^32 - 1 and alias = self
 }
 
+// Store a FP64 value in the dtype (BF16: nearest, ties to even, of the FP32 value).
+static void store_as(double v, int vk, uint8_t *dst) {
+    if (vk == ASYRK_F64) {
+        std::memcpy(dst, &v, 8);
+    } else {
+        const float f = (float)v;
+        if (vk == ASYRK_F32) {
+            std::memcpy(dst, &f, 4);
+        } else {
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            const uint32_t bias = ((u >> 16) & 1u) + 0x7FFFu;
+            const uint16_t h = (uint16_t)((u + bias) >> 16);
+            std::memcpy(dst, &h, 2);
+        }
+    }
+}
+
+// Rows 0..n-1: row j holds phi * A[i, j] at columns n + i (i increasing) and
+// right-hand side phi * sum_i A[i, j] b_i (i increasing); rows n..n+m-1: row
+// n + i holds a_i at its own columns, then -zeta at column n + i, right-hand
+// side 0.
+asyrk_status build_augmented(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const void *vals, int vk, const double *b, double zeta, double phi, AugCSR &out) {
+    if (!(zeta > 0.0) || !(phi > 0.0) || !std::isfinite(zeta) || !std::isfinite(phi)) return ASYRK_ERR_INVALID_ARG;
+    if (m < 1 || n < 1 || m + n > INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    const int64_t nnz = row_ptr[m];
+    if (2 * nnz + m >= (int64_t)INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    const int vb = vk == ASYRK_F64 ? 8 : (vk == ASYRK_F32 ? 4 : 2);
+    const int64_t N = n + m;
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) cnt[col[k] + 1]++;
+    for (int64_t j = 0; j < n; ++j)
+        if (cnt[j + 1] == 0) return ASYRK_ERR_ZERO_ROW;  // an empty column of A
+    for (int64_t j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
+    try {
+        out.row_ptr.assign(N + 1, 0);
+        out.col.resize(2 * nnz + m);
+        out.vals.resize((2 * nnz + m) * vb);
+        out.b.assign(N, 0.0);
+    } catch (...) {
+        return ASYRK_ERR_OOM;
+    }
+    for (int64_t j = 0; j < n; ++j) out.row_ptr[j + 1] = cnt[j + 1];
+    for (int64_t i = 0; i < m; ++i) out.row_ptr[n + i + 1] = nnz + row_ptr[i + 1] + i + 1;
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    std::vector<double> atb(n, 0.0);
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const double a = promote(vals, vk, k);
+            const int64_t pos = fill[j]++;
+            out.col[pos] = (int32_t)(n + i);
+            store_as(phi * a, vk, &out.vals[pos * vb]);
+            atb[j] = atb[j] + a * b[i];
+        }
+        const int64_t base = nnz + row_ptr[i] + i;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            out.col[base + (k - row_ptr[i])] = col[k];
+            std::memcpy(&out.vals[(base + (k - row_ptr[i])) * vb], static_cast<const uint8_t *>(vals) + k * vb, vb);
+        }
+        const int64_t last = nnz + row_ptr[i + 1] + i;
+        out.col[last] = (int32_t)(n + i);
+        store_as(-zeta, vk, &out.vals[last * vb]);
+    }
+    for (int64_t j = 0; j < n; ++j) out.b[j] = phi * atb[j];
+    return ASYRK_OK;
+}
+
 // Record stride for equal-length rows: pad to 64 bytes when that touches
 // fewer 64-byte sectors per record than 16-byte packing does on average.
 static int64_t choose_stride(int64_t raw) {

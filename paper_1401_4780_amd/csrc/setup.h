@@ -23,6 +23,17 @@ struct SetupResult {
     std::vector<uint8_t> rec;  // packed records
 };
 
+// Augmented consistent system for least squares (inconsistent A x = b):
+// [[0, phi A^T], [A, -zeta I]] z = [phi A^T b; 0], z = (x, y) of length n + m.
+struct AugCSR {
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<uint8_t> vals;  // in the storage dtype of A
+    std::vector<double> b;
+};
+asyrk_status build_augmented(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const void *vals, int vk, const double *b, double zeta, double phi, AugCSR &out);
+
 asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                              const void *vals, int vk, const double *b, SetupResult &out);
 void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,

@@ -142,6 +142,8 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_solve(None, x.ctypes.data, 1.0, 1, 0, None, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_residual(None, x.ctypes.data, None, C.byref(v))] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_create(None, 1, 1, None, None, None, 0, None, 0, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_create_augmented(None, 1, 1, None, None, None, 0, None, 1.0, 1.0, 0,
+                                             None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_lambda_max(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_destroy(None)] == "OK"
     assert P.STATUS[L.asyrk_probe_copy(0, 1, C.byref(v))] == "INVALID_ARG"
@@ -177,3 +179,21 @@ def test_binding_type_checks():
         P.System(rp, col.astype(np.int64), val, b, n=n)
     with pytest.raises(TypeError):
         P.System(rp, col, val, b.astype(np.float32), n=n)
+
+
+@pytest.mark.parametrize("zeta,phi,expect", [(0.0, 1.0, "INVALID_ARG"), (1.0, -1.0, "INVALID_ARG"),
+                                             (float("nan"), 1.0, "INVALID_ARG")])
+def test_augmented_validation(zeta, phi, expect):
+    rp, col, val, b, n = _good()
+    h = C.c_void_p()
+    rc = P.lib().asyrk_create_augmented(C.byref(h), rp.size - 1, n, rp.ctypes.data, col.ctypes.data,
+                                        val.ctypes.data, P.F32, b.ctypes.data, zeta, phi, P.MEM_HOST, None)
+    assert P.STATUS[rc] == expect
+
+
+def test_augmented_rejects_empty_column():
+    rp, col, val, b, n = _good()
+    h = C.c_void_p()
+    rc = P.lib().asyrk_create_augmented(C.byref(h), rp.size - 1, n + 5, rp.ctypes.data, col.ctypes.data,
+                                        val.ctypes.data, P.F32, b.ctypes.data, 0.5, 1.0, P.MEM_HOST, None)
+    assert P.STATUS[rc] == "ZERO_ROW"

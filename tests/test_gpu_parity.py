@@ -442,3 +442,42 @@ def test_autotune_picks_a_lane_width():
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
     assert st["lanes"] == best and st["status"] == "OK"
     sysm.close()
+
+
+# ------------------------------------------------------------------ inconsistent systems (augmented)
+
+def _inconsistent(m, n, k, seed):
+    s = synth.uniform_rows(m, n, k, seed=seed, dtype="f64")
+    b = s.b + 0.3 * np.random.default_rng(seed).standard_normal(m)
+    return s, b
+
+
+def test_replay_augmented_matches_oracle():
+    s, b = _inconsistent(300, 80, 6, 21)
+    A = s.dense()
+    zeta = np.linalg.svd(A, compute_uv=False).min() / np.sqrt(2)
+    _say("replay augmented")
+    rp, col, val, ba = oracle.augmented_system(s.row_ptr, s.col, s.val64, b, s.n, zeta, 1.0)
+    N = s.n + s.m
+    ref = oracle.rk_run(rp, col, val, ba, N, np.zeros(N), 1.0, 30 * N, 8)
+    sysm = P.System(s.row_ptr, s.col, s.val, b, n=s.n, augmented=(zeta, 1.0))
+    z = np.zeros(N)
+    st = sysm.solve(z, 1.0, 30, 8, mode="replay")
+    assert st["status"] == "OK"
+    assert np.linalg.norm(z - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    sysm.close()
+
+
+def test_async_augmented_reaches_least_squares():
+    s, b = _inconsistent(4000, 1000, 10, 22)
+    A = s.dense()
+    x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+    zeta = np.linalg.svd(A, compute_uv=False).min() / np.sqrt(2)
+    _say("async augmented least squares")
+    sysm = P.System(_dev(s.row_ptr), _dev(s.col), _dev(s.val), _dev(b), n=s.n, augmented=(zeta, 1.0))
+    torch = _torch()
+    z = torch.zeros(s.n + s.m, dtype=torch.float64, device="cuda")
+    st = sysm.solve(z, 1.0, 3000, 3, tol=1e-13, check_every=10)
+    x = sysm.least_squares_x(z).cpu().numpy()
+    assert np.linalg.norm(x - x_ls) <= 1e-8 * np.linalg.norm(x_ls), (st["status"], st["sweeps_done"])
+    sysm.close()
