@@ -441,8 +441,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (a single system's "
+              "lock-free sweep does not shard within the paper's delay bound; independent "
+              "systems would be placed one GPU each).", file=sys.stderr)
         sys.exit(2)
     fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed,
           "serving": run_serving}[args.workload]

@@ -319,6 +319,9 @@ typedef struct asyrk_server_config {
     int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
     int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */
     double gamma;          /* step length in (0, 2), default 1 */
+    int64_t pinned_bytes;  /* pinned host staging for queued requests (uploads become one DMA
+                              each), default 4 GiB; 0 = none; a request that does not fit is
+                              uploaded from pageable memory */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {

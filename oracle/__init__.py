@@ -1,9 +1,9 @@
 """CPU oracle for the asynchronous randomized Kaczmarz sweep.
 
 TEST INFRASTRUCTURE ONLY: the plain, slow, sequential FP64 reference that the
-GPU library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()``
-and the CPU-baseline leg of ``bench.py`` may import it; the GPU library never
-does, and the two share no code.
+GPU library is checked against.  Only ``tests/``, the smoke check and the
+CPU-baseline leg of ``bench.py`` may import it; the GPU library never does,
+and the two share no code.
 
 The arithmetic lives in ``rk_oracle.c`` (plain C, ``-O2 -ffp-contract=off``,
 single thread); this module only builds it with gcc and marshals numpy arrays.

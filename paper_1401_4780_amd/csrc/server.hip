@@ -225,6 +225,9 @@ struct Request {
     int64_t R = 1;
     int64_t off_rec = -1, off_loc = -1, off_b = -1, off_x = -1, off_d = -1;
     int64_t bytes = 0;
+    int64_t rec_bytes = 0;    // packed record bytes
+    int64_t pin_off = -1;     // staging copy of rec | loc | b64 in the pinned arena, or -1
+    int64_t pin_bytes = 0;
     int64_t ticket = 0;
     int32_t rounds = 0;
     int64_t sweeps = 0;
@@ -243,6 +246,7 @@ struct asyrk_server {
     asyrk_server_config cfg{};
     hipStream_t st = nullptr;
     Arena arena;
+    Arena pinned;                  // host staging arena (pinned), guarded by mu
     TableHead *d_head = nullptr;
     SlotDesc *d_slots = nullptr;
     double *d_norm2 = nullptr;
@@ -298,6 +302,7 @@ void free_server(asyrk_server *s) {
     if (s->st) (void)hipStreamSynchronize(s->st);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     (void)hipFree(s->arena.base);
+    if (s->pinned.base) (void)hipHostFree(s->pinned.base);
     (void)hipFree(s->d_head);
     (void)hipFree(s->d_slots);
     (void)hipFree(s->d_norm2);
@@ -324,6 +329,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->max_rounds = 60;
     c->gamma = 1.0;
     c->use_graph = 1;
+    c->pinned_bytes = (int64_t)4 << 30;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
@@ -334,7 +340,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         cfg = *cfg_in;
     else
         asyrk_server_config_init(&cfg);
-    if (cfg.budget_bytes < (1 << 20) || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
+    if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
         !(cfg.gamma > 0.0 && cfg.gamma < 2.0))
         return ASYRK_ERR_INVALID_ARG;
@@ -349,6 +355,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_head, sizeof(TableHead), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_slots, sizeof(SlotDesc) * cfg.max_slots, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_norm2, sizeof(double) * cfg.max_slots, hipHostMallocDefault);
+    if (e == hipSuccess && cfg.pinned_bytes > 0)
+        e = hipHostMalloc((void **)&s->pinned.base, (size_t)cfg.pinned_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&s->e0);
     if (e == hipSuccess) e = hipEventCreate(&s->e1);
     if (e != hipSuccess) {
@@ -357,6 +365,10 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     }
     s->arena.size = cfg.budget_bytes;
     s->arena.free_[0] = cfg.budget_bytes;
+    if (cfg.pinned_bytes > 0) {
+        s->pinned.size = cfg.pinned_bytes;
+        s->pinned.free_[0] = cfg.pinned_bytes;
+    }
     s->sweep_blocks = (int)((cfg.max_workers * kSrvG + 255) / 256);
     std::memset(s->h_head, 0, sizeof(TableHead));
     if (cfg.use_graph) {
@@ -407,8 +419,29 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     r->fro2 = r->pack.fro2;
     const double q = std::sqrt((double)n / (double)m);
     r->lam = std::max((1.0 + q) * (1.0 + q) * r->fro2 / (double)n, r->pack.max_col_norm2);
+    r->rec_bytes = (int64_t)r->pack.rec.size();
     r->bytes = request_bytes(*r);
     if (r->bytes > s->cfg.budget_bytes) return ASYRK_ERR_OOM;
+    // stage rec | loc | b64 in pinned memory so admission is a plain DMA
+    const int64_t lrec = Arena::round_up((int64_t)r->pack.rec.size());
+    const int64_t lloc = Arena::round_up((int64_t)r->pack.loc.size() * 8);
+    const int64_t lb = Arena::round_up(m * 8);
+    if (s->pinned.base) {
+        int64_t off;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            off = s->pinned.alloc(lrec + lloc + lb);
+        }
+        if (off >= 0) {
+            uint8_t *p = s->pinned.base + off;
+            std::memcpy(p, r->pack.rec.data(), r->pack.rec.size());
+            if (!r->pack.loc.empty()) std::memcpy(p + lrec, r->pack.loc.data(), r->pack.loc.size() * 8);
+            std::memcpy(p + lrec + lloc, b, (size_t)m * 8);
+            r->pin_off = off;
+            r->pin_bytes = lrec + lloc + lb;
+            std::vector<uint8_t>().swap(r->pack.rec);  // the staged copy replaces it
+        }
+    }
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
     r->id = s->next_id++;
@@ -440,7 +473,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             r->off_rec = off;
         }
         Request &q = *r;
-        int64_t o = q.off_rec + Arena::round_up((int64_t)q.pack.rec.size());
+        int64_t o = q.off_rec + Arena::round_up(q.rec_bytes);
         q.off_loc = o;
         o += Arena::round_up((int64_t)q.pack.loc.size() * 8);
         q.off_b = o;
@@ -449,11 +482,18 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         o += Arena::round_up(q.n * 8);
         q.off_d = o;
         uint8_t *base = s->arena.base;
-        SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.pack.rec.size(), hipMemcpyHostToDevice, s->st));
-        if (!q.pack.loc.empty())
-            SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8, hipMemcpyHostToDevice,
+        if (q.pin_off >= 0) {
+            // one DMA of the staged rec | loc | b64 block (same relative layout)
+            SRV_OK(hipMemcpyAsync(base + q.off_rec, s->pinned.base + q.pin_off, q.pin_bytes, hipMemcpyHostToDevice,
                                   s->st));
-        SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->st));
+        } else {
+            SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.pack.rec.size(), hipMemcpyHostToDevice,
+                                  s->st));
+            if (!q.pack.loc.empty())
+                SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8,
+                                      hipMemcpyHostToDevice, s->st));
+            SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->st));
+        }
         SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->st));
         q.t_admit = now_s();
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
@@ -516,6 +556,14 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     float ms = 0.f;
     SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
     s->stats.gpu_seconds += ms * 1e-3;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : s->active)
+            if (r->pin_off >= 0) {
+                s->pinned.release(r->pin_off, r->pin_bytes);
+                r->pin_off = -1;
+            }
+    }
     s->stats.rounds++;
     // ---- bookkeeping and retirement
     std::vector<std::unique_ptr<Request>> keep;

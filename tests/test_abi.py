@@ -158,7 +158,9 @@ def test_server_config_validation():
     c = P.ServerConfig()
     L.asyrk_server_config_init(C.byref(c))
     assert c.budget_bytes == 64 << 30 and c.use_graph == 1 and c.max_workers == 65536
-    for field, bad in (("gamma", 2.0), ("max_slots", 0), ("inner_sweeps", 0), ("budget_bytes", 10)):
+    assert c.inner_sweeps == 8 and c.pinned_bytes == 4 << 30
+    for field, bad in (("gamma", 2.0), ("max_slots", 0), ("inner_sweeps", 0), ("budget_bytes", 10),
+                       ("pinned_bytes", -1)):
         d = P.ServerConfig()
         L.asyrk_server_config_init(C.byref(d))
         setattr(d, field, bad)

@@ -60,12 +60,13 @@ def _check(s, res):
     assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_server_solves_a_mixed_stream(use_graph):
-    _say(f"server mixed stream graph={use_graph}")
+@pytest.mark.parametrize("use_graph,pinned", [(True, 1 << 30), (False, 0), (True, 8 << 20)])
+def test_server_solves_a_mixed_stream(use_graph, pinned):
+    """pinned = 8 MiB holds only the small requests: both upload paths in one run."""
+    _say(f"server mixed stream graph={use_graph} pinned={pinned}")
     sizes = [1000, 1500, 4000, 12000, 30000, 2000, 800, 60000, 5000, 1000]
     systems = _systems(range(100, 110), sizes)
-    with P.Server(budget_bytes=1 << 30, use_graph=use_graph) as srv:
+    with P.Server(budget_bytes=1 << 30, use_graph=use_graph, pinned_bytes=pinned) as srv:
         res = _run_all(srv, systems)
         for s, r in zip(systems, res):
             _check(s, r)
