@@ -481,3 +481,23 @@ def test_async_augmented_reaches_least_squares():
     x = sysm.least_squares_x(z).cpu().numpy()
     assert np.linalg.norm(x - x_ls) <= 1e-8 * np.linalg.norm(x_ls), (st["status"], st["sweeps_done"])
     sysm.close()
+
+
+def test_skewed_rows_default_in_flight_respects_corollary():
+    """Zipf columns make lambda_max large (a hot column sits in most rows), so
+    Corollary 1 allows only a few workers.  The library's default R stays
+    within the bound and converges; 64x that many workers diverges."""
+    s = synth.skewed_rows(200_000, 50_000, seed=2, dtype="f32")
+    _say("skewed default in-flight")
+    sysm = make_system(s, device=True)
+    info = sysm.info()
+    lam, tau_max = sysm.lambda_max(iters=60, seed=1)
+    R0 = info["default_in_flight"]
+    assert info["max_col_norm2"] <= lam * (1 + 1e-9)  # a column norm^2 bounds lambda_max below
+    assert R0 - 1 <= max(tau_max, 0) + 1
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=4, seed=3, history=8)
+    h = st["history"]
+    assert st["in_flight"] == R0 and np.all(np.diff(h) < 0)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=4, seed=3, in_flight=64 * R0 + 64)
+    assert st["status"] == "DIVERGED" or st["final_err"] > h[-1] * 10
+    sysm.close()
