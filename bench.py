@@ -65,11 +65,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(s, target_s=12.0):
+def cpu_baseline(s, target_s=15.0):
     """Sequential FP64 oracle on a bounded sample of the same system."""
     import oracle
     x0 = np.zeros(s.n)
-    probe = 200_000
+    probe = 2_000_000
     t0 = time.perf_counter()
     oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, probe, 7)
     rate0 = probe / (time.perf_counter() - t0)

@@ -501,3 +501,40 @@ def test_skewed_rows_default_in_flight_respects_corollary():
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=4, seed=3, in_flight=64 * R0 + 64)
     assert st["status"] == "DIVERGED" or st["final_err"] > h[-1] * 10
     sysm.close()
+
+
+def test_set_rhs_refreshes_fp64_side_records():
+    """After set_rhs, an FP64-iterate solve of an FP32 system uses the new b."""
+    s = synth.uniform_rows(20_000, 5_000, 12, seed=31, dtype="f32")
+    _say("set_rhs with f64 side records")
+    sysm = make_system(s, device=False)
+    x = np.zeros(s.n)
+    st = sysm.solve(x, 1.0, 200, 1, tol=1e-10, x_ref=s.x_star, iter_dtype="f64", in_flight=256)
+    assert st["status"] == "OK"
+    x2 = np.random.default_rng(5).standard_normal(s.n)
+    A = __import__("scipy.sparse", fromlist=["csr_matrix"]).csr_matrix((s.val64, s.col, s.row_ptr),
+                                                                       shape=(s.m, s.n))
+    sysm.set_rhs(A @ x2)
+    x = np.zeros(s.n)
+    st = sysm.solve(x, 1.0, 200, 2, tol=1e-10, x_ref=x2, iter_dtype="f64", in_flight=256)
+    assert st["status"] == "OK"
+    assert np.linalg.norm(x - x2) <= 1.05e-10 * np.linalg.norm(x2)
+    sysm.close()
+
+
+def test_replay_bf16_ragged_slices_and_alg1_norm2():
+    """BF16 ragged rows under the slice scheme with an FP64 iterate, and
+    Algorithm 1's step with norm-weighted rows: both against the oracle."""
+    rng = np.random.default_rng(33)
+    s = synth.ragged_rows(900, 300, rng.integers(1, 70, 900), seed=33, dtype="bf16")
+    _say("replay bf16 ragged slices / alg1 norm2")
+    ref = oracle_run(s, 0.8, 6, 4, slices=True, workers=1)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=0.8, sweeps=6, seed=4, mode="replay", order="slices",
+                      iter_dtype="f64")
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    ref1 = oracle_run(s, 0.05, 6, 4, update_one=True)
+    x, st = gpu_solve(sysm, s, True, gamma=0.05, sweeps=6, seed=4, mode="replay", update="one",
+                      iter_dtype="f64")
+    assert np.linalg.norm(x - ref1["x"]) <= 1e-12 * np.linalg.norm(ref1["x"])
+    sysm.close()

@@ -124,3 +124,35 @@ def test_budget_admission_and_continuous_batching():
         with pytest.raises(P.AsyrkError) as ei:
             srv.submit(big.row_ptr, big.col, big.val, big.b, n=big.n)
         assert ei.value.name == "OOM"
+
+
+def test_concurrent_submitters_while_rounds_run():
+    """submit() from several threads while one thread drives progress()."""
+    import threading
+    _say("server concurrent submitters")
+    systems = _systems(range(400, 424), [1000 + 700 * k for k in range(24)])
+    ids = [None] * len(systems)
+    with P.Server(budget_bytes=1 << 30) as srv:
+        def worker(lo):
+            for k in range(lo, len(systems), 4):
+                s = systems[k]
+                ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+        for t in threads:
+            t.start()
+        out = {}
+        for _ in range(3000):
+            srv.progress()
+            for k in range(len(systems)):
+                if k not in out and ids[k] is not None:
+                    r = srv.poll(ids[k], n=systems[k].n)
+                    if r is not None:
+                        out[k] = r
+            if len(out) == len(systems):
+                break
+        for t in threads:
+            t.join()
+        assert len(out) == len(systems)
+        for k, s in enumerate(systems):
+            _check(s, out[k])
+        assert len(set(ids)) == len(ids)
