@@ -105,9 +105,10 @@ def run_c2(args):
     x = torch.zeros(N, dtype=torch.float64, device=dev)
     tuned = None
     if args.lanes == 0:
-        best, rates = sysm.autotune(GAMMA, in_flight=args.in_flight)
-        tuned = {"best_lanes": best, "rows_per_s_by_lanes": rates}
-        log(f"autotune: G={best} {rates}")
+        best, pipe, rates = sysm.autotune(GAMMA, in_flight=args.in_flight)
+        tuned = {"best_lanes": best, "pipelined": pipe,
+                 "rows_per_s": {f"G={g}{' pipelined' if p else ''}": r for (g, p), r in rates.items()}}
+        log(f"autotune: G={best} pipelined={pipe} {tuned['rows_per_s']}")
 
     def solve(seed, R=args.in_flight):
         x.zero_()
@@ -154,7 +155,8 @@ def run_c2(args):
         "data": "synthetic",
         "config": {"workload": "asyrk_4Mx1M_nnz20_f32_to_1e-6", "m": M, "n": N, "nnz_per_row": NNZ,
                    "gamma": GAMMA, "tol": TOL, "in_flight": sts[0]["in_flight"],
-                   "lanes": sts[0]["lanes"], "record_stride_bytes": info["record_stride"]},
+                   "lanes": sts[0]["lanes"], "pipelined": sts[0]["pipelined"],
+                   "record_stride_bytes": info["record_stride"]},
         "time_to_tol_s_p50": float(np.percentile(lat, 50)),
         "time_to_tol_s_p99": float(np.percentile(lat, 99)),
         "sweeps_to_tol_mean": launches / args.steps,
@@ -165,7 +167,8 @@ def run_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "sweep_kernel<F32,G>", "algorithmic_bytes_per_row": bytes_per_row,
+                     "kernel": ("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
+                     + f"<F32,F32,{sts[0]['lanes']}>", "algorithmic_bytes_per_row": bytes_per_row,
                      "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
     }
 
@@ -210,6 +213,18 @@ def run_c2(args):
         result["slices_without_replacement"] = {
             "sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"], "status": st["status"],
             "time_to_tol_s": time.perf_counter() - t1}
+        # Algorithm 1 (the analysed variant): one coordinate and one atomic per row,
+        # uniform rows, gamma = 1/psi = 1/mu (Corollary 1 with tau -> 0)
+        x.zero_()
+        t1 = time.perf_counter()
+        st = sysm.solve(x, 1.0 / NNZ, 600, 13, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
+                        update="one", sampling="uniform", check_every=10)
+        kbytes = info["record_bytes_per_row"] * M
+        result["algorithm1_single_coordinate"] = {
+            "sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"], "status": st["status"],
+            "final_err": st["final_err"], "time_to_tol_s": time.perf_counter() - t1,
+            "algorithmic_GBps": kbytes * st["rows_per_s"] / M / 1e9,
+            "hbm_roofline_frac": kbytes * st["rows_per_s"] / M / 1e9 / HBM_PEAK_GBPS}
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -349,7 +364,10 @@ def run_serving(args):
         m, n = (int(v) for v in specs[rid])
         return synth.serving_system(rid, m, n)
 
-    srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}))
+    srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}),
+                   **({"lanes": args.lanes} if args.lanes in (4, 8) else {}),
+                   **({"max_workers": args.max_workers} if args.max_workers else {}),
+                   **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}))
 
     def drive(first, count, arrivals):
         """Submit requests first..first+count-1 at their arrival times (seconds
@@ -359,36 +377,45 @@ def run_serving(args):
         ids = [None] * count
         sub_pool = ThreadPoolExecutor(8)
 
+        id_of = {}
+
         def submit(k):
             delay = t0 + arrivals[k] - P.now()
             if delay > 0:
                 time.sleep(delay)
             s = systems[k]
             ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=tol, seed=first + k)
+            id_of[ids[k]] = k
 
+        st0 = srv.stats()
         futs = [sub_pool.submit(submit, k) for k in range(count)]
         done, lat, sweeps, bad = {}, [], [], 0
         while len(done) < count:
             active, queued = srv.progress()
             if active == 0 and queued == 0:
                 time.sleep(0.0005)
-            for k in range(count):
-                if k in done or ids[k] is None:
-                    continue
-                r = srv.poll(ids[k])
-                if r is not None:
-                    status, st, _ = r
-                    done[k] = st
-                    lat.append(st["t_done"] - (t0 + arrivals[k]))
-                    sweeps.append(st["sweeps"])
-                    bad += status != "OK" or st["rel_residual"] > tol
+            for rid in srv.take_completed():
+                while rid not in id_of:  # its submit call is still returning
+                    time.sleep(0.0001)
+                k = id_of[rid]
+                status, st, _ = srv.poll(rid)
+                done[k] = st
+                lat.append(st["t_done"] - (t0 + arrivals[k]))
+                sweeps.append(st["sweeps"])
+                bad += status != "OK" or st["rel_residual"] > tol
         for f in futs:
             f.result()
         t_end = max(st["t_done"] for st in done.values())
         sub_pool.shutdown()
+        st1 = srv.stats()
+        gpu_s = st1["gpu_seconds"] - st0["gpu_seconds"]
         return {"solves_per_s": count / (t_end - t0), "latency_s_p50": float(np.percentile(lat, 50)),
                 "latency_s_p99": float(np.percentile(lat, 99)), "mean_sweeps": float(np.mean(sweeps)),
-                "failed": int(bad)}
+                "failed": int(bad),
+                # row updates per second of round time on the GPU, and the share of
+                # wall time the GPU spent in rounds
+                "gpu_rows_per_s": (st1["row_updates"] - st0["row_updates"]) / max(gpu_s, 1e-9),
+                "gpu_busy_frac": gpu_s / (t_end - t0), "rounds": st1["rounds"] - st0["rounds"]}
 
     # saturation: every request present at t = 0
     sat = drive(0, n_req, np.zeros(n_req))
@@ -420,7 +447,9 @@ def run_serving(args):
             "vs_baseline": None, "data": "synthetic", "dtype": "f32 sweeps, f64 refinement",
             "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8",
                        "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
-                       "inner_sweeps_per_round": srv.config["inner_sweeps"]},
+                       "inner_sweeps_per_round": srv.config["inner_sweeps"],
+                       "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
+                       "pipe_workers": srv.config["pipe_workers"]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
@@ -437,6 +466,9 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="refinement inner sweeps (0: default)")
     ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed", "serving"])
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
+    ap.add_argument("--max-workers", type=int, default=0, help="serving: total row workers (0: default)")
+    ap.add_argument("--pipe-workers", type=int, default=-1,
+                    help="serving: pipelined rounds up to this many workers (-1: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
     args = ap.parse_args()

@@ -120,6 +120,16 @@ typedef struct asyrk_solve_params {
                                 them once per sweep in a keyed permutation (see
                                 "Slice permutation"); needs UPDATE_ALL and ticket0 a
                                 multiple of m */
+    int32_t pipeline;        /* worker loop: 1 = pipelined (each worker fetches its next
+                                ticket's row while the current one gathers and scatters:
+                                same arithmetic and reads of x, two dependent memory
+                                round trips per ticket; faster when few workers are in
+                                flight, slower when the atomic unit is saturated); needs
+                                ASYNC, UPDATE_ALL, order 0, no trace.  0 = plain.
+                                -1 (set by asyrk_solve_params_init) = the autotuned
+                                choice when the autotuner ran at this R and G, else
+                                pipelined for R <= 8192 where allowed */
+    int32_t reserved;        /* must be 0 */
 } asyrk_solve_params;
 
 /* Slice permutation (order = 1), for sweep s (= ticket / m) and worker w:
@@ -139,6 +149,8 @@ typedef struct asyrk_solve_stats {
     int64_t in_flight;         /* R used */
     int32_t lanes;             /* G used */
     int32_t outer_iters;       /* refinement outer iterations (0 without refinement) */
+    int32_t pipelined;         /* 1 if the pipelined worker loop ran */
+    int32_t reserved;
     double seconds;            /* wall time of the call after setup */
     double sweep_seconds;      /* GPU time of the sweep kernels (HIP events) */
     double rows_per_s;         /* row_updates / sweep_seconds */
@@ -271,15 +283,17 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
 
 /*
  * Autotuner: times one sweep (at least 2^21 tickets) from x = 0 for each
- * lane-group width G in {1, 2, 4, 8, 16} on this system, at in_flight workers
- * (0 = the default R) and the given iterate dtype (-1 = default), and keeps
- * the fastest G for later solves with lanes = 0.  best_lanes (nullable)
- * receives it; rows_per_s (nullable, double[5]) the rate of each candidate.
- * The system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,
+ * lane-group width G in {1, 2, 4, 8, 16} and each worker loop (plain,
+ * pipelined) on this system, at in_flight workers (0 = the default R) and the
+ * given iterate dtype (-1 = default), and keeps the fastest pair for later
+ * solves with lanes = 0 and pipeline = -1 at that R.  best_lanes and
+ * best_pipeline (nullable) receive it; rows_per_s (nullable, double[10]) the
+ * rate of each candidate: [0..4] plain, [5..9] pipelined, G ascending.  The
+ * system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,
  * DEVICE.
  */
 asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
-                            int32_t *best_lanes, double *rows_per_s);
+                            int32_t *best_lanes, int32_t *best_pipeline, double *rows_per_s);
 
 /*
  * Device ceilings used to read the roofline (no system needed):
@@ -322,6 +336,11 @@ typedef struct asyrk_server_config {
     int64_t pinned_bytes;  /* pinned host staging for queued requests (uploads become one DMA
                               each), default 4 GiB; 0 = none; a request that does not fit is
                               uploaded from pageable memory */
+    int32_t lanes;         /* lanes per row in the packed sweep: 4 or 8 (each keeps rows of up
+                              to 64 entries in registers), default 4 */
+    int32_t pipe_workers;  /* rounds whose active systems hold at most this many row workers
+                              run the pipelined worker loop (see asyrk_solve_params.pipeline),
+                              default 8192; 0 = never */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {
@@ -366,6 +385,11 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
  * queued or active, INVALID_ARG for an unknown or already-polled id. */
 asyrk_status asyrk_server_poll(asyrk_server *s, int64_t request_id, double *x_out,
                                asyrk_request_stats *st);
+
+/* Ids of requests that finished since the last call (up to cap, oldest
+ * first); *count receives how many were written.  Each id is reported once;
+ * fetch its result with asyrk_server_poll.  Errors: INVALID_ARG. */
+asyrk_status asyrk_server_take_completed(asyrk_server *s, int64_t *ids, int64_t cap, int64_t *count);
 
 /* Counters of the server. */
 asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out);

@@ -53,7 +53,7 @@ class SolveParams(C.Structure):
         ("check_every", C.c_int32), ("refine", C.c_int32), ("inner_sweeps", C.c_int64),
         ("stream_id", C.c_uint32), ("trace", C.c_int32), ("ticket0", C.c_int64),
         ("cancel", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int64),
-        ("iter_dtype", C.c_int32), ("order", C.c_int32),
+        ("iter_dtype", C.c_int32), ("order", C.c_int32), ("pipeline", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -61,7 +61,8 @@ class SolveStats(C.Structure):
     _fields_ = [
         ("sweeps_done", C.c_int64), ("row_updates", C.c_int64), ("next_ticket", C.c_int64),
         ("history_len", C.c_int64), ("in_flight", C.c_int64), ("lanes", C.c_int32),
-        ("outer_iters", C.c_int32), ("seconds", C.c_double), ("sweep_seconds", C.c_double),
+        ("outer_iters", C.c_int32), ("pipelined", C.c_int32), ("reserved", C.c_int32),
+        ("seconds", C.c_double), ("sweep_seconds", C.c_double),
         ("rows_per_s", C.c_double), ("final_err", C.c_double), ("tau_design", C.c_double),
         ("tau_obs_mean", C.c_double), ("tau_obs_max", C.c_double), ("window_ns_mean", C.c_double),
         ("window_ns_max", C.c_double),
@@ -82,7 +83,7 @@ class ServerConfig(C.Structure):
     _fields_ = [
         ("budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("inner_sweeps", C.c_int32),
         ("max_workers", C.c_int64), ("max_rounds", C.c_int32), ("use_graph", C.c_int32),
-        ("gamma", C.c_double), ("pinned_bytes", C.c_int64),
+        ("gamma", C.c_double), ("pinned_bytes", C.c_int64), ("lanes", C.c_int32), ("pipe_workers", C.c_int32),
     ]
 
 
@@ -134,7 +135,7 @@ def lib():
     L.asyrk_residual.argtypes = [P, P, P, P]
     L.asyrk_sample_rows.argtypes = [P, u64, u32, i32, i64, i64, P, P]
     L.asyrk_lambda_max.argtypes = [P, i32, u64, P, P]
-    L.asyrk_autotune.argtypes = [P, dbl, i32, i64, P, P]
+    L.asyrk_autotune.argtypes = [P, dbl, i32, i64, P, P, P]
     L.asyrk_probe_copy.argtypes = [i64, i32, P]
     L.asyrk_probe_scatter.argtypes = [i64, i64, i32, i32, i32, P]
     L.asyrk_server_config_init.argtypes = [P]
@@ -145,13 +146,14 @@ def lib():
     L.asyrk_server_progress.argtypes = [P, P, P]
     L.asyrk_server_poll.argtypes = [P, i64, P, P]
     L.asyrk_server_stats_get.argtypes = [P, P]
+    L.asyrk_server_take_completed.argtypes = [P, P, i64, P]
     L.asyrk_now.argtypes = []
     L.asyrk_now.restype = dbl
     for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
-                 "asyrk_server_poll", "asyrk_server_stats_get"):
+                 "asyrk_server_poll", "asyrk_server_stats_get", "asyrk_server_take_completed"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -308,19 +310,20 @@ class System:
         return lam.value, tau.value
 
     def autotune(self, gamma=1.0, iter_dtype=None, in_flight=0):
-        """Time one sweep per lane-group width; the fastest becomes the default.
-        Returns (best G, {G: rows/s})."""
-        best = C.c_int32()
-        rates = (C.c_double * 5)()
+        """Time one sweep per lane-group width and worker loop; the fastest pair
+        becomes the default at this R.  Returns (best G, pipelined?, {(G, pipelined): rows/s})."""
+        best, pipe = C.c_int32(), C.c_int32()
+        rates = (C.c_double * 10)()
         _check(lib().asyrk_autotune(self._h, float(gamma), {None: -1, "f32": F32, "f64": F64}[iter_dtype],
-                                    int(in_flight), C.byref(best), rates), "asyrk_autotune")
-        return best.value, dict(zip((1, 2, 4, 8, 16), list(rates)))
+                                    int(in_flight), C.byref(best), C.byref(pipe), rates), "asyrk_autotune")
+        keys = [(g, p) for p in (False, True) for g in (1, 2, 4, 8, 16)]
+        return best.value, bool(pipe.value), dict(zip(keys, list(rates)))
 
     # -- the method
     def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
               update="all", lanes=0, in_flight=0, tol=0.0, x_ref=None, check_every=1,
               refine=False, inner_sweeps=0, stream_id=0, trace=False, ticket0=0, cancel=None,
-              history=0, iter_dtype=None, order="replacement") -> dict:
+              history=0, iter_dtype=None, order="replacement", pipeline=None) -> dict:
         """Run from x (float64, overwritten with the result).  Returns the stats
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
         "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
@@ -344,6 +347,7 @@ class System:
         p.ticket0 = ticket0
         p.iter_dtype = {None: -1, "f32": F32, "f64": F64}[iter_dtype]
         p.order = {"replacement": 0, "slices": 1}[order]
+        p.pipeline = -1 if pipeline is None else int(bool(pipeline))
         if cancel is not None:
             if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):
                 raise TypeError("cancel: expected a numpy int32 array")
@@ -433,6 +437,14 @@ class Server:
         if rc not in (0, 5, 6):
             _check(rc, "asyrk_server_poll")
         return STATUS[rc], {f: getattr(st, f) for f, _ in RequestStats._fields_}, x
+
+    def take_completed(self, cap=4096):
+        """Ids of requests finished since the last call."""
+        ids = np.empty(cap, dtype=np.int64)
+        cnt = C.c_int64()
+        _check(lib().asyrk_server_take_completed(self._h, _ptr(ids), cap, C.byref(cnt)),
+               "asyrk_server_take_completed")
+        return ids[: cnt.value].tolist()
 
     def stats(self) -> dict:
         st = ServerStats()

@@ -35,6 +35,8 @@ struct asyrk_system {
     int64_t device_bytes = 0;
     bool rec_b_dirty = false;
     int tuned_G[2] = {0, 0};      // autotuned lanes per row for F64 / F32 iterates (0 = none)
+    int tuned_pipe[2] = {0, 0};   // autotuned worker loop (1 = pipelined) for F64 / F32 iterates
+    int64_t tuned_R[2] = {0, 0};  // the R those were tuned at
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
@@ -108,6 +110,11 @@ asyrk_status fetch_scalar(asyrk_system *s, int nparts, double *host_out) {
     *host_out = s->h_pin[0];
     return ASYRK_OK;
 }
+
+// Without autotuning, the pipelined worker loop is used up to this many
+// workers: below it the sweep is bound by each worker's memory latency, above
+// it by the atomic unit, where the plain loop measured faster.
+constexpr int64_t kPipeMaxR = 8192;
 
 int auto_lanes(const asyrk_system *s, int64_t R) {
     const Geom g = geom_of(s->vk);
@@ -204,6 +211,7 @@ void asyrk_solve_params_init(asyrk_solve_params *p) {
     p->update = ASYRK_UPDATE_ALL;
     p->check_every = 1;
     p->iter_dtype = -1;
+    p->pipeline = -1;
 }
 
 asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
@@ -477,7 +485,7 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
 }
 
 asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
-                            int32_t *best_lanes, double *rows_per_s_out) {
+                            int32_t *best_lanes, int32_t *best_pipeline, double *rows_per_s_out) {
     if (!s || !(gamma > 0.0 && gamma < 2.0) || in_flight < 0) return ASYRK_ERR_INVALID_ARG;
     if (iter_dtype != -1 && iter_dtype != ASYRK_F32 && iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
     const int xk = iter_dtype >= 0 ? iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
@@ -496,22 +504,31 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
     // at least one sweep and at least 2M tickets per candidate
     const int64_t tickets = std::max<int64_t>(s->m, (int64_t)2 << 20);
     const int cands[5] = {1, 2, 4, 8, 16};
-    int best = 0;
+    int best = 0, best_pipe = 0;
     double best_rate = 0.0;
-    for (int G : cands) {
-        HIP_OK(launch_zero(s->d_x, s->n * 8, s->st));
-        double gpu_s = 0.0, a = 0, b = 0, c = 0;
-        asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &a, &b, &c);
-        if (rc) return rc;
-        const double rate = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
-        if (rate > best_rate) {
-            best_rate = rate;
-            best = G;
+    for (int pipe = 0; pipe < 2; ++pipe) {
+        p.pipeline = pipe;
+        for (int k = 0; k < 5; ++k) {
+            const int G = cands[k];
+            HIP_OK(launch_zero(s->d_x, s->n * 8, s->st));
+            double gpu_s = 0.0, a = 0, b = 0, c = 0;
+            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &a, &b, &c);
+            if (rc) return rc;
+            const double rate = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = G;
+                best_pipe = pipe;
+            }
+            if (rows_per_s_out) rows_per_s_out[5 * pipe + k] = rate;
         }
-        if (rows_per_s_out) rows_per_s_out[G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4] = rate;
     }
-    s->tuned_G[xk == ASYRK_F32 ? 1 : 0] = best;
+    const int xi = xk == ASYRK_F32 ? 1 : 0;
+    s->tuned_G[xi] = best;
+    s->tuned_pipe[xi] = best_pipe;
+    s->tuned_R[xi] = R;
     if (best_lanes) *best_lanes = best;
+    if (best_pipeline) *best_pipeline = best_pipe;
     return ASYRK_OK;
 }
 
@@ -550,6 +567,7 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     a.gamma = gamma;
     a.trace = p.trace ? s->d_trace : nullptr;
     a.slices = p.order;
+    a.pipe = p.pipeline;
     HIP_OK(hipEventRecord(s->e0, s->st));
     if (p.order == 1)
         HIP_OK(launch_sweep_slices(s->vk, xk, G, a, s->st));
@@ -592,6 +610,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
         return ASYRK_ERR_INVALID_ARG;
     if (p.order != 0 && p.order != 1) return ASYRK_ERR_INVALID_ARG;
+    if (p.pipeline < -1 || p.pipeline > 1 || p.reserved != 0) return ASYRK_ERR_INVALID_ARG;
+    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL || p.order != 0 || p.trace))
+        return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
     if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
@@ -601,10 +622,16 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.refine && (p.mode == ASYRK_REPLAY || p.update == ASYRK_UPDATE_ONE)) return ASYRK_ERR_UNSUPPORTED;
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
-    const int tuned = s->tuned_G[xk == ASYRK_F32 ? 1 : 0];
+    const int xi = xk == ASYRK_F32 ? 1 : 0;
+    const int tuned = s->tuned_G[xi];
     int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
     const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
+    if (p.pipeline == -1) {
+        const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && p.order == 0 && !p.trace;
+        const bool tuned_here = tuned && s->tuned_R[xi] == R && G == tuned;
+        p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
+    }
     const bool f32 = xk == ASYRK_F32;
     const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2h = s->mem == ASYRK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
@@ -614,6 +641,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     S.final_err = NAN;
     S.in_flight = R;
     S.lanes = G;
+    S.pipelined = p.pipeline;
     S.tau_design = (double)(R - 1);
 
     // inputs

@@ -28,6 +28,19 @@ __device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t 
     }
 }
 
+// 64 zero bytes: the read-only stand-in for an absent unit or row locator,
+// so that loads can be issued unconditionally (no branch, no wait at a join).
+static __device__ __attribute__((aligned(64))) const uint8_t kZeroPad[64] = {0};
+
+// locate() without a branch: the locator is read from kZeroPad for
+// fixed-stride rows and the values are picked by select.
+__device__ __forceinline__ void locate_nb(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
+    const bool ragged = r.loc != nullptr;
+    const RowLoc l = *(ragged ? r.loc + i : reinterpret_cast<const RowLoc *>(kZeroPad));
+    rec = ragged ? r.rec + (int64_t)l.off16 * 16 : r.rec + (int64_t)i * r.stride;
+    nnz = ragged ? (int)l.nnz : r.fixed_nnz;
+}
+
 template <int VK> struct Unit;
 template <> struct Unit<ASYRK_F32> {
     int c[4];
@@ -236,6 +249,148 @@ __device__ __forceinline__ uint64_t process_ticket(
         unsafeAtomicAdd(x + c, -s1 * (X)v);
     }
     return trace ? wall_clock64() - t0 : 0;
+}
+
+// The tickets j0, j0 + step, ... < j_end of one worker with the steps of
+// process_ticket (sampled rows, all-coordinate update), arranged so that a
+// ticket costs two dependent memory round trips instead of one per access:
+//
+//   1. the next ticket's row locator is requested together with this
+//      ticket's gathers, which are issued back to back (padded slots read
+//      x[0] and are masked out by a select, so no branch splits them) and
+//      waited for once;
+//   2. the atomics are issued while no load is outstanding, then the next
+//      ticket's record is requested; its wait overlaps the atomics.
+//
+// Row records are read-only during a sweep, so fetching the next record
+// early moves no read of x: the gathers of ticket t + 1 are still issued
+// after the atomics of ticket t.
+template <int VK, int XK, int G, int UPL = Upl<G>::value>
+__device__ __forceinline__ void run_tickets_pipelined(
+    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
+    const double2 *side, int64_t j, int64_t j_end, int64_t step, uint32_t stream_id, uint32_t k0,
+    uint32_t k1, int uniform, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma,
+    int gl) {
+    using T = VT<VK>;
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    using H = typename T::hdr_t;
+    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
+    constexpr int U = T::U;
+    if (j >= j_end) return;
+
+    // units base + gl, base + gl + G, ... of a row; absent units are read
+    // from kZeroPad, so every load is issued unconditionally
+    static_assert(T::UB <= (int)sizeof(kZeroPad), "zero pad smaller than a unit");
+    auto fetch_chunk = [&](const uint8_t *rec, int base, int nunits, Unit<VK> *dst) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int uu = base + gl + q * G;
+            dst[q].load(uu < nunits ? rec + T::HB + (int64_t)uu * T::UB : kZeroPad);
+        }
+    };
+    auto fetch_units = [&](const uint8_t *rec, int nunits, Unit<VK> *dst) { fetch_chunk(rec, 0, nunits, dst); };
+    // branch-free gather-dot of one chunk held in registers
+    auto chunk_dot = [&](const Unit<VK> *cu, int base, int nnz, X acc) {
+        X xv[UPL][U];
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const bool ok = (base + gl + q * G) * U + e < nnz;
+                xv[q][e] = load_agent(x + (ok ? cu[q].c[e] : 0));
+            }
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const bool ok = (base + gl + q * G) * U + e < nnz;
+                acc = ok ? fma((X)cu[q].v[e], xv[q][e], acc) : acc;
+            }
+        return acc;
+    };
+    auto chunk_scatter = [&](const Unit<VK> *cu, int base, int nnz, X s) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e)
+                if ((base + gl + q * G) * U + e < nnz) unsafeAtomicAdd(x + cu[q].c[e], -s * (X)cu[q].v[e]);
+    };
+    // the alias branch of the draw (needs the bucket row's header)
+    auto resolve = [&](const U4 &u, uint32_t &i, const uint8_t *&rec, int &nnz, H &h, Unit<VK> *dst) {
+        if (!uniform && !(u.c < h.thresh)) {
+            i = (uint32_t)h.alias;
+            locate_nb(rows, i, rec, nnz);
+            h = load_hdr<VK>(rec);
+            fetch_units(rec, (nnz + U - 1) / U, dst);
+        }
+    };
+    auto coeffs = [&](uint32_t i, const H &h, X &bi, X &inv_w) {
+        if constexpr (SIDE) {
+            const double2 sd = side[i];
+            bi = sd.x;
+            inv_w = sd.y;
+        } else {
+            bi = (X)h.b;
+            inv_w = (X)h.inv_w;
+        }
+    };
+
+    // prologue: the first ticket, fetched in full
+    U4 u = draw(j, stream_id, k0, k1);
+    uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+    const uint8_t *rec;
+    int nnz;
+    locate_nb(rows, i, rec, nnz);
+    H h = load_hdr<VK>(rec);
+    Unit<VK> un[UPL];
+    fetch_units(rec, (nnz + U - 1) / U, un);
+    resolve(u, i, rec, nnz, h, un);
+    X bi, inv_w;
+    coeffs(i, h, bi, inv_w);
+
+    for (;;) {
+        const int64_t jn = j + step;
+        const bool more = jn < j_end;
+        // the next ticket's row and locator, requested with this ticket's gathers
+        // (drawn even past the end: the row is valid and simply not used)
+        U4 u2 = draw(jn, stream_id, k0, k1);
+        uint32_t i2 = bucket_of(u2.a, u2.b, (uint32_t)rows.m);
+        const uint8_t *rec2;
+        int nnz2;
+        locate_nb(rows, i2, rec2, nnz2);
+        // gather-dot: first chunk from registers, further chunks (long rows) re-read
+        const int nunits = (nnz + U - 1) / U;
+        X acc = chunk_dot(un, 0, nnz, (X)0);
+        for (int base = G * UPL; base < nunits; base += G * UPL) {
+            Unit<VK> t[UPL];
+            fetch_chunk(rec, base, nunits, t);
+            acc = chunk_dot(t, base, nnz, acc);
+        }
+        acc = group_sum<G>(acc);
+        const X s = gamma * (acc - bi) * inv_w;
+        // lock-free scatter
+        chunk_scatter(un, 0, nnz, s);
+        for (int base = G * UPL; base < nunits; base += G * UPL) {
+            Unit<VK> t[UPL];
+            fetch_chunk(rec, base, nunits, t);
+            chunk_scatter(t, base, nnz, s);
+        }
+        if (!more) break;
+        // the next ticket's record; its wait overlaps the atomics above
+        H h2 = load_hdr<VK>(rec2);
+        Unit<VK> un2[UPL];
+        fetch_units(rec2, (nnz2 + U - 1) / U, un2);
+        resolve(u2, i2, rec2, nnz2, h2, un2);
+        coeffs(i2, h2, bi, inv_w);
+        j = jn;
+        u = u2;
+        i = i2;
+        rec = rec2;
+        nnz = nnz2;
+        h = h2;
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) un[q] = un2[q];
+    }
 }
 
 // Keyed bijection of [0, L) for the slice scheme: with b the smallest width

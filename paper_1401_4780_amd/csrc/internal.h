@@ -35,7 +35,7 @@ struct SweepArgs {
     double gamma;
     uint64_t *trace;       // nullable: per worker {max window, sum window, count} in clock ticks
     int32_t slices;        // 1: without-replacement slice scheme (t_begin, t_end are sweep multiples)
-    int32_t pad;
+    int32_t pipe;          // 1: software-pipelined worker loop (asynchronous, all-coordinate, no trace)
 };
 
 // ---------------------------------------------------------------------------

@@ -46,6 +46,21 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     }
 }
 
+// The same worker loop with the steps of consecutive tickets overlapped
+// (run_tickets_pipelined): for asynchronous, all-coordinate sweeps without
+// tracing.
+template <int VK, int XK, int G>
+__global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / G) + (lane / G);
+    if (worker >= a.R) return;
+    run_tickets_pipelined<VK, XK, G>(a.rows, reinterpret_cast<X *>(a.x), a.side, a.t_begin + worker, a.t_end,
+                                     a.R, a.stream_id, a.key0, a.key1, a.uniform, (X)a.gamma, gl);
+}
+
 // Without-replacement slice scheme (the paper's experiments): worker w owns
 // rows [w L, min(m, (w + 1) L)), L = ceil(m / R), and visits them in a fresh
 // keyed permutation every sweep; one launch covers sweeps
@@ -116,6 +131,19 @@ static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     const int64_t threads = a.R * G;
     const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
     const int64_t grid = (threads + block - 1) / block;
+    if (a.pipe) {
+        switch (G) {
+            case 1: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
+            case 4: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
+            case 16: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+            case 32: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
+            case 64: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (G) {
         case 1: hipLaunchKernelGGL((sweep_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
         case 2: hipLaunchKernelGGL((sweep_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;

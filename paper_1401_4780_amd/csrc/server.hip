@@ -41,8 +41,6 @@ using namespace asyrk;
 
 namespace {
 
-constexpr int kSrvG = 8;             // lanes per row in the packed sweep; 2 units per lane keep
-                                     // rows of up to 64 FP32 entries in registers
 constexpr int kVecBlocks = 2048;     // grid of the flat vector/residual kernels
 
 struct SlotDesc {
@@ -93,18 +91,29 @@ __global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, cons
     }
 }
 
-__global__ __launch_bounds__(256) void srv_sweep_kernel(const TableHead *th, const SlotDesc *sl) {
+// G lanes per row with 16 / G units per lane: rows of up to 64 FP32 entries
+// stay in registers.  Four waves per SIMD keep the default 65536 workers
+// (x 4 lanes) resident at once.  PIPE: the pipelined worker loop, for rounds
+// with few workers (latency-bound); the plain loop saturates the atomic unit
+// better when many are active.
+template <int G, bool PIPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void srv_sweep_kernel(const TableHead *th, const SlotDesc *sl) {
     const int lane = threadIdx.x & 63;
-    const int gl = lane & (kSrvG - 1);
+    const int gl = lane & (G - 1);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t worker = wave * (64 / kSrvG) + (lane / kSrvG);
+    const int64_t worker = wave * (64 / G) + (lane / G);
     if (worker >= th->total_workers) return;
     const int s = find_slot(th->nact, worker, [&](int k) { return sl[k].w_off; });
-    const SlotDesc &d = sl[s];
+    const SlotDesc d = sl[s];  // a copy: the scatter cannot be taken to alias it
     const int64_t w = worker - d.w_off;
-    for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
-        process_ticket<ASYRK_F32, ASYRK_F32, kSrvG, 2>(d.rows, d.d, nullptr, j, 0u, d.key0, d.key1, 0, 0,
-                                                       d.gamma, gl, 0);
+    if constexpr (PIPE) {
+        run_tickets_pipelined<ASYRK_F32, ASYRK_F32, G, 16 / G>(d.rows, d.d, nullptr, d.t_begin + w, d.t_end, d.R,
+                                                               0u, d.key0, d.key1, 0, d.gamma, gl);
+    } else {
+        for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
+            process_ticket<ASYRK_F32, ASYRK_F32, G, 16 / G>(d.rows, d.d, nullptr, j, 0u, d.key0, d.key1, 0, 0,
+                                                             d.gamma, gl, 0);
+    }
 }
 
 __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, const SlotDesc *sl) {
@@ -253,14 +262,15 @@ struct asyrk_server {
     TableHead *h_head = nullptr;   // pinned
     SlotDesc *h_slots = nullptr;   // pinned
     double *h_norm2 = nullptr;     // pinned
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // plain / pipelined sweep
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    int sweep_blocks = 0;
+    int sweep_blocks[2] = {0, 0};
 
     std::mutex mu;
     std::deque<std::unique_ptr<Request>> queue;
     std::unordered_map<int64_t, std::unique_ptr<Request>> done;
     std::unordered_set<int64_t> live;  // submitted and not yet polled
+    std::vector<int64_t> finished;     // completed ids not yet reported by take_completed
     int64_t next_id = 1;
 
     std::vector<std::unique_ptr<Request>> active;  // progress() thread only
@@ -288,10 +298,21 @@ int64_t request_bytes(const Request &r) {
            Arena::round_up(r.m * 8) + Arena::round_up(r.n * 8) + Arena::round_up(r.n * 4) + 5 * 256;
 }
 
-hipError_t launch_round(asyrk_server *s, hipStream_t st) {
+hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
     const int wblocks = kVecBlocks;
+    const dim3 grid(s->sweep_blocks[pipe]);
     hipLaunchKernelGGL(srv_zero_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
-    hipLaunchKernelGGL(srv_sweep_kernel, dim3(s->sweep_blocks), dim3(256), 0, st, s->d_head, s->d_slots);
+    if (s->cfg.lanes == 4) {
+        if (pipe)
+            hipLaunchKernelGGL((srv_sweep_kernel<4, true>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+        else
+            hipLaunchKernelGGL((srv_sweep_kernel<4, false>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+    } else {
+        if (pipe)
+            hipLaunchKernelGGL((srv_sweep_kernel<8, true>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+        else
+            hipLaunchKernelGGL((srv_sweep_kernel<8, false>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+    }
     hipLaunchKernelGGL(srv_axpy_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots);
     hipLaunchKernelGGL(srv_residual_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
     return hipGetLastError();
@@ -300,7 +321,8 @@ hipError_t launch_round(asyrk_server *s, hipStream_t st) {
 void free_server(asyrk_server *s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
-    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    for (hipGraphExec_t g : s->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     (void)hipFree(s->arena.base);
     if (s->pinned.base) (void)hipHostFree(s->pinned.base);
     (void)hipFree(s->d_head);
@@ -330,6 +352,8 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->gamma = 1.0;
     c->use_graph = 1;
     c->pinned_bytes = (int64_t)4 << 30;
+    c->lanes = 4;
+    c->pipe_workers = 8192;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
@@ -342,7 +366,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         asyrk_server_config_init(&cfg);
     if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
-        !(cfg.gamma > 0.0 && cfg.gamma < 2.0))
+        !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 4 && cfg.lanes != 8) || cfg.pipe_workers < 0)
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
@@ -369,20 +393,24 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         s->pinned.size = cfg.pinned_bytes;
         s->pinned.free_[0] = cfg.pinned_bytes;
     }
-    s->sweep_blocks = (int)((cfg.max_workers * kSrvG + 255) / 256);
+    s->sweep_blocks[0] = (int)((cfg.max_workers * cfg.lanes + 255) / 256);
+    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.lanes + 255) / 256);
     std::memset(s->h_head, 0, sizeof(TableHead));
     if (cfg.use_graph) {
-        // capture the four phases once; they read the slot table, so the same
-        // graph serves every round whatever systems are active
-        hipGraph_t g = nullptr;
-        e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t le = launch_round(s, s->st);
-            e = hipStreamEndCapture(s->st, &g);
-            if (e == hipSuccess) e = le;
+        // capture the four phases once per sweep variant; they read the slot
+        // table, so the same graphs serve every round whatever systems are active
+        for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
+            if (pipe && cfg.pipe_workers == 0) break;
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t le = launch_round(s, s->st, pipe);
+                e = hipStreamEndCapture(s->st, &g);
+                if (e == hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[pipe], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
             free_server(s);
             return srv_fail(e);
@@ -546,10 +574,11 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     SRV_OK(hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(SlotDesc) * h.nact, hipMemcpyHostToDevice, s->st));
     // ---- run one round
     SRV_OK(hipEventRecord(s->e0, s->st));
-    if (s->graph)
-        SRV_OK(hipGraphLaunch(s->graph, s->st));
+    const int pipe = h.total_workers <= cfg.pipe_workers ? 1 : 0;
+    if (s->graph[pipe])
+        SRV_OK(hipGraphLaunch(s->graph[pipe], s->st));
     else
-        SRV_OK(launch_round(s, s->st));
+        SRV_OK(launch_round(s, s->st, pipe));
     SRV_OK(hipEventRecord(s->e1, s->st));
     SRV_OK(hipMemcpyAsync(s->h_norm2, s->d_norm2, sizeof(double) * h.nact, hipMemcpyDeviceToHost, s->st));
     SRV_OK(hipStreamSynchronize(s->st));
@@ -565,8 +594,8 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             }
     }
     s->stats.rounds++;
-    // ---- bookkeeping and retirement
-    std::vector<std::unique_ptr<Request>> keep;
+    // ---- bookkeeping and retirement: every finished x is copied out, then one wait
+    std::vector<std::unique_ptr<Request>> keep, out;
     for (int k = 0; k < h.nact; ++k) {
         std::unique_ptr<Request> &r = s->active[k];
         r->ticket += (int64_t)cfg.inner_sweeps * r->m;
@@ -581,19 +610,26 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             r->status = conv ? ASYRK_OK : (bad ? ASYRK_ERR_DIVERGED : ASYRK_ERR_NOT_CONVERGED);
             r->x.resize(r->n);
             SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, s->st));
-            SRV_OK(hipStreamSynchronize(s->st));
-            r->t_done = now_s();
-            s->workers_in_use -= r->R;
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->arena.release(r->off_rec, r->bytes);
-            r->pack = SetupResult();  // drop the packed copy
-            s->stats.completed++;
-            s->done[r->id] = std::move(r);
+            out.push_back(std::move(r));
         } else {
             keep.push_back(std::move(r));
         }
     }
     s->active.swap(keep);
+    if (!out.empty()) {
+        SRV_OK(hipStreamSynchronize(s->st));
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : out) {
+            r->t_done = t;
+            s->workers_in_use -= r->R;
+            s->arena.release(r->off_rec, r->bytes);
+            r->pack = SetupResult();  // drop the packed copy
+            s->stats.completed++;
+            s->finished.push_back(r->id);
+            s->done[r->id] = std::move(r);
+        }
+    }
     if (n_active) *n_active = (int32_t)s->active.size();
     if (n_queued) {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -638,6 +674,16 @@ asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out) {
     out->active = (int64_t)s->active.size();
     out->queued = (int64_t)s->queue.size();
     out->arena_used = s->arena.used;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_take_completed(asyrk_server *s, int64_t *ids, int64_t cap, int64_t *count) {
+    if (!s || !count || cap < 0 || (cap > 0 && !ids)) return ASYRK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int64_t k = std::min<int64_t>(cap, (int64_t)s->finished.size());
+    std::copy(s->finished.begin(), s->finished.begin() + k, ids);
+    s->finished.erase(s->finished.begin(), s->finished.begin() + k);
+    *count = k;
     return ASYRK_OK;
 }
 

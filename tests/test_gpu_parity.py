@@ -436,11 +436,80 @@ def test_autotune_picks_a_lane_width():
     s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
     _say("autotune")
     sysm = make_system(s, device=True)
-    best, rates = sysm.autotune(in_flight=800)
-    assert best in (1, 2, 4, 8, 16) and all(r > 0 for r in rates.values())
-    assert rates[best] == max(rates.values())
+    best, pipe, rates = sysm.autotune(in_flight=800)
+    assert best in (1, 2, 4, 8, 16) and len(rates) == 10 and all(r > 0 for r in rates.values())
+    assert rates[(best, pipe)] == max(rates.values())
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
-    assert st["lanes"] == best and st["status"] == "OK"
+    assert st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
+    # the tuned loop applies at the tuned R only; elsewhere the rule (R <= 8192)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=20_000)
+    assert st["pipelined"] == 0
+    sysm.close()
+
+
+# ------------------------------------------------------------------ pipelined worker loop
+
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_pipelined_single_worker_matches_oracle(lanes):
+    """One asynchronous worker running the pipelined loop performs plain RK:
+    its gathers for ticket t + 1 must see its own atomics of ticket t (ragged
+    rows of 1..37 entries, three 300-entry rows that take the multi-chunk path,
+    norm-weighted sampling through the alias branch, FP64)."""
+    rng = np.random.default_rng(5)
+    lens = rng.integers(1, 38, 700)
+    lens[[3, 100, 555]] = 300
+    s = synth.ragged_rows(700, 400, lens, seed=5, dtype="f64")
+    _say(f"pipelined single worker lanes={lanes}")
+    ref = oracle_run(s, 0.9, 6, 11)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=0.9, sweeps=6, seed=11, in_flight=1, lanes=lanes,
+                      pipeline=True, history=16)
+    assert st["status"] == "OK" and st["pipelined"] == 1
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    sysm.close()
+
+
+PIPE_CASES = {
+    "f32_ragged": (lambda: synth.serving_system(31, 30_000, 7_500), None),
+    "bf16_fixed": (lambda: synth.uniform_rows(30_000, 7_500, 16, seed=8, dtype="bf16"), None),
+    "f32_rows_f64_iterate": (lambda: synth.uniform_rows(30_000, 7_500, 20, seed=9, dtype="f32"), "f64"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(PIPE_CASES))
+def test_pipelined_async_matches_plain_loop(case):
+    """Many workers: the pipelined loop reaches 1e-6 in about the sweeps the
+    plain loop needs (same R, lanes, seed)."""
+    make, it = PIPE_CASES[case]
+    s = make()
+    _say(f"pipelined async {case}")
+    sysm = make_system(s, device=True)
+    out = {}
+    for pipe in (False, True):
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=3, tol=1e-6, in_flight=512,
+                          lanes=4, pipeline=pipe, iter_dtype=it)
+        assert st["status"] == "OK" and st["pipelined"] == int(pipe), (pipe, st["status"])
+        assert np.linalg.norm(x - s.x_star) <= 1.05e-6 * np.linalg.norm(s.x_star)
+        out[pipe] = st["sweeps_done"]
+    assert out[True] <= 1.5 * out[False] + 1, out
+    sysm.close()
+
+
+def test_pipelined_option_checks():
+    s = synth.uniform_rows(500, 100, 5, seed=3, dtype="f32", require_full_columns=False)
+    _say("pipelined option checks")
+    sysm = make_system(s, device=False)
+    for kw in ({"mode": "replay"}, {"update": "one"}, {"order": "slices"}, {"trace": True}):
+        with pytest.raises(P.AsyrkError) as ei:
+            sysm.solve(np.zeros(s.n), 1.0, 1, 0, pipeline=True, **kw)
+        assert ei.value.name == "UNSUPPORTED", kw
+        st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, **kw)  # automatic choice: plain loop
+        assert st["pipelined"] == 0, kw
+    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64)
+    assert st["pipelined"] == 1  # the rule for few workers
+    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64, pipeline=False)
+    assert st["pipelined"] == 0
     sysm.close()
 
 

@@ -156,3 +156,31 @@ def test_concurrent_submitters_while_rounds_run():
         for k, s in enumerate(systems):
             _check(s, out[k])
         assert len(set(ids)) == len(ids)
+
+
+@pytest.mark.parametrize("pipe_workers", [0, 1 << 24])
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_lane_widths_and_completion_list(lanes, pipe_workers):
+    """Every lane width and worker loop (plain: pipe_workers = 0; pipelined:
+    every round) of the packed sweep drains a mixed stream to tolerance;
+    take_completed reports each finished id exactly once."""
+    _say(f"server lanes={lanes} pipe_workers={pipe_workers} take_completed")
+    sizes = [900, 3000, 17000, 1200, 40000, 2500]
+    systems = _systems(range(500, 506), sizes)
+    with P.Server(budget_bytes=1 << 30, lanes=lanes, pipe_workers=pipe_workers) as srv:
+        ids = [srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
+               for k, s in enumerate(systems)]
+        index = {rid: k for k, rid in enumerate(ids)}
+        seen, out = [], {}
+        for _ in range(400):
+            srv.progress()
+            for rid in srv.take_completed(cap=2):
+                seen.append(rid)
+                k = index[rid]
+                out[k] = srv.poll(rid, n=systems[k].n)
+            if len(out) == len(ids):
+                break
+        assert sorted(seen) == sorted(ids) and len(seen) == len(set(seen))
+        assert srv.take_completed() == []
+        for k, s in enumerate(systems):
+            _check(s, out[k])
