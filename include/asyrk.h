@@ -93,9 +93,10 @@ typedef struct asyrk_solve_params {
     int32_t mode;            /* asyrk_mode, default ASYNC */
     int32_t sampling;        /* asyrk_sampling, default NORM2 */
     int32_t update;          /* asyrk_update, default ALL */
-    int32_t lanes;           /* lanes per row G in {1,2,4,8,16,32,64}; 0 = autotuned value if
-                                any, else a rule of thumb (a whole wave per row when
-                                R <= 256 workers) */
+    int32_t lanes;           /* lanes per row G in {1,2,4,8,16,32,64}; 0 = the autotuned
+                                value when the autotuner ran at this R, else the largest
+                                power of two with R * G <= 65536, capped by the smallest
+                                power of two covering an average row's units */
     int64_t in_flight;       /* R, row workers in flight (tau_design = R - 1); 0 = choose */
     double tol;              /* stop when the monitored error <= tol; 0 = run every sweep */
     const double *x_ref;     /* nullable, length n: monitor ||x - x_ref||/||x_ref||;

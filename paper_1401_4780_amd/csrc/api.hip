@@ -116,13 +116,17 @@ asyrk_status fetch_scalar(asyrk_system *s, int nparts, double *host_out) {
 // it by the atomic unit, where the plain loop measured faster.
 constexpr int64_t kPipeMaxR = 8192;
 
+// Lanes per row without autotuning: the sweep saturates once about 2^16
+// lanes are in flight, so G is the largest power of two with R * G <= 2^16,
+// but no wider than the smallest power of two covering a row of average
+// length (more lanes than units leave lanes idle) and at most 64.
 int auto_lanes(const asyrk_system *s, int64_t R) {
     const Geom g = geom_of(s->vk);
     const double units = ((double)s->nnz / (double)s->m) / g.U;
+    int cover = 1;
+    while (cover < 64 && cover < units) cover *= 2;
     int G = 1;
-    while (G < 16 && G < units / 2.0) G *= 2;
-    // with few workers, lanes are free: a whole wave per row (long rows too)
-    if (R * 64 <= 256 * 64) G = 64;
+    while (G < cover && R * (2 * G) <= ((int64_t)1 << 16)) G *= 2;
     return G;
 }
 
@@ -623,13 +627,14 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
     const int xi = xk == ASYRK_F32 ? 1 : 0;
-    const int tuned = s->tuned_G[xi];
     int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
+    // the autotuned pair holds at the R it was measured at
+    const int tuned = s->tuned_R[xi] == R ? s->tuned_G[xi] : 0;
     const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     if (p.pipeline == -1) {
         const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && p.order == 0 && !p.trace;
-        const bool tuned_here = tuned && s->tuned_R[xi] == R && G == tuned;
+        const bool tuned_here = tuned && G == tuned;
         p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
     }
     const bool f32 = xk == ASYRK_F32;
