@@ -5,6 +5,8 @@ Workload (the at-scale FP32 configuration): m = 4,000,000, n = 1,000,000,
 exactly 20 distinct uniform-random columns per row, N(0,1) values, unit-norm
 rows stored in FP32, int32 column indices; x* ~ N(0,1), b = A x* (FP64 from
 the stored values); x0 = 0; gamma = 1; run until ||x - x*||/||x*|| <= 1e-6.
+The iterate is the library's default, FP64 (FP64 atomics are the faster ones
+on this GPU); the same solve with an FP32 iterate is reported beside it.
 
 One step = one complete solve from x0 = 0 to the tolerance: row sampling,
 record fetch, gather-dot, step, atomic scatter, staleness control and the
@@ -37,6 +39,11 @@ sys.path.insert(0, str(ROOT))
 M, N, NNZ, GEN_SEED = 4_000_000, 1_000_000, 20, 1
 GAMMA, TOL, BUDGET = 1.0, 1e-6, 200
 HBM_PEAK_GBPS = 8000.0
+# iterate of the headline solve: the library's default, FP64 (FP64 atomics run
+# faster than FP32 ones on this GPU); the FP32-valued records then take b_i and
+# 1/||a_i||^2 from 16-byte FP64 side records instead of the 8-byte FP32 pair
+ITER = "f64"
+SIDE_EXTRA_BYTES = 8
 R_SWEEP = (1024, 2048, 4096, 8192, 16384, 32768, 65536)
 
 
@@ -50,7 +57,7 @@ def kernel_source_hash() -> str:
 def traffic_from_profile():
     """HBM bytes per sweep launch measured with rocprofv3 counters, if the
     committed summary was taken on the current kernel sources."""
-    p = ROOT / "profiles" / "sweep_kernel_c2_4Mx1M_f32_traffic.md"
+    p = ROOT / "profiles" / "sweep_kernel_c2_4Mx1M_f32values_f64iter_traffic.md"
     if not p.exists():
         return None
     text = p.read_text()
@@ -135,7 +142,7 @@ def run_c2(args):
     ok = all(st["status"] == "OK" for st in sts)
     log(f"timed {args.steps} solves in {elapsed:.3f}s, all converged={ok}")
 
-    bytes_per_row = info["record_bytes_per_row"]
+    bytes_per_row = info["record_bytes_per_row"] + SIDE_EXTRA_BYTES
     per_launch_s = kern_s / launches
     achieved = bytes_per_row * M / per_launch_s / 1e9
     traffic = traffic_from_profile()
@@ -151,9 +158,10 @@ def run_c2(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": ITER,
         "data": "synthetic",
         "config": {"workload": "asyrk_4Mx1M_nnz20_f32_to_1e-6", "m": M, "n": N, "nnz_per_row": NNZ,
+                   "values": "f32", "iterate": ITER,
                    "gamma": GAMMA, "tol": TOL, "in_flight": sts[0]["in_flight"],
                    "lanes": sts[0]["lanes"], "pipelined": sts[0]["pipelined"],
                    "record_stride_bytes": info["record_stride"]},
@@ -168,7 +176,7 @@ def run_c2(args):
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
                      "kernel": ("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
-                     + f"<F32,F32,{sts[0]['lanes']}>", "algorithmic_bytes_per_row": bytes_per_row,
+                     + f"<F32,F64,{sts[0]['lanes']}>", "algorithmic_bytes_per_row": bytes_per_row,
                      "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
     }
 
@@ -180,14 +188,21 @@ def run_c2(args):
                            "lambda_max": lam, "tau_max_corollary1": tau_max,
                            "tau_times_nnz": st["tau_design"] * NNZ}
 
-    # device ceilings for the x traffic (random 4-byte gathers and atomics)
+    # device ceilings for the x traffic (random gathers and atomics of the
+    # headline iterate, and of FP32 for comparison)
     copy = P.probe_copy(1 << 30, 20)
-    gat = P.probe_scatter(N, 1 << 27, "f32", "load", 5)
-    atm = P.probe_scatter(N, 1 << 27, "f32", "atomic", 5)
-    x_bound = 1.0 / (NNZ / gat + NNZ / atm)
-    result["ceilings"] = {"stream_copy_GBps": copy, "gather_f32_per_s": gat, "atomic_f32_per_s": atm,
-                          "rows_per_s_bound_by_x_traffic": x_bound,
-                          "frac_of_x_traffic_bound": result["kernel_rows_per_s"] / x_bound}
+    ceil = {"stream_copy_GBps": copy}
+    for dt in ("f32", "f64"):
+        ceil[f"gather_{dt}_per_s"] = P.probe_scatter(N, 1 << 27, dt, "load", 5)
+        ceil[f"atomic_{dt}_per_s"] = P.probe_scatter(N, 1 << 27, dt, "atomic", 5)
+    # the atomics alone cap the sweep at atomic_rate / nnz rows/s; if gathers and
+    # atomics could not overlap at all the cap would be the serialized one
+    atomic_bound = ceil[f"atomic_{ITER}_per_s"] / NNZ
+    serial_bound = 1.0 / (NNZ / ceil[f"gather_{ITER}_per_s"] + NNZ / ceil[f"atomic_{ITER}_per_s"])
+    ceil["rows_per_s_bound_by_atomics"] = atomic_bound
+    ceil["rows_per_s_bound_gathers_and_atomics_serialized"] = serial_bound
+    ceil["frac_of_atomic_bound"] = result["kernel_rows_per_s"] / atomic_bound
+    result["ceilings"] = ceil
 
     if not args.no_sweep:
         sweep = {}
@@ -203,9 +218,10 @@ def run_c2(args):
         x.zero_()
         t1 = time.perf_counter()
         st = sysm.solve(x, GAMMA, BUDGET, 11, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
-                        iter_dtype="f64")
-        result["f64_iterate"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
-                                 "status": st["status"], "time_to_tol_s": time.perf_counter() - t1}
+                        iter_dtype="f32")
+        result["f32_iterate"] = {"sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"],
+                                 "status": st["status"], "lanes": st["lanes"],
+                                 "time_to_tol_s": time.perf_counter() - t1}
         x.zero_()
         t1 = time.perf_counter()
         st = sysm.solve(x, GAMMA, BUDGET, 12, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
@@ -219,7 +235,7 @@ def run_c2(args):
         t1 = time.perf_counter()
         st = sysm.solve(x, 1.0 / NNZ, 600, 13, tol=TOL, x_ref=x_ref, in_flight=args.in_flight,
                         update="one", sampling="uniform", check_every=10)
-        kbytes = info["record_bytes_per_row"] * M
+        kbytes = (info["record_bytes_per_row"] + SIDE_EXTRA_BYTES) * M
         result["algorithm1_single_coordinate"] = {
             "sweeps": st["sweeps_done"], "rows_per_s": st["rows_per_s"], "status": st["status"],
             "final_err": st["final_err"], "time_to_tol_s": time.perf_counter() - t1,
@@ -333,7 +349,7 @@ def run_skewed(args):
     best = max(converging or res, key=lambda q: res[q]["rows_per_s"])
     return {"metric": "row updates/s (skewed rows, hot columns)", "value": res[best]["rows_per_s"],
             "unit": "row updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
-            "vs_baseline": None, "data": "synthetic", "dtype": "f32",
+            "vs_baseline": None, "data": "synthetic", "dtype": "f64",
             "config": {"workload": "asyrk_skewed_2Mx500k_lognormal16_zipf1.1", "m": s.m, "n": s.n,
                        "nnz": s.nnz, "mu": info["mu"], "nu": info["nu"], "sweeps": sweeps,
                        "best_converging_in_flight": best},

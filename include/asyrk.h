@@ -112,9 +112,12 @@ typedef struct asyrk_solve_params {
                                 each check (refinement: after each outer iteration) */
     int64_t history_cap;     /* capacity of history */
     int32_t iter_dtype;      /* iterate and sweep arithmetic: -1 (set by
-                                asyrk_solve_params_init) = the system's default (F64
-                                values: F64, else F32); ASYRK_F32 (F32/BF16 values only)
-                                or ASYRK_F64 (any values; FP64 atomics) */
+                                asyrk_solve_params_init) = ASYRK_F64, or ASYRK_F32 with
+                                refine = 1; ASYRK_F32 (F32/BF16 values only: FP32
+                                atomics) or ASYRK_F64 (any values; FP64 atomics, which
+                                this GPU executes faster than FP32 ones; FP32/BF16 values
+                                then take b_i and 1/||a_i||^2 in FP64 from side records
+                                of 16 bytes per row, built on first use) */
     int32_t order;           /* 0: each ticket draws its row (with replacement, default);
                                 1: the paper's experimental scheme: worker w owns rows
                                 [w L, (w+1) L), L = ceil(m / R), and visits each of
@@ -171,7 +174,7 @@ typedef struct asyrk_system_info {
     int64_t record_stride;     /* bytes per row record when fixed_nnz > 0 */
     int64_t device_bytes;      /* device memory held by the system */
     int32_t vals_dtype;        /* asyrk_dtype of the stored values */
-    int32_t iter_dtype;        /* default iterate dtype: ASYRK_F64 for F64 values, else ASYRK_F32 */
+    int32_t iter_dtype;        /* default iterate dtype (ASYRK_F64) */
     double fro2;               /* ||A||_F^2 (FP64, stored values) */
     double lambda_mp;          /* (1 + sqrt(n/m))^2 * fro2 / n: Gaussian-ensemble estimate of lambda_max */
     int64_t record_bytes_per_row; /* algorithmic bytes per row update (values, indices, b_i, w_i, start) */

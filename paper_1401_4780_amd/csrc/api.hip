@@ -370,7 +370,7 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
     info->record_stride = s->stride;
     info->device_bytes = s->device_bytes;
     info->vals_dtype = s->vk;
-    info->iter_dtype = s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32;
+    info->iter_dtype = ASYRK_F64;
     info->fro2 = s->fro2;
     info->lambda_mp = lambda_mp(s);
     const Geom g = geom_of(s->vk);
@@ -492,7 +492,7 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
                             int32_t *best_lanes, int32_t *best_pipeline, double *rows_per_s_out) {
     if (!s || !(gamma > 0.0 && gamma < 2.0) || in_flight < 0) return ASYRK_ERR_INVALID_ARG;
     if (iter_dtype != -1 && iter_dtype != ASYRK_F32 && iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
-    const int xk = iter_dtype >= 0 ? iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
+    const int xk = iter_dtype >= 0 ? iter_dtype : ASYRK_F64;
     if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
     if (s->rec_b_dirty) {
         HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
@@ -620,7 +620,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
     if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
-    const int xk = p.iter_dtype >= 0 ? p.iter_dtype : (s->vk == ASYRK_F64 ? ASYRK_F64 : ASYRK_F32);
+    // FP64 by default: FP64 atomics outrun FP32 ones on this part, so the FP64
+    // iterate is both faster and more accurate; refinement sweeps in FP32
+    const int xk = p.iter_dtype >= 0 ? p.iter_dtype : (p.refine ? ASYRK_F32 : ASYRK_F64);
     if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
     if (p.refine && xk == ASYRK_F64) return ASYRK_ERR_UNSUPPORTED;
     if (p.refine && (p.mode == ASYRK_REPLAY || p.update == ASYRK_UPDATE_ONE)) return ASYRK_ERR_UNSUPPORTED;

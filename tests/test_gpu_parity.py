@@ -168,7 +168,8 @@ def test_replay_fp32_storage_within_fp32_floor(dtype):
     _say(f"replay {dtype} C1 shape")
     ref = oracle_run(s, 1.0, 20, 0)
     sysm = make_system(s, device=True)
-    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, mode="replay", history=32)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, mode="replay", history=32,
+                      iter_dtype="f32")
     nx = np.linalg.norm(s.x_star)
     assert np.linalg.norm(x - ref["x"]) <= 1e-6 * nx
     assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-6
@@ -188,8 +189,8 @@ def test_replay_fp64_iterate_over_fp32_storage(dtype):
                       history=16)
     assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
-    # the same system still runs with the default FP32 iterate afterwards
-    x2, st2 = gpu_solve(sysm, s, True, gamma=1.0, sweeps=10, seed=3, mode="replay")
+    # the same system still runs with the FP32 iterate afterwards
+    x2, st2 = gpu_solve(sysm, s, True, gamma=1.0, sweeps=10, seed=3, mode="replay", iter_dtype="f32")
     assert np.linalg.norm(x2 - ref["x"]) <= 1e-5 * np.linalg.norm(s.x_star)
     sysm.close()
 
@@ -217,17 +218,19 @@ def _sweeps_to(curve, tol):
 
 # 40k x 10k unit rows: lambda_max ~ (1 + sqrt(n/m))^2 m/n = 9, so Corollary 1
 # admits tau + 1 <= m / (2 e lambda_max) ~ 817 workers.
+@pytest.mark.parametrize("it", ["f32", None])
 @pytest.mark.parametrize("gamma", [1.0, 0.5])
 @pytest.mark.parametrize("R", [64, 800])
-def test_async_fp32_reaches_1e6(gamma, R):
+def test_async_fp32_reaches_1e6(gamma, R, it):
+    """FP32 values, FP32 iterate (it = "f32") or the default FP64 iterate."""
     s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
-    _say(f"async f32 40k x 10k gamma={gamma} R={R}")
+    _say(f"async f32 40k x 10k gamma={gamma} R={R} iterate={it}")
     ref = oracle_run(s, gamma, 60, 1)
     k_orc = _sweeps_to(ref["err"], 1e-6)
     assert k_orc is not None
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=gamma, sweeps=200, seed=1, tol=1e-6, in_flight=R,
-                      history=256)
+                      history=256, iter_dtype=it)
     assert st["status"] == "OK", st
     err = np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star)
     assert err <= 1.05e-6
@@ -235,7 +238,8 @@ def test_async_fp32_reaches_1e6(gamma, R):
     sysm.close()
 
 
-def test_in_flight_threshold():
+@pytest.mark.parametrize("it", ["f32", None])
+def test_in_flight_threshold(it):
     """Below Corollary 1's bound the error-per-sweep curves merge (Section
     "Experiments": the workload is nearly independent of the worker count);
     far above it (16x) progress per sweep collapses."""
@@ -244,7 +248,7 @@ def test_in_flight_threshold():
     sysm = make_system(s, device=True)
     errs = {}
     for R in (16, 256, 800, 13_000):
-        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=12, seed=2, in_flight=R)
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=12, seed=2, in_flight=R, iter_dtype=it)
         errs[R] = st["final_err"]
     ref = oracle_run(s, 1.0, 12, 2)["err"][-1]
     for R in (16, 256, 800):
