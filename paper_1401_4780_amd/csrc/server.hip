@@ -21,6 +21,7 @@
 // limit (tau + 1 <= ||A||_F^2 / (2 e lambda)), so small systems take few
 // workers and the GPU is filled by packing many systems into one launch.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -264,6 +265,8 @@ struct asyrk_server {
     double *h_norm2 = nullptr;     // pinned
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // plain / pipelined sweep
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t cst = nullptr;     // admission uploads
+    hipEvent_t ev_copy = nullptr;  // recorded on cst after the last admission batch
     int sweep_blocks[2] = {0, 0};
 
     std::mutex mu;
@@ -274,6 +277,8 @@ struct asyrk_server {
     int64_t next_id = 1;
 
     std::vector<std::unique_ptr<Request>> active;  // progress() thread only
+    std::vector<std::unique_ptr<Request>> staged;  // uploading during the current round; join the next
+    std::atomic<int64_t> n_active{0};              // active + staged, for other threads
     int64_t workers_in_use = 0;
     asyrk_server_stats stats{};
 };
@@ -321,6 +326,7 @@ hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
 void free_server(asyrk_server *s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
+    if (s->cst) (void)hipStreamSynchronize(s->cst);
     for (hipGraphExec_t g : s->graph)
         if (g) (void)hipGraphExecDestroy(g);
     (void)hipFree(s->arena.base);
@@ -334,6 +340,8 @@ void free_server(asyrk_server *s) {
     if (s->e0) (void)hipEventDestroy(s->e0);
     if (s->e1) (void)hipEventDestroy(s->e1);
     if (s->st) (void)hipStreamDestroy(s->st);
+    if (s->cst) (void)hipStreamDestroy(s->cst);
+    if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
     delete s;
 }
 
@@ -383,6 +391,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         e = hipHostMalloc((void **)&s->pinned.base, (size_t)cfg.pinned_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&s->e0);
     if (e == hipSuccess) e = hipEventCreate(&s->e1);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_server(s);
         return srv_fail(e);
@@ -483,12 +493,32 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
     if (!s) return ASYRK_ERR_INVALID_ARG;
     const asyrk_server_config &cfg = s->cfg;
-    // ---- admit
+    // ---- join the requests staged by the previous call: their uploads ran on
+    // the copy stream while that call's round computed
+    if (!s->staged.empty()) {
+        SRV_OK(hipEventSynchronize(s->ev_copy));
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : s->staged) {
+            if (r->pin_off >= 0) {
+                s->pinned.release(r->pin_off, r->pin_bytes);
+                r->pin_off = -1;
+            }
+            s->active.push_back(std::move(r));
+        }
+        s->staged.clear();
+    }
+    // ---- admit.  While the active systems keep the GPU busy (more workers
+    // than a pipelined round takes), new requests upload during this round
+    // and join the next; otherwise this round waits for their upload.
+    int64_t active_workers = 0;
+    for (const auto &r : s->active) active_workers += r->R;
+    const bool defer = active_workers > cfg.pipe_workers && active_workers > 0;
+    bool admitted = false;
     for (;;) {
         std::unique_ptr<Request> r;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->queue.empty() || (int)s->active.size() >= cfg.max_slots) break;
+            if (s->queue.empty() || (int)(s->active.size() + s->staged.size()) >= cfg.max_slots) break;
             Request &f = *s->queue.front();
             int64_t R = (int64_t)std::floor(f.fro2 / (2.0 * M_E * f.lam));
             R = std::max<int64_t>(1, std::min<int64_t>(R, cfg.max_workers / 4));
@@ -513,22 +543,28 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         if (q.pin_off >= 0) {
             // one DMA of the staged rec | loc | b64 block (same relative layout)
             SRV_OK(hipMemcpyAsync(base + q.off_rec, s->pinned.base + q.pin_off, q.pin_bytes, hipMemcpyHostToDevice,
-                                  s->st));
+                                  s->cst));
         } else {
             SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.pack.rec.size(), hipMemcpyHostToDevice,
-                                  s->st));
+                                  s->cst));
             if (!q.pack.loc.empty())
                 SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8,
-                                      hipMemcpyHostToDevice, s->st));
-            SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->st));
+                                      hipMemcpyHostToDevice, s->cst));
+            SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->cst));
         }
-        SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->st));
+        SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->cst));
         q.t_admit = now_s();
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
         s->workers_in_use += q.R;
-        s->active.push_back(std::move(r));
+        (defer ? s->staged : s->active).push_back(std::move(r));
         s->stats.admitted++;
+        admitted = true;
     }
+    if (admitted) {
+        SRV_OK(hipEventRecord(s->ev_copy, s->cst));
+        if (!defer) SRV_OK(hipStreamWaitEvent(s->st, s->ev_copy, 0));
+    }
+    s->n_active.store((int64_t)(s->active.size() + s->staged.size()));
     if (s->active.empty()) {
         if (n_active) *n_active = 0;
         if (n_queued) {
@@ -616,6 +652,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         }
     }
     s->active.swap(keep);
+    s->n_active.store((int64_t)(s->active.size() + s->staged.size()));
     if (!out.empty()) {
         SRV_OK(hipStreamSynchronize(s->st));
         const double t = now_s();
@@ -630,7 +667,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             s->done[r->id] = std::move(r);
         }
     }
-    if (n_active) *n_active = (int32_t)s->active.size();
+    if (n_active) *n_active = (int32_t)(s->active.size() + s->staged.size());
     if (n_queued) {
         std::lock_guard<std::mutex> lk(s->mu);
         *n_queued = (int32_t)s->queue.size();
@@ -671,7 +708,7 @@ asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out) {
     if (!s || !out) return ASYRK_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
-    out->active = (int64_t)s->active.size();
+    out->active = s->n_active.load();
     out->queued = (int64_t)s->queue.size();
     out->arena_used = s->arena.used;
     return ASYRK_OK;

@@ -453,17 +453,20 @@ def test_autotune_picks_a_lane_width():
 
 # ------------------------------------------------------------------ pipelined worker loop
 
-@pytest.mark.parametrize("lanes", [1, 4, 16])
-def test_pipelined_single_worker_matches_oracle(lanes):
+@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f64"), (4, "f32"), (1, "bf16"),
+                                         (16, "bf16")])
+def test_pipelined_single_worker_matches_oracle(lanes, dtype):
     """One asynchronous worker running the pipelined loop performs plain RK:
     its gathers for ticket t + 1 must see its own atomics of ticket t (ragged
     rows of 1..37 entries, three 300-entry rows that take the multi-chunk path,
-    norm-weighted sampling through the alias branch, FP64)."""
+    norm-weighted sampling through the alias branch).  FP32/BF16 values take
+    b_i and 1/w_i from the FP64 side records; with the FP64 iterate every
+    value dtype matches the FP64 oracle on the stored values to 1e-12."""
     rng = np.random.default_rng(5)
     lens = rng.integers(1, 38, 700)
     lens[[3, 100, 555]] = 300
-    s = synth.ragged_rows(700, 400, lens, seed=5, dtype="f64")
-    _say(f"pipelined single worker lanes={lanes}")
+    s = synth.ragged_rows(700, 400, lens, seed=5, dtype=dtype)
+    _say(f"pipelined single worker lanes={lanes} values={dtype}")
     ref = oracle_run(s, 0.9, 6, 11)
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=0.9, sweeps=6, seed=11, in_flight=1, lanes=lanes,
@@ -475,8 +478,8 @@ def test_pipelined_single_worker_matches_oracle(lanes):
 
 
 PIPE_CASES = {
-    "f32_ragged": (lambda: synth.serving_system(31, 30_000, 7_500), None),
-    "bf16_fixed": (lambda: synth.uniform_rows(30_000, 7_500, 16, seed=8, dtype="bf16"), None),
+    "f32_ragged": (lambda: synth.serving_system(31, 30_000, 7_500), "f32"),
+    "bf16_fixed": (lambda: synth.uniform_rows(30_000, 7_500, 16, seed=8, dtype="bf16"), "f32"),
     "f32_rows_f64_iterate": (lambda: synth.uniform_rows(30_000, 7_500, 20, seed=9, dtype="f32"), "f64"),
 }
 
