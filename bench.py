@@ -383,7 +383,8 @@ def run_serving(args):
     srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}),
                    **({"lanes": args.lanes} if args.lanes in (4, 8) else {}),
                    **({"max_workers": args.max_workers} if args.max_workers else {}),
-                   **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}))
+                   **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}),
+                   **({"pipe_lanes": args.pipe_lanes} if args.pipe_lanes else {}))
 
     def drive(first, count, arrivals):
         """Submit requests first..first+count-1 at their arrival times (seconds
@@ -465,7 +466,7 @@ def run_serving(args):
                        "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
-                       "pipe_workers": srv.config["pipe_workers"]},
+                       "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
@@ -483,6 +484,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed", "serving"])
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
     ap.add_argument("--max-workers", type=int, default=0, help="serving: total row workers (0: default)")
+    ap.add_argument("--pipe-lanes", type=int, default=0, help="serving: lanes in pipelined rounds (0: default)")
     ap.add_argument("--pipe-workers", type=int, default=-1,
                     help="serving: pipelined rounds up to this many workers (-1: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -340,11 +340,14 @@ typedef struct asyrk_server_config {
     int64_t pinned_bytes;  /* pinned host staging for queued requests (uploads become one DMA
                               each), default 4 GiB; 0 = none; a request that does not fit is
                               uploaded from pageable memory */
-    int32_t lanes;         /* lanes per row in the packed sweep: 4 or 8 (each keeps rows of up
-                              to 64 entries in registers), default 4 */
+    int32_t lanes;         /* lanes per row in the packed sweep of busy rounds: 4 or 8 (each
+                              keeps rows of up to 64 entries in registers), default 4 */
     int32_t pipe_workers;  /* rounds whose active systems hold at most this many row workers
                               run the pipelined worker loop (see asyrk_solve_params.pipeline),
                               default 8192; 0 = never */
+    int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 8 (fewer
+                              entries per lane shorten each latency-bound ticket) */
+    int32_t reserved;      /* must be 0 */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {

@@ -48,7 +48,8 @@ struct SlotDesc {
     Rows rows;
     double *b64;
     double *x64;
-    float *d;
+    double *d;        // correction, FP64 (FP64 atomics are the faster ones)
+    double2 *side;    // per row {r_i, 1/||a_i||^2}: the correction system's right-hand side
     int64_t n;
     int64_t R;        // row workers of this system
     int64_t w_off;    // first global worker
@@ -56,8 +57,7 @@ struct SlotDesc {
     int64_t col_off;  // first global column
     int64_t t_begin, t_end;
     uint32_t key0, key1;
-    float gamma;
-    int32_t pad;
+    double gamma;
 };
 
 struct TableHead {
@@ -88,17 +88,16 @@ __global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, cons
     if (tid < nact) norm2[tid] = 0.0;
     for (int64_t q = tid; q < total; q += stride) {
         const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
-        sl[s].d[q - sl[s].col_off] = 0.f;
+        sl[s].d[q - sl[s].col_off] = 0.0;
     }
 }
 
 // G lanes per row with 16 / G units per lane: rows of up to 64 FP32 entries
-// stay in registers.  Four waves per SIMD keep the default 65536 workers
-// (x 4 lanes) resident at once.  PIPE: the pipelined worker loop, for rounds
-// with few workers (latency-bound); the plain loop saturates the atomic unit
-// better when many are active.
+// stay in registers.  PIPE: the pipelined worker loop, for rounds with few
+// workers (latency-bound); the plain loop saturates the atomic unit better
+// when many are active.
 template <int G, bool PIPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void srv_sweep_kernel(const TableHead *th, const SlotDesc *sl) {
+__device__ __forceinline__ void srv_sweep_body(const TableHead *th, const SlotDesc *sl) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -108,13 +107,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     const SlotDesc d = sl[s];  // a copy: the scatter cannot be taken to alias it
     const int64_t w = worker - d.w_off;
     if constexpr (PIPE) {
-        run_tickets_pipelined<ASYRK_F32, ASYRK_F32, G, 16 / G>(d.rows, d.d, nullptr, d.t_begin + w, d.t_end, d.R,
+        run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.side, d.t_begin + w, d.t_end, d.R,
                                                                0u, d.key0, d.key1, 0, d.gamma, gl);
     } else {
         for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
-            process_ticket<ASYRK_F32, ASYRK_F32, G, 16 / G>(d.rows, d.d, nullptr, j, 0u, d.key0, d.key1, 0, 0,
+            process_ticket<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.side, j, 0u, d.key0, d.key1, 0, 0,
                                                              d.gamma, gl, 0);
     }
+}
+
+// Plain loop: four waves per SIMD keep the default 65536 workers (x 4 lanes)
+// resident at once.
+template <int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void srv_sweep_kernel(const TableHead *th, const SlotDesc *sl) {
+    srv_sweep_body<G, false>(th, sl);
+}
+
+// Pipelined loop: its rounds hold at most a few thousand workers, so it may
+// use the registers of two tickets without an occupancy bound.
+template <int G>
+__global__ __launch_bounds__(256) void srv_sweep_pipe_kernel(const TableHead *th, const SlotDesc *sl) {
+    srv_sweep_body<G, true>(th, sl);
 }
 
 __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, const SlotDesc *sl) {
@@ -124,7 +137,7 @@ __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, cons
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
         const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
         const int64_t c = q - sl[s].col_off;
-        sl[s].x64[c] += (double)sl[s].d[c];
+        sl[s].x64[c] += sl[s].d[c];
     }
 }
 
@@ -164,7 +177,7 @@ __global__ __launch_bounds__(256) void srv_residual_kernel(const TableHead *th, 
             acc = group_sum<G>(acc);
             const double r = d.b64[i] - acc;
             if (gl == 0) {
-                reinterpret_cast<HdrF32 *>(const_cast<uint8_t *>(rec))->b = (float)r;
+                d.side[i].x = r;
                 r2 = r * r;
             }
         }
@@ -229,11 +242,12 @@ struct Request {
     uint64_t seed = 0;
     SetupResult pack;
     std::vector<double> b64;
+    std::vector<double> side;  // {b_i, 1/||a_i||^2} per row until staged in pinned memory
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
     // active state
     int slot = -1;
     int64_t R = 1;
-    int64_t off_rec = -1, off_loc = -1, off_b = -1, off_x = -1, off_d = -1;
+    int64_t off_rec = -1, off_loc = -1, off_b = -1, off_side = -1, off_x = -1, off_d = -1;
     int64_t bytes = 0;
     int64_t rec_bytes = 0;    // packed record bytes
     int64_t pin_off = -1;     // staging copy of rec | loc | b64 in the pinned arena, or -1
@@ -300,23 +314,24 @@ asyrk_status srv_fail(hipError_t e) {
 
 int64_t request_bytes(const Request &r) {
     return Arena::round_up((int64_t)r.pack.rec.size()) + Arena::round_up((int64_t)r.pack.loc.size() * 8) +
-           Arena::round_up(r.m * 8) + Arena::round_up(r.n * 8) + Arena::round_up(r.n * 4) + 5 * 256;
+           Arena::round_up(r.m * 8) + Arena::round_up(r.m * 16) + Arena::round_up(r.n * 8) +
+           Arena::round_up(r.n * 8) + 6 * 256;
 }
 
 hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
     const int wblocks = kVecBlocks;
     const dim3 grid(s->sweep_blocks[pipe]);
     hipLaunchKernelGGL(srv_zero_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
-    if (s->cfg.lanes == 4) {
-        if (pipe)
-            hipLaunchKernelGGL((srv_sweep_kernel<4, true>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
-        else
-            hipLaunchKernelGGL((srv_sweep_kernel<4, false>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+    if (pipe) {
+        switch (s->cfg.pipe_lanes) {
+            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
+            default: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
+        }
+    } else if (s->cfg.lanes == 4) {
+        hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(256), 0, st, s->d_head, s->d_slots);
     } else {
-        if (pipe)
-            hipLaunchKernelGGL((srv_sweep_kernel<8, true>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
-        else
-            hipLaunchKernelGGL((srv_sweep_kernel<8, false>), grid, dim3(256), 0, st, s->d_head, s->d_slots);
+        hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, dim3(256), 0, st, s->d_head, s->d_slots);
     }
     hipLaunchKernelGGL(srv_axpy_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots);
     hipLaunchKernelGGL(srv_residual_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
@@ -362,6 +377,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->pinned_bytes = (int64_t)4 << 30;
     c->lanes = 4;
     c->pipe_workers = 8192;
+    c->pipe_lanes = 8;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
@@ -374,7 +390,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         asyrk_server_config_init(&cfg);
     if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
-        !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 4 && cfg.lanes != 8) || cfg.pipe_workers < 0)
+        !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 4 && cfg.lanes != 8) || cfg.pipe_workers < 0 ||
+        (cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) || cfg.reserved != 0)
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
@@ -404,7 +421,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         s->pinned.free_[0] = cfg.pinned_bytes;
     }
     s->sweep_blocks[0] = (int)((cfg.max_workers * cfg.lanes + 255) / 256);
-    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.lanes + 255) / 256);
+    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.pipe_lanes + 255) / 256);
     std::memset(s->h_head, 0, sizeof(TableHead));
     if (cfg.use_graph) {
         // capture the four phases once per sweep variant; they read the slot
@@ -451,6 +468,12 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     r->tol = tol;
     r->seed = seed;
     r->b64.assign(b, b + m);
+    // the first round's correction system has right-hand side r_0 = b (x_0 = 0)
+    r->side.resize((size_t)m * 2);
+    for (int64_t i = 0; i < m; ++i) {
+        r->side[2 * i] = b[i];
+        r->side[2 * i + 1] = r->pack.w[i] > 0.0 ? 1.0 / r->pack.w[i] : 0.0;
+    }
     double bn = 0.0;
     for (int64_t i = 0; i < m; ++i) bn += b[i] * b[i];
     r->b_norm2 = bn;
@@ -460,24 +483,27 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     r->rec_bytes = (int64_t)r->pack.rec.size();
     r->bytes = request_bytes(*r);
     if (r->bytes > s->cfg.budget_bytes) return ASYRK_ERR_OOM;
-    // stage rec | loc | b64 in pinned memory so admission is a plain DMA
+    // stage rec | loc | b64 | side in pinned memory so admission is a plain DMA
     const int64_t lrec = Arena::round_up((int64_t)r->pack.rec.size());
     const int64_t lloc = Arena::round_up((int64_t)r->pack.loc.size() * 8);
     const int64_t lb = Arena::round_up(m * 8);
+    const int64_t lside = Arena::round_up(m * 16);
     if (s->pinned.base) {
         int64_t off;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            off = s->pinned.alloc(lrec + lloc + lb);
+            off = s->pinned.alloc(lrec + lloc + lb + lside);
         }
         if (off >= 0) {
             uint8_t *p = s->pinned.base + off;
             std::memcpy(p, r->pack.rec.data(), r->pack.rec.size());
             if (!r->pack.loc.empty()) std::memcpy(p + lrec, r->pack.loc.data(), r->pack.loc.size() * 8);
             std::memcpy(p + lrec + lloc, b, (size_t)m * 8);
+            std::memcpy(p + lrec + lloc + lb, r->side.data(), (size_t)m * 16);
             r->pin_off = off;
-            r->pin_bytes = lrec + lloc + lb;
+            r->pin_bytes = lrec + lloc + lb + lside;
             std::vector<uint8_t>().swap(r->pack.rec);  // the staged copy replaces it
+            std::vector<double>().swap(r->side);
         }
     }
     r->t_submit = now_s();
@@ -536,12 +562,14 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         o += Arena::round_up((int64_t)q.pack.loc.size() * 8);
         q.off_b = o;
         o += Arena::round_up(q.m * 8);
+        q.off_side = o;
+        o += Arena::round_up(q.m * 16);
         q.off_x = o;
         o += Arena::round_up(q.n * 8);
         q.off_d = o;
         uint8_t *base = s->arena.base;
         if (q.pin_off >= 0) {
-            // one DMA of the staged rec | loc | b64 block (same relative layout)
+            // one DMA of the staged rec | loc | b64 | side block (same relative layout)
             SRV_OK(hipMemcpyAsync(base + q.off_rec, s->pinned.base + q.pin_off, q.pin_bytes, hipMemcpyHostToDevice,
                                   s->cst));
         } else {
@@ -551,6 +579,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
                 SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8,
                                       hipMemcpyHostToDevice, s->cst));
             SRV_OK(hipMemcpyAsync(base + q.off_b, q.b64.data(), q.m * 8, hipMemcpyHostToDevice, s->cst));
+            SRV_OK(hipMemcpyAsync(base + q.off_side, q.side.data(), q.m * 16, hipMemcpyHostToDevice, s->cst));
         }
         SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->cst));
         q.t_admit = now_s();
@@ -588,7 +617,8 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         d.rows.m = (int32_t)q.m;
         d.b64 = reinterpret_cast<double *>(base + q.off_b);
         d.x64 = reinterpret_cast<double *>(base + q.off_x);
-        d.d = reinterpret_cast<float *>(base + q.off_d);
+        d.d = reinterpret_cast<double *>(base + q.off_d);
+        d.side = reinterpret_cast<double2 *>(base + q.off_side);
         d.n = q.n;
         d.R = q.R;
         d.w_off = wo;
@@ -598,7 +628,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         d.t_end = q.ticket + (int64_t)cfg.inner_sweeps * q.m;
         d.key0 = (uint32_t)q.seed;
         d.key1 = (uint32_t)(q.seed >> 32);
-        d.gamma = (float)cfg.gamma;
+        d.gamma = cfg.gamma;
         wo += q.R;
         ro += q.m;
         co += q.n;

@@ -158,16 +158,16 @@ def test_concurrent_submitters_while_rounds_run():
         assert len(set(ids)) == len(ids)
 
 
-@pytest.mark.parametrize("pipe_workers", [0, 1 << 24])
+@pytest.mark.parametrize("pipe_workers,pipe_lanes", [(0, 8), (1 << 24, 4), (1 << 24, 8), (1 << 24, 16)])
 @pytest.mark.parametrize("lanes", [4, 8])
-def test_lane_widths_and_completion_list(lanes, pipe_workers):
+def test_lane_widths_and_completion_list(lanes, pipe_workers, pipe_lanes):
     """Every lane width and worker loop (plain: pipe_workers = 0; pipelined:
     every round) of the packed sweep drains a mixed stream to tolerance;
     take_completed reports each finished id exactly once."""
-    _say(f"server lanes={lanes} pipe_workers={pipe_workers} take_completed")
+    _say(f"server lanes={lanes} pipe_workers={pipe_workers} pipe_lanes={pipe_lanes} take_completed")
     sizes = [900, 3000, 17000, 1200, 40000, 2500]
     systems = _systems(range(500, 506), sizes)
-    with P.Server(budget_bytes=1 << 30, lanes=lanes, pipe_workers=pipe_workers) as srv:
+    with P.Server(budget_bytes=1 << 30, lanes=lanes, pipe_workers=pipe_workers, pipe_lanes=pipe_lanes) as srv:
         ids = [srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
                for k, s in enumerate(systems)]
         index = {rid: k for k, rid in enumerate(ids)}
