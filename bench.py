@@ -461,8 +461,8 @@ def run_serving(args):
     base = nb / (time.perf_counter() - t0)
     return {"metric": "solves/s and p50/p99 solve latency (serving)", "value": sat["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
-            "vs_baseline": None, "data": "synthetic", "dtype": "f32 sweeps, f64 refinement",
-            "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8",
+            "vs_baseline": None, "data": "synthetic", "dtype": "f64",
+            "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8", "values": "f32",
                        "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],

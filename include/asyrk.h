@@ -317,9 +317,10 @@ asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_
  * Serving: many independent systems with continuous batching.
  *
  * Each request is a consistent system with FP32 values, solved to
- * ||b - A x|| <= tol ||b|| by FP32 asynchronous sweeps (row workers bounded by
- * the system's own Corollary 1 limit) inside an FP64 refinement loop
- * (r = b - A x, d from A d = fp32(r), x += d).  One progress() call runs one
+ * ||b - A x|| <= tol ||b|| by asynchronous sweeps (row workers bounded by the
+ * system's own Corollary 1 limit; FP64 correction and FP64 atomics over the
+ * FP32 values) inside an FP64 refinement loop (r = b - A x, d from A d = r,
+ * x += d).  One progress() call runs one
  * round over every active system in one packed launch per phase; requests
  * that arrive meanwhile are admitted as slots, workers and device memory
  * free up.  A request's result does not depend on what else is in the batch
@@ -332,7 +333,7 @@ typedef struct asyrk_server asyrk_server;
 typedef struct asyrk_server_config {
     int64_t budget_bytes;  /* device memory for resident systems (one arena), default 64 GiB */
     int32_t max_slots;     /* systems active at once, default 1024 */
-    int32_t inner_sweeps;  /* FP32 sweeps per round (refinement inner solve), default 8 */
+    int32_t inner_sweeps;  /* sweeps per round (refinement inner solve), default 8 */
     int64_t max_workers;   /* row workers over all active systems, default 65536 */
     int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
     int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */
@@ -353,7 +354,7 @@ typedef struct asyrk_server_config {
 typedef struct asyrk_request_stats {
     int64_t m, n, nnz;
     int64_t in_flight;     /* R_s */
-    int64_t sweeps;        /* FP32 sweeps run */
+    int64_t sweeps;        /* sweeps run (inner solves) */
     int32_t rounds;        /* refinement rounds */
     int32_t status;        /* ASYRK_OK, ASYRK_ERR_NOT_CONVERGED or ASYRK_ERR_DIVERGED */
     double rel_residual;   /* ||b - A x|| / ||b|| of the returned x (FP64) */

@@ -10,11 +10,14 @@
 //               device-memory budget allow (first-fit arena: no device
 //               allocation or free in the loop);
 //       run     one packed launch per phase over every active system:
-//               zero d -> FP32 asynchronous sweeps on A d = fp32(r) ->
-//               x += d (FP64) -> r = b - A x (FP64, also written as the next
-//               round's FP32 right-hand side) -> per-system ||r||^2.
-//               The four launches are captured once in a hipGraph (fixed
-//               grids; kernels read the device slot table).
+//               zero d -> asynchronous sweeps on A d = r (FP32 values, FP64
+//               correction d and FP64 atomics) -> x += d (FP64) ->
+//               r = b - A x (FP64, written to the per-row side records as the
+//               next round's right-hand side) -> per-system ||r||^2.
+//               The four launches are captured once per sweep variant in a
+//               hipGraph (fixed grids; kernels read the device slot table).
+//   Admissions upload on a copy stream; while a busy round computes, the
+//   requests admitted during it join the round after.
 //   poll()     (any thread)  fetch a finished request's x and statistics.
 //
 // Each system runs R_s row workers with R_s bounded by its own Corollary 1
@@ -141,8 +144,8 @@ __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, cons
     }
 }
 
-// r = b - A x64 in FP64 (4 lanes per row); fp32(r) becomes the record's b for
-// the next round; ||r||^2 accumulates per system.
+// r = b - A x64 in FP64 (4 lanes per row); r becomes the side record's
+// right-hand side for the next round; ||r||^2 accumulates per system.
 __global__ __launch_bounds__(256) void srv_residual_kernel(const TableHead *th, const SlotDesc *sl, double *norm2) {
     using T = VT<ASYRK_F32>;
     constexpr int G = 4;
