@@ -126,13 +126,16 @@ def test_budget_admission_and_continuous_batching():
         assert ei.value.name == "OOM"
 
 
-def test_concurrent_submitters_while_rounds_run():
-    """submit() from several threads while one thread drives progress()."""
+@pytest.mark.parametrize("pipe_workers", [8192, 0])
+def test_concurrent_submitters_while_rounds_run(pipe_workers):
+    """submit() from several threads while one thread drives progress().
+    pipe_workers = 0 makes every round with active systems a busy one, so
+    requests arriving meanwhile upload during it and join the next round."""
     import threading
-    _say("server concurrent submitters")
+    _say(f"server concurrent submitters pipe_workers={pipe_workers}")
     systems = _systems(range(400, 424), [1000 + 700 * k for k in range(24)])
     ids = [None] * len(systems)
-    with P.Server(budget_bytes=1 << 30) as srv:
+    with P.Server(budget_bytes=1 << 30, pipe_workers=pipe_workers) as srv:
         def worker(lo):
             for k in range(lo, len(systems), 4):
                 s = systems[k]
@@ -156,6 +159,8 @@ def test_concurrent_submitters_while_rounds_run():
         for k, s in enumerate(systems):
             _check(s, out[k])
         assert len(set(ids)) == len(ids)
+        st = srv.stats()
+        assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
 
 
 @pytest.mark.parametrize("pipe_workers,pipe_lanes", [(0, 8), (1 << 24, 4), (1 << 24, 8), (1 << 24, 16)])
