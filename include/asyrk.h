@@ -96,7 +96,7 @@ typedef struct asyrk_solve_params {
     int32_t lanes;           /* lanes per row G in {1,2,4,8,16,32,64}; 0 = the autotuned
                                 value when the autotuner ran at this R, else the largest
                                 power of two with R * G <= 65536, capped by the smallest
-                                power of two covering an average row's units */
+                                power of two covering the longest row's units (and 64) */
     int64_t in_flight;       /* R, row workers in flight (tau_design = R - 1); 0 = choose */
     double tol;              /* stop when the monitored error <= tol; 0 = run every sweep */
     const double *x_ref;     /* nullable, length n: monitor ||x - x_ref||/||x_ref||;

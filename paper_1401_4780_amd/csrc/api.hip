@@ -118,11 +118,14 @@ constexpr int64_t kPipeMaxR = 8192;
 
 // Lanes per row without autotuning: the sweep saturates once about 2^16
 // lanes are in flight, so G is the largest power of two with R * G <= 2^16,
-// but no wider than the smallest power of two covering a row of average
-// length (more lanes than units leave lanes idle) and at most 64.
+// but no wider than the smallest power of two covering the longest row's
+// units (wider groups only idle) and at most 64.  Sized by the longest row,
+// not the average: with few workers a long row read in several chunks costs a
+// dependent round trip per chunk (heavy-tailed rows: 2-3x faster at G = 64
+// than at the average's G = 8).
 int auto_lanes(const asyrk_system *s, int64_t R) {
     const Geom g = geom_of(s->vk);
-    const double units = ((double)s->nnz / (double)s->m) / g.U;
+    const double units = (double)s->mu / g.U;
     int cover = 1;
     while (cover < 64 && cover < units) cover *= 2;
     int G = 1;
