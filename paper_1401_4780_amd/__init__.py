@@ -314,10 +314,10 @@ class System:
         """Time one sweep per lane-group width and worker loop; the fastest pair
         becomes the default at this R.  Returns (best G, pipelined?, {(G, pipelined): rows/s})."""
         best, pipe = C.c_int32(), C.c_int32()
-        rates = (C.c_double * 10)()
+        rates = (C.c_double * 14)()
         _check(lib().asyrk_autotune(self._h, float(gamma), {None: -1, "f32": F32, "f64": F64}[iter_dtype],
                                     int(in_flight), C.byref(best), C.byref(pipe), rates), "asyrk_autotune")
-        keys = [(g, p) for p in (False, True) for g in (1, 2, 4, 8, 16)]
+        keys = [(g, p) for p in (False, True) for g in (1, 2, 4, 8, 16, 32, 64)]
         return best.value, bool(pipe.value), dict(zip(keys, list(rates)))
 
     # -- the method

@@ -510,12 +510,12 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
     const int64_t R = in_flight ? in_flight : auto_in_flight(s);
     // at least one sweep and at least 2M tickets per candidate
     const int64_t tickets = std::max<int64_t>(s->m, (int64_t)2 << 20);
-    const int cands[5] = {1, 2, 4, 8, 16};
+    const int cands[7] = {1, 2, 4, 8, 16, 32, 64};
     int best = 0, best_pipe = 0;
     double best_rate = 0.0;
     for (int pipe = 0; pipe < 2; ++pipe) {
         p.pipeline = pipe;
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 7; ++k) {
             const int G = cands[k];
             HIP_OK(launch_zero(s->d_x, s->n * 8, s->st));
             double gpu_s = 0.0, a = 0, b = 0, c = 0;
@@ -527,7 +527,7 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
                 best = G;
                 best_pipe = pipe;
             }
-            if (rows_per_s_out) rows_per_s_out[5 * pipe + k] = rate;
+            if (rows_per_s_out) rows_per_s_out[7 * pipe + k] = rate;
         }
     }
     const int xi = xk == ASYRK_F32 ? 1 : 0;

@@ -441,7 +441,7 @@ def test_autotune_picks_a_lane_width():
     _say("autotune")
     sysm = make_system(s, device=True)
     best, pipe, rates = sysm.autotune(in_flight=800)
-    assert best in (1, 2, 4, 8, 16) and len(rates) == 10 and all(r > 0 for r in rates.values())
+    assert best in (1, 2, 4, 8, 16, 32, 64) and len(rates) == 14 and all(r > 0 for r in rates.values())
     assert rates[(best, pipe)] == max(rates.values())
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
     assert st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
