@@ -82,11 +82,14 @@ def cpu_baseline(s, target_s=15.0):
     rate0 = probe / (time.perf_counter() - t0)
     steps = int(min(max(rate0 * target_s, s.m), 12 * s.m))
     t0 = time.perf_counter()
-    oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, steps, 7)
+    # the error after every sweep is one O(n) pass, under 1% of a sweep
+    out = oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, steps, 7, curve_every=s.m,
+                        x_ref=s.x_star, want_res=False)
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "row updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} row updates ({steps / s.m:.2f} sweeps) of the same 4Mx1M system "
-                      f"from x0=0, sequential FP64, single thread, {dt:.1f} s"}
+                      f"from x0=0, sequential FP64, single thread, {dt:.1f} s",
+            "err_curve": [float(v) for v in out["err"]]}
 
 
 def run_c2(args):
@@ -120,7 +123,7 @@ def run_c2(args):
     def solve(seed, R=args.in_flight):
         x.zero_()
         return sysm.solve(x, GAMMA, BUDGET, seed, tol=TOL, x_ref=x_ref, in_flight=R,
-                          lanes=args.lanes)
+                          lanes=args.lanes, history=BUDGET + 1)
 
     for w in range(args.warmup):
         st = solve(1000 + w)
@@ -165,6 +168,9 @@ def run_c2(args):
                    "gamma": GAMMA, "tol": TOL, "in_flight": sts[0]["in_flight"],
                    "lanes": sts[0]["lanes"], "pipelined": sts[0]["pipelined"],
                    "record_stride_bytes": info["record_stride"]},
+        # ||x - x*|| / ||x*|| after every sweep of the first timed solve; the
+        # sequential FP64 oracle's curve on the same system is in cpu_baseline
+        "err_curve": [float(v) for v in sts[0]["history"]],
         "time_to_tol_s_p50": float(np.percentile(lat, 50)),
         "time_to_tol_s_p99": float(np.percentile(lat, 99)),
         "sweeps_to_tol_mean": launches / args.steps,

@@ -158,12 +158,13 @@ def slice_order(m, workers, seed, sweep) -> np.ndarray:
 
 def rk_run(row_ptr, col, val, b, n, x0, gamma, nsteps, seed, *, stream=0, uniform=False,
            update_one=False, tau=0, ticket0=0, curve_every=0, x_ref=None, want_rows=False,
-           slices=False, workers=1):
+           slices=False, workers=1, want_res=True):
     """Sequential RK (eq. (2) with step length gamma) for ``nsteps`` tickets.
 
     Returns a dict with ``x`` and, as requested, ``err`` (||x-x_ref||/||x_ref||),
-    ``res`` (||Ax-b||/||b||) sampled every ``curve_every`` steps (index 0 is
-    the start point) and ``rows`` (the row drawn for every ticket).
+    ``res`` (||Ax-b||/||b||, unless ``want_res`` is false) sampled every
+    ``curve_every`` steps (index 0 is the start point) and ``rows`` (the row
+    drawn for every ticket).
     """
     lib = _load()
     rp = _c(row_ptr, np.int64)
@@ -174,7 +175,7 @@ def rk_run(row_ptr, col, val, b, n, x0, gamma, nsteps, seed, *, stream=0, unifor
     m = rp.size - 1
     npts = (nsteps // curve_every + 1) if curve_every > 0 else 0
     err = np.zeros(npts) if (curve_every > 0 and x_ref is not None) else None
-    res = np.zeros(npts) if curve_every > 0 else None
+    res = np.zeros(npts) if (curve_every > 0 and want_res) else None
     rows = np.zeros(nsteps, dtype=np.int32) if want_rows else None
     xr = None if x_ref is None else _c(x_ref, np.float64)
     rc = lib.orc_rk_run(m, n, _p(rp), _p(cl), _p(v), _p(bb), _p(x), float(gamma), seed, stream,
