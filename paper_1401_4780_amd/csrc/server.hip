@@ -589,7 +589,10 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
         s->workers_in_use += q.R;
         (defer ? s->staged : s->active).push_back(std::move(r));
-        s->stats.admitted++;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);  // stats are read by other threads
+            s->stats.admitted++;
+        }
         admitted = true;
     }
     if (admitted) {
@@ -653,7 +656,8 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     SRV_OK(hipStreamSynchronize(s->st));
     float ms = 0.f;
     SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
-    s->stats.gpu_seconds += ms * 1e-3;
+    int64_t round_rows = 0;
+    for (int k = 0; k < h.nact; ++k) round_rows += (int64_t)cfg.inner_sweeps * s->active[k]->m;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &r : s->active)
@@ -661,8 +665,10 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
                 s->pinned.release(r->pin_off, r->pin_bytes);
                 r->pin_off = -1;
             }
+        s->stats.gpu_seconds += ms * 1e-3;
+        s->stats.rounds++;
+        s->stats.row_updates += round_rows;
     }
-    s->stats.rounds++;
     // ---- bookkeeping and retirement: every finished x is copied out, then one wait
     std::vector<std::unique_ptr<Request>> keep, out;
     for (int k = 0; k < h.nact; ++k) {
@@ -670,7 +676,6 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         r->ticket += (int64_t)cfg.inner_sweeps * r->m;
         r->sweeps += cfg.inner_sweeps;
         r->rounds++;
-        s->stats.row_updates += (int64_t)cfg.inner_sweeps * r->m;
         const double nr = s->h_norm2[k];
         r->rel = r->b_norm2 > 0 ? std::sqrt(nr / r->b_norm2) : std::sqrt(nr);
         const bool conv = r->rel <= r->tol;
