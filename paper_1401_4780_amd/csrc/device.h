@@ -2,6 +2,7 @@
 // kernels (kernels.hip) and the packed serving kernels (server.hip).
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "internal.h"
@@ -10,9 +11,55 @@ namespace asyrk {
 
 // ---------------------------------------------------------------- utilities
 
+// Every pointer the sweep dereferences is device global memory (records,
+// locators, side records, the iterate, the zero pad).  Saying so turns the
+// generic (flat) accesses the compiler emits for pointers it cannot trace -
+// loaded from a table, or selected between two arrays - into global ones:
+// flat accesses may complete out of order with other memory accesses, so
+// while one is outstanding every wait becomes a wait for everything.
+#define ASYRK_GLOBAL __attribute__((address_space(1)))
+
+typedef uint32_t gv2u __attribute__((ext_vector_type(2)));
+typedef uint32_t gv4u __attribute__((ext_vector_type(4)));
+
+// A load of T from global memory.  Structs (int4, float4, headers, locators)
+// are read as native vectors of the same size and copied bitwise: copying a
+// struct through its copy constructor would read it through a generic
+// reference and bring the flat access back.  T must be naturally aligned.
+template <class T>
+__device__ __forceinline__ T gload(const void *p) {
+    T out;
+    if constexpr (sizeof(T) == 2) {
+        const uint16_t v = *(const ASYRK_GLOBAL uint16_t *)p;
+        __builtin_memcpy(&out, &v, 2);
+    } else if constexpr (sizeof(T) == 4) {
+        const uint32_t v = *(const ASYRK_GLOBAL uint32_t *)p;
+        __builtin_memcpy(&out, &v, 4);
+    } else if constexpr (sizeof(T) == 8) {
+        const gv2u v = *(const ASYRK_GLOBAL gv2u *)p;
+        __builtin_memcpy(&out, &v, 8);
+    } else if constexpr (sizeof(T) == 16) {
+        const gv4u v = *(const ASYRK_GLOBAL gv4u *)p;
+        __builtin_memcpy(&out, &v, 16);
+    } else {
+        static_assert(sizeof(T) == 32, "gload: unsupported size");
+        const gv4u a = *(const ASYRK_GLOBAL gv4u *)p;
+        const gv4u b = *(const ASYRK_GLOBAL gv4u *)((const uint8_t *)p + 16);
+        __builtin_memcpy(&out, &a, 16);
+        __builtin_memcpy(reinterpret_cast<uint8_t *>(&out) + 16, &b, 16);
+    }
+    return out;
+}
+
 template <class T>
 __device__ __forceinline__ T load_agent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const ASYRK_GLOBAL T *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// no-return atomic add at agent scope (a hardware float atomic)
+template <class T>
+__device__ __forceinline__ void atomic_add(T *p, T v) {
+    (void)__hip_atomic_fetch_add((ASYRK_GLOBAL T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __uint_as_float(bits << 16); }
@@ -22,21 +69,24 @@ __device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t 
         rec = r.rec + (int64_t)i * r.stride;
         nnz = r.fixed_nnz;
     } else {
-        const RowLoc l = r.loc[i];
+        const RowLoc l = gload<RowLoc>(r.loc + i);
         rec = r.rec + (int64_t)l.off16 * 16;
         nnz = (int)l.nnz;
     }
 }
 
-// 64 zero bytes: the read-only stand-in for an absent unit or row locator,
-// so that loads can be issued unconditionally (no branch, no wait at a join).
-static __device__ __attribute__((aligned(64))) const uint8_t kZeroPad[64] = {0};
+// 64 zero bytes: the stand-in for an absent unit or row locator, so that
+// loads can be issued unconditionally (no branch, no wait at a join).  Never
+// written.  Not declared const: a const device array lives in the constant
+// address space, and a pointer selected between it and a global array can
+// only be generic, which brings back the flat accesses avoided above.
+static __device__ __attribute__((aligned(64))) uint8_t kZeroPad[64] = {0};
 
 // locate() without a branch: the locator is read from kZeroPad for
 // fixed-stride rows and the values are picked by select.
 __device__ __forceinline__ void locate_nb(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
     const bool ragged = r.loc != nullptr;
-    const RowLoc l = *(ragged ? r.loc + i : reinterpret_cast<const RowLoc *>(kZeroPad));
+    const RowLoc l = gload<RowLoc>(ragged ? (const void *)(r.loc + i) : (const void *)kZeroPad);
     rec = ragged ? r.rec + (int64_t)l.off16 * 16 : r.rec + (int64_t)i * r.stride;
     nnz = ragged ? (int)l.nnz : r.fixed_nnz;
 }
@@ -46,8 +96,8 @@ template <> struct Unit<ASYRK_F32> {
     int c[4];
     float v[4];
     __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 ci = *reinterpret_cast<const int4 *>(p);
-        const float4 vi = *reinterpret_cast<const float4 *>(p + 16);
+        const int4 ci = gload<int4>(p);
+        const float4 vi = gload<float4>(p + 16);
         c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
         v[0] = vi.x; v[1] = vi.y; v[2] = vi.z; v[3] = vi.w;
     }
@@ -56,9 +106,9 @@ template <> struct Unit<ASYRK_BF16> {
     int c[8];
     float v[8];
     __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 c0 = *reinterpret_cast<const int4 *>(p);
-        const int4 c1 = *reinterpret_cast<const int4 *>(p + 16);
-        const uint4 vb = *reinterpret_cast<const uint4 *>(p + 32);
+        const int4 c0 = gload<int4>(p);
+        const int4 c1 = gload<int4>(p + 16);
+        const uint4 vb = gload<uint4>(p + 32);
         c[0] = c0.x; c[1] = c0.y; c[2] = c0.z; c[3] = c0.w;
         c[4] = c1.x; c[5] = c1.y; c[6] = c1.z; c[7] = c1.w;
         v[0] = bf16_to_f32(vb.x & 0xffffu); v[1] = bf16_to_f32(vb.x >> 16);
@@ -71,9 +121,9 @@ template <> struct Unit<ASYRK_F64> {
     int c[4];
     double v[4];
     __device__ __forceinline__ void load(const uint8_t *p) {
-        const int4 ci = *reinterpret_cast<const int4 *>(p);
-        const double2 v0 = *reinterpret_cast<const double2 *>(p + 16);
-        const double2 v1 = *reinterpret_cast<const double2 *>(p + 32);
+        const int4 ci = gload<int4>(p);
+        const double2 v0 = gload<double2>(p + 16);
+        const double2 v1 = gload<double2>(p + 32);
         c[0] = ci.x; c[1] = ci.y; c[2] = ci.z; c[3] = ci.w;
         v[0] = v0.x; v[1] = v0.y; v[2] = v1.x; v[3] = v1.y;
     }
@@ -81,7 +131,7 @@ template <> struct Unit<ASYRK_F64> {
 
 template <int VK>
 __device__ __forceinline__ typename VT<VK>::hdr_t load_hdr(const uint8_t *rec) {
-    return *reinterpret_cast<const typename VT<VK>::hdr_t *>(rec);
+    return gload<typename VT<VK>::hdr_t>(rec);
 }
 
 // Entry `pos` of a row record (column, value), read directly.
@@ -91,11 +141,11 @@ __device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
     using T = VT<VK>;
     const uint8_t *u = rec + T::HB + (int64_t)(pos / T::U) * T::UB;
     const int e = pos % T::U;
-    c = *reinterpret_cast<const int *>(u + 4 * e);
+    c = gload<int>(u + 4 * e);
     if constexpr (VK == ASYRK_BF16)
-        v = bf16_to_f32(*reinterpret_cast<const uint16_t *>(u + T::COLB + 2 * e));
+        v = bf16_to_f32(gload<uint16_t>(u + T::COLB + 2 * e));
     else
-        v = *reinterpret_cast<const typename T::val_t *>(u + T::COLB + T::VB * e);
+        v = gload<typename T::val_t>(u + T::COLB + T::VB * e);
 }
 
 template <int G, class X>
@@ -203,7 +253,7 @@ __device__ __forceinline__ uint64_t process_ticket(
     // a4: step s = gamma * (a_i^T x - b_i) / ||a_i||^2
     X bi, inv_w;
     if constexpr (SIDE) {
-        const double2 sd = side[i];
+        const double2 sd = gload<double2>(side + i);
         bi = sd.x;
         inv_w = sd.y;
     } else {
@@ -222,7 +272,7 @@ __device__ __forceinline__ uint64_t process_ticket(
                 if (uu < nunits) {
 #pragma unroll
                     for (int e = 0; e < U; ++e)
-                        if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                        if (uu * U + e < nnz) atomic_add(x + un[q].c[e], -s * (X)un[q].v[e]);
                 }
             }
         } else {
@@ -234,7 +284,7 @@ __device__ __forceinline__ uint64_t process_ticket(
                         un[q].load(rec + T::HB + (int64_t)uu * T::UB);
 #pragma unroll
                         for (int e = 0; e < U; ++e)
-                            if (uu * U + e < nnz) unsafeAtomicAdd(x + un[q].c[e], -s * (X)un[q].v[e]);
+                            if (uu * U + e < nnz) atomic_add(x + un[q].c[e], -s * (X)un[q].v[e]);
                     }
                 }
             }
@@ -246,25 +296,32 @@ __device__ __forceinline__ uint64_t process_ticket(
         typename VT<VK>::x_t v;
         load_entry<VK>(rec, t, c, v);
         const X s1 = gamma * (X)nnz * r * inv_w;
-        unsafeAtomicAdd(x + c, -s1 * (X)v);
+        atomic_add(x + c, -s1 * (X)v);
     }
     return trace ? wall_clock64() - t0 : 0;
 }
 
 // The tickets j0, j0 + step, ... < j_end of one worker with the steps of
-// process_ticket (sampled rows, all-coordinate update), arranged so that a
-// ticket costs two dependent memory round trips instead of one per access:
+// process_ticket (sampled rows, all-coordinate update), software pipelined
+// so that a ticket costs about one memory round trip instead of one per
+// access.  For ticket t:
 //
-//   1. the next ticket's row locator is requested together with this
-//      ticket's gathers, which are issued back to back (padded slots read
-//      x[0] and are masked out by a select, so no branch splits them) and
-//      waited for once;
-//   2. the atomics are issued while no load is outstanding, then the next
-//      ticket's record is requested; its wait overlaps the atomics.
+//   1. t's gathers are issued back to back (padded slots read x[0] and are
+//      masked out by a select, so no branch splits them);
+//   2. t+1's record is requested (its row locator arrived during t-1), then
+//      t+2's locator;
+//   3. t's gathers are consumed: the wait covers them only, not the loads of
+//      step 2, which were issued later;
+//   4. t's atomics are issued, with no load waited for between them;
+//   5. t+1's alias decision needs its record header: that wait covers loads
+//      issued before t's atomics only, so t+1's gathers leave while t's
+//      atomics are still in flight.
 //
-// Row records are read-only during a sweep, so fetching the next record
-// early moves no read of x: the gathers of ticket t + 1 are still issued
-// after the atomics of ticket t.
+// Row records are read-only during a sweep, so fetching them early moves no
+// read of x.  A worker's gathers for t+1 follow its atomics for t in program
+// order; the memory system keeps one wave's accesses to one address in order,
+// so the worker still sees its own update (the one-worker pipelined run
+// equals the sequential oracle to 1e-12).
 template <int VK, int XK, int G, int UPL = Upl<G>::value>
 __device__ __forceinline__ void run_tickets_pipelined(
     const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
@@ -289,9 +346,8 @@ __device__ __forceinline__ void run_tickets_pipelined(
         }
     };
     auto fetch_units = [&](const uint8_t *rec, int nunits, Unit<VK> *dst) { fetch_chunk(rec, 0, nunits, dst); };
-    // branch-free gather-dot of one chunk held in registers
-    auto chunk_dot = [&](const Unit<VK> *cu, int base, int nnz, X acc) {
-        X xv[UPL][U];
+    // branch-free gathers of one chunk held in registers, issued ...
+    auto gather_issue = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U]) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
@@ -299,6 +355,9 @@ __device__ __forceinline__ void run_tickets_pipelined(
                 const bool ok = (base + gl + q * G) * U + e < nnz;
                 xv[q][e] = load_agent(x + (ok ? cu[q].c[e] : 0));
             }
+    };
+    // ... and consumed
+    auto gather_dot = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U], X acc) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
@@ -313,7 +372,17 @@ __device__ __forceinline__ void run_tickets_pipelined(
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
             for (int e = 0; e < U; ++e)
-                if ((base + gl + q * G) * U + e < nnz) unsafeAtomicAdd(x + cu[q].c[e], -s * (X)cu[q].v[e]);
+                if ((base + gl + q * G) * U + e < nnz) atomic_add(x + cu[q].c[e], -s * (X)cu[q].v[e]);
+    };
+    // a row's locator is loaded in one ticket and used in the next, so the
+    // loaded word is carried raw (a value used at once would be waited for at once)
+    auto locator_load = [&](uint32_t r) -> RowLoc {
+        return gload<RowLoc>(rows.loc != nullptr ? (const void *)(rows.loc + r) : (const void *)kZeroPad);
+    };
+    auto from_locator = [&](uint32_t r, const RowLoc &l, const uint8_t *&rec, int &nnz) {
+        const bool ragged = rows.loc != nullptr;
+        rec = ragged ? rows.rec + (int64_t)l.off16 * 16 : rows.rec + (int64_t)r * rows.stride;
+        nnz = ragged ? (int)l.nnz : rows.fixed_nnz;
     };
     // the alias branch of the draw (needs the bucket row's header)
     auto resolve = [&](const U4 &u, uint32_t &i, const uint8_t *&rec, int &nnz, H &h, Unit<VK> *dst) {
@@ -322,20 +391,12 @@ __device__ __forceinline__ void run_tickets_pipelined(
             locate_nb(rows, i, rec, nnz);
             h = load_hdr<VK>(rec);
             fetch_units(rec, (nnz + U - 1) / U, dst);
+            return true;
         }
-    };
-    auto coeffs = [&](uint32_t i, const H &h, X &bi, X &inv_w) {
-        if constexpr (SIDE) {
-            const double2 sd = side[i];
-            bi = sd.x;
-            inv_w = sd.y;
-        } else {
-            bi = (X)h.b;
-            inv_w = (X)h.inv_w;
-        }
+        return false;
     };
 
-    // prologue: the first ticket, fetched in full
+    // prologue: ticket j in full, ticket j + step's locator
     U4 u = draw(j, stream_id, k0, k1);
     uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
     const uint8_t *rec;
@@ -346,29 +407,62 @@ __device__ __forceinline__ void run_tickets_pipelined(
     fetch_units(rec, (nnz + U - 1) / U, un);
     resolve(u, i, rec, nnz, h, un);
     X bi, inv_w;
-    coeffs(i, h, bi, inv_w);
+    if constexpr (SIDE) {
+        const double2 sd = gload<double2>(side + i);
+        bi = sd.x;
+        inv_w = sd.y;
+    } else {
+        bi = (X)h.b;
+        inv_w = (X)h.inv_w;
+    }
+    // (tickets drawn past the end have valid rows and are simply not used)
+    U4 u1 = draw(j + step, stream_id, k0, k1);
+    uint32_t i1 = bucket_of(u1.a, u1.b, (uint32_t)rows.m);
+    RowLoc l1 = locator_load(i1);
 
     for (;;) {
         const int64_t jn = j + step;
         const bool more = jn < j_end;
-        // the next ticket's row and locator, requested with this ticket's gathers
-        // (drawn even past the end: the row is valid and simply not used)
-        U4 u2 = draw(jn, stream_id, k0, k1);
-        uint32_t i2 = bucket_of(u2.a, u2.b, (uint32_t)rows.m);
-        const uint8_t *rec2;
-        int nnz2;
-        locate_nb(rows, i2, rec2, nnz2);
-        // gather-dot: first chunk from registers, further chunks (long rows) re-read
         const int nunits = (nnz + U - 1) / U;
-        X acc = chunk_dot(un, 0, nnz, (X)0);
+        // 1. this ticket's gathers
+        X xv[UPL][U];
+        gather_issue(un, 0, nnz, xv);
+        // 2. the next ticket's record, then the locator of the one after
+        const uint8_t *rec1;
+        int nnz1;
+        from_locator(i1, l1, rec1, nnz1);
+        // (with side records only the sampling fields are read: loading the
+        // unused b_i, 1/w_i lets the allocator reuse their registers while
+        // the load is in flight, which forces a wait for everything)
+        H h1;
+        if constexpr (SIDE) {
+            const gv2u ta = gload<gv2u>(rec1 + offsetof(H, thresh));
+            h1.thresh = ta.x;
+            h1.alias = (int32_t)ta.y;
+        } else {
+            h1 = load_hdr<VK>(rec1);
+        }
+        Unit<VK> un1[UPL];
+        fetch_units(rec1, (nnz1 + U - 1) / U, un1);
+        double2 sd1{0.0, 0.0};
+        if constexpr (SIDE) sd1 = gload<double2>(side + i1);
+        const U4 u2 = draw(jn + step, stream_id, k0, k1);
+        const uint32_t i2 = bucket_of(u2.a, u2.b, (uint32_t)rows.m);
+        const RowLoc l2 = locator_load(i2);
+        // 3. gather-dot: the first chunk from registers (waiting for these
+        // gathers only), then further chunks of long rows, re-read after it so
+        // that neither a loop entry nor its exit joins the wait above
+        X acc = gather_dot(un, 0, nnz, xv, (X)0);
         for (int base = G * UPL; base < nunits; base += G * UPL) {
             Unit<VK> t[UPL];
             fetch_chunk(rec, base, nunits, t);
-            acc = chunk_dot(t, base, nnz, acc);
+            X tv[UPL][U];
+            gather_issue(t, base, nnz, tv);
+            acc = gather_dot(t, base, nnz, tv, acc);
         }
         acc = group_sum<G>(acc);
         const X s = gamma * (acc - bi) * inv_w;
-        // lock-free scatter
+        // 4. lock-free scatter
         chunk_scatter(un, 0, nnz, s);
         for (int base = G * UPL; base < nunits; base += G * UPL) {
             Unit<VK> t[UPL];
@@ -376,20 +470,26 @@ __device__ __forceinline__ void run_tickets_pipelined(
             chunk_scatter(t, base, nnz, s);
         }
         if (!more) break;
-        // the next ticket's record; its wait overlaps the atomics above
-        H h2 = load_hdr<VK>(rec2);
-        Unit<VK> un2[UPL];
-        fetch_units(rec2, (nnz2 + U - 1) / U, un2);
-        resolve(u2, i2, rec2, nnz2, h2, un2);
-        coeffs(i2, h2, bi, inv_w);
+        // 5. rotate: the next ticket becomes current
+        if (resolve(u1, i1, rec1, nnz1, h1, un1)) {
+            if constexpr (SIDE) sd1 = gload<double2>(side + i1);
+        }
+        if constexpr (SIDE) {
+            bi = sd1.x;
+            inv_w = sd1.y;
+        } else {
+            bi = (X)h1.b;
+            inv_w = (X)h1.inv_w;
+        }
         j = jn;
-        u = u2;
-        i = i2;
-        rec = rec2;
-        nnz = nnz2;
-        h = h2;
+        i = i1;
+        rec = rec1;
+        nnz = nnz1;
 #pragma unroll
-        for (int q = 0; q < UPL; ++q) un[q] = un2[q];
+        for (int q = 0; q < UPL; ++q) un[q] = un1[q];
+        u1 = u2;
+        i1 = i2;
+        l1 = l2;
     }
 }
 

@@ -129,7 +129,10 @@ hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStr
 template <int VK, int XK>
 static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     const int64_t threads = a.R * G;
-    const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
+    // The pipelined loop serves the latency-bound regime (few workers): one
+    // wave per block spreads those workers over as many CUs as there are
+    // waves instead of packing four waves onto each CU's memory pipeline.
+    const int block = a.pipe ? 64 : (threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256);
     const int64_t grid = (threads + block - 1) / block;
     if (a.pipe) {
         switch (G) {

@@ -324,17 +324,18 @@ int64_t request_bytes(const Request &r) {
 hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
     const int wblocks = kVecBlocks;
     const dim3 grid(s->sweep_blocks[pipe]);
+    const dim3 block(pipe ? 64 : 256);  // light rounds: one wave per block, spread over the CUs
     hipLaunchKernelGGL(srv_zero_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
     if (pipe) {
         switch (s->cfg.pipe_lanes) {
-            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
-            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
-            default: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(256), 0, st, s->d_head, s->d_slots); break;
+            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, block, 0, st, s->d_head, s->d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, block, 0, st, s->d_head, s->d_slots); break;
+            default: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, block, 0, st, s->d_head, s->d_slots); break;
         }
     } else if (s->cfg.lanes == 4) {
-        hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(256), 0, st, s->d_head, s->d_slots);
+        hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, block, 0, st, s->d_head, s->d_slots);
     } else {
-        hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, dim3(256), 0, st, s->d_head, s->d_slots);
+        hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, block, 0, st, s->d_head, s->d_slots);
     }
     hipLaunchKernelGGL(srv_axpy_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots);
     hipLaunchKernelGGL(srv_residual_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
@@ -424,7 +425,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         s->pinned.free_[0] = cfg.pinned_bytes;
     }
     s->sweep_blocks[0] = (int)((cfg.max_workers * cfg.lanes + 255) / 256);
-    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.pipe_lanes + 255) / 256);
+    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.pipe_lanes + 63) / 64);
     std::memset(s->h_head, 0, sizeof(TableHead));
     if (cfg.use_graph) {
         // capture the four phases once per sweep variant; they read the slot

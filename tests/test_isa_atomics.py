@@ -6,10 +6,9 @@ flags and checks what the hot path relies on:
 * every sweep kernel scatters with hardware float atomics
   (global/flat_atomic_add_f32 or _f64), never a compare-and-swap loop;
 * no packed-FP32 instruction appears anywhere (the build disables them);
-* the pipelined worker loop issues a lane's gathers for a ticket back to
-  back: at least min(entries the lane holds, 8) agent-scope loads in a row
-  with no wait between them (a lane's 4-8 entries all at once; longer lanes
-  are split by the register allocator into a few runs).
+* the pipelined worker loop issues a lane's gathers for a ticket together:
+  at least one unit's entries (4, or 8 for BF16) of agent-scope loads in a
+  row with no wait between them, never one load per wait.
 """
 import re
 import shutil
@@ -78,6 +77,11 @@ def _lane_entries(name):
     return u * upl
 
 
+def _unit_entries(name):
+    m = re.search(r"17sweep_pipe_kernelILi(\d)E", name)
+    return 8 if (m and int(m.group(1)) == 2) else 4
+
+
 def test_pipelined_gathers_issue_back_to_back(kernels):
     """A lane's gathers for a ticket leave together, not one per wait."""
     pipe = {k: v for k, v in kernels.items() if "sweep_pipe_kernel" in k}
@@ -91,7 +95,9 @@ def test_pipelined_gathers_issue_back_to_back(kernels):
                 best = max(best, run)
             elif t.startswith("s_waitcnt"):
                 run = 0
-        # lanes holding 32-64 entries see the run split in two or three for
-        # registers; serialized gathers would show runs of one
-        want = min(_lane_entries(name), 8)
+        # at least one unit's entries leave together: a lane whose units are
+        # still arriving issues each unit's gathers as soon as that unit lands
+        # (waits for unit data, not between gathers); serialized gathers would
+        # show runs of one
+        want = min(_lane_entries(name), _unit_entries(name))
         assert best >= want, (name, best, want)
