@@ -54,16 +54,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
+def traffic_from_profile(kernel):
     """HBM bytes per sweep launch measured with rocprofv3 counters, if the
-    committed summary was taken on the current kernel sources."""
+    committed summary was taken on the current kernel sources and on the same
+    kernel instance."""
     p = ROOT / "profiles" / "sweep_kernel_c2_4Mx1M_f32values_f64iter_traffic.md"
     if not p.exists():
         return None
     text = p.read_text()
     mh = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    mk = re.search(r"profiled_kernel:\s*(\S+)", text)
     mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not mh or not mb or mh.group(1) != kernel_source_hash():
+    if not mh or not mk or not mb or mh.group(1) != kernel_source_hash() or mk.group(1) != kernel:
         return None
     return float(mb.group(1))
 
@@ -148,7 +150,9 @@ def run_c2(args):
     bytes_per_row = info["record_bytes_per_row"] + SIDE_EXTRA_BYTES
     per_launch_s = kern_s / launches
     achieved = bytes_per_row * M / per_launch_s / 1e9
-    traffic = traffic_from_profile()
+    kernel = (("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
+              + f"<F32,F64,{sts[0]['lanes']}>")
+    traffic = traffic_from_profile(kernel)
 
     result = {
         "metric": "row updates/s + time-to-1e-6 residual vs plain RK; p50/p99 solve latency",
@@ -181,8 +185,7 @@ def run_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": ("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
-                     + f"<F32,F64,{sts[0]['lanes']}>", "algorithmic_bytes_per_row": bytes_per_row,
+                     "kernel": kernel, "algorithmic_bytes_per_row": bytes_per_row,
                      "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
     }
 

@@ -290,7 +290,9 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
  * lane-group width G in {1, 2, 4, 8, 16, 32, 64} and each worker loop (plain,
  * pipelined) on this system, at in_flight workers (0 = the default R) and the
  * given iterate dtype (-1 = default), and keeps the fastest pair for later
- * solves with lanes = 0 and pipeline = -1 at that R.  best_lanes and
+ * solves with lanes = 0 and pipeline = -1 at that R.  Near-ties go by a fixed
+ * rule: the pipelined loop only when its best rate beats the plain loop's by
+ * more than 3%, then the smallest G within 2% of that loop's best.  best_lanes and
  * best_pipeline (nullable) receive it; rows_per_s (nullable, double[14]) the
  * rate of each candidate: [0..6] plain, [7..13] pipelined, G ascending.  The
  * system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,
