@@ -401,7 +401,7 @@ def run_serving(args):
         systems = list(pool.map(gen, range(first, first + count)))
         t0 = P.now() + 0.05
         ids = [None] * count
-        sub_pool = ThreadPoolExecutor(8)
+        sub_pool = ThreadPoolExecutor(args.submit_threads)
 
         id_of = {}
 
@@ -475,7 +475,8 @@ def run_serving(args):
                        "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
-                       "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"]},
+                       "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"],
+                       "submit_threads": args.submit_threads},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
@@ -488,6 +489,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
+    ap.add_argument("--submit-threads", type=int, default=8,
+                    help="serving: client threads calling submit (each packs its own requests)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--inner", type=int, default=0, help="refinement inner sweeps (0: default)")
     ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed", "serving"])

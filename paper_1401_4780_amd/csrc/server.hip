@@ -244,8 +244,8 @@ struct Request {
     double tol = 1e-8, b_norm2 = 0.0, fro2 = 0.0, lam = 0.0;
     uint64_t seed = 0;
     SetupResult pack;
-    std::vector<double> b64;
-    std::vector<double> side;  // {b_i, 1/||a_i||^2} per row until staged in pinned memory
+    std::vector<double> b64;   // b and the side records {b_i, 1/||a_i||^2} when no
+    std::vector<double> side;  // pinned staging block was free at submit
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
     // active state
     int slot = -1;
@@ -253,7 +253,7 @@ struct Request {
     int64_t off_rec = -1, off_loc = -1, off_b = -1, off_side = -1, off_x = -1, off_d = -1;
     int64_t bytes = 0;
     int64_t rec_bytes = 0;    // packed record bytes
-    int64_t pin_off = -1;     // staging copy of rec | loc | b64 in the pinned arena, or -1
+    int64_t pin_off = -1;     // staging block rec | loc | b64 | side in the pinned arena, or -1
     int64_t pin_bytes = 0;
     int64_t ticket = 0;
     int32_t rounds = 0;
@@ -316,7 +316,7 @@ asyrk_status srv_fail(hipError_t e) {
     } while (0)
 
 int64_t request_bytes(const Request &r) {
-    return Arena::round_up((int64_t)r.pack.rec.size()) + Arena::round_up((int64_t)r.pack.loc.size() * 8) +
+    return Arena::round_up(r.rec_bytes) + Arena::round_up((int64_t)r.pack.loc.size() * 8) +
            Arena::round_up(r.m * 8) + Arena::round_up(r.m * 16) + Arena::round_up(r.n * 8) +
            Arena::round_up(r.n * 8) + 6 * 256;
 }
@@ -464,51 +464,64 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     if (!r) return ASYRK_ERR_OOM;
     asyrk_status rc = validate_system(m, n, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack);
     if (rc) return rc;
-    rc = pack_records(m, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack);
+    std::vector<uint32_t> thresh;
+    std::vector<int32_t> alias;
+    build_alias(r->pack.w, thresh, alias);
+    rc = plan_records(m, row_ptr, ASYRK_F32, r->pack, &r->rec_bytes);
     if (rc) return rc;
     r->m = m;
     r->n = n;
     r->nnz = r->pack.nnz;
     r->tol = tol;
     r->seed = seed;
-    r->b64.assign(b, b + m);
-    // the first round's correction system has right-hand side r_0 = b (x_0 = 0)
-    r->side.resize((size_t)m * 2);
-    for (int64_t i = 0; i < m; ++i) {
-        r->side[2 * i] = b[i];
-        r->side[2 * i + 1] = r->pack.w[i] > 0.0 ? 1.0 / r->pack.w[i] : 0.0;
-    }
     double bn = 0.0;
     for (int64_t i = 0; i < m; ++i) bn += b[i] * b[i];
     r->b_norm2 = bn;
     r->fro2 = r->pack.fro2;
     const double q = std::sqrt((double)n / (double)m);
     r->lam = std::max((1.0 + q) * (1.0 + q) * r->fro2 / (double)n, r->pack.max_col_norm2);
-    r->rec_bytes = (int64_t)r->pack.rec.size();
     r->bytes = request_bytes(*r);
     if (r->bytes > s->cfg.budget_bytes) return ASYRK_ERR_OOM;
-    // stage rec | loc | b64 | side in pinned memory so admission is a plain DMA
-    const int64_t lrec = Arena::round_up((int64_t)r->pack.rec.size());
+    // The records, locators, b and the first round's side records
+    // {r_0 = b (x_0 = 0), 1/||a_i||^2} are written straight into a pinned
+    // staging block laid out as rec | loc | b64 | side, so admission is one
+    // DMA; without room there they go to pageable vectors.
+    const int64_t lrec = Arena::round_up(r->rec_bytes);
     const int64_t lloc = Arena::round_up((int64_t)r->pack.loc.size() * 8);
     const int64_t lb = Arena::round_up(m * 8);
     const int64_t lside = Arena::round_up(m * 16);
+    int64_t off = -1;
     if (s->pinned.base) {
-        int64_t off;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            off = s->pinned.alloc(lrec + lloc + lb + lside);
+        std::lock_guard<std::mutex> lk(s->mu);
+        off = s->pinned.alloc(lrec + lloc + lb + lside);
+    }
+    uint8_t *p_rec, *p_b, *p_side;
+    if (off >= 0) {
+        uint8_t *p = s->pinned.base + off;
+        p_rec = p;
+        if (!r->pack.loc.empty()) std::memcpy(p + lrec, r->pack.loc.data(), r->pack.loc.size() * 8);
+        p_b = p + lrec + lloc;
+        p_side = p + lrec + lloc + lb;
+        r->pin_off = off;
+        r->pin_bytes = lrec + lloc + lb + lside;
+    } else {
+        try {
+            r->pack.rec.resize((size_t)r->rec_bytes);
+            r->b64.resize((size_t)m);
+            r->side.resize((size_t)m * 2);
+        } catch (...) {
+            return ASYRK_ERR_OOM;
         }
-        if (off >= 0) {
-            uint8_t *p = s->pinned.base + off;
-            std::memcpy(p, r->pack.rec.data(), r->pack.rec.size());
-            if (!r->pack.loc.empty()) std::memcpy(p + lrec, r->pack.loc.data(), r->pack.loc.size() * 8);
-            std::memcpy(p + lrec + lloc, b, (size_t)m * 8);
-            std::memcpy(p + lrec + lloc + lb, r->side.data(), (size_t)m * 16);
-            r->pin_off = off;
-            r->pin_bytes = lrec + lloc + lb + lside;
-            std::vector<uint8_t>().swap(r->pack.rec);  // the staged copy replaces it
-            std::vector<double>().swap(r->side);
-        }
+        p_rec = r->pack.rec.data();
+        p_b = reinterpret_cast<uint8_t *>(r->b64.data());
+        p_side = reinterpret_cast<uint8_t *>(r->side.data());
+    }
+    write_records(m, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack, thresh.data(), alias.data(), p_rec);
+    std::memcpy(p_b, b, (size_t)m * 8);
+    double *side = reinterpret_cast<double *>(p_side);
+    for (int64_t i = 0; i < m; ++i) {
+        side[2 * i] = b[i];
+        side[2 * i + 1] = 1.0 / r->pack.w[i];
     }
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(s->mu);
@@ -577,7 +590,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             SRV_OK(hipMemcpyAsync(base + q.off_rec, s->pinned.base + q.pin_off, q.pin_bytes, hipMemcpyHostToDevice,
                                   s->cst));
         } else {
-            SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.pack.rec.size(), hipMemcpyHostToDevice,
+            SRV_OK(hipMemcpyAsync(base + q.off_rec, q.pack.rec.data(), q.rec_bytes, hipMemcpyHostToDevice,
                                   s->cst));
             if (!q.pack.loc.empty())
                 SRV_OK(hipMemcpyAsync(base + q.off_loc, q.pack.loc.data(), q.pack.loc.size() * 8,

@@ -42,6 +42,103 @@ static void parallel_rows(int64_t m, F fn) {
     for (auto &x : th) x.join();
 }
 
+template <int VK>
+static inline double promote_t(const void *vals, int64_t k) {
+    if constexpr (VK == ASYRK_F64) {
+        return static_cast<const double *>(vals)[k];
+    } else if constexpr (VK == ASYRK_F32) {
+        return (double)static_cast<const float *>(vals)[k];
+    } else {
+        const uint32_t u = (uint32_t) static_cast<const uint16_t *>(vals)[k] << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return (double)f;
+    }
+}
+
+// Rows lo..hi-1: sorted in-range columns, finite values, w_i (FP64, CSR
+// order).  With cnt/cn2 the column statistics are accumulated in the same pass
+// (entries in increasing k, as the separate pass would).  Returns false on an
+// invalid entry.
+template <int VK>
+static bool scan_rows(int64_t lo, int64_t hi, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                      const void *vals, double *w, int64_t &mu_out, int32_t *cnt, double *cn2) {
+    int64_t mu = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
+        mu = std::max(mu, end - beg);
+        double s = 0.0;
+        int32_t prev = -1;
+        for (int64_t k = beg; k < end; ++k) {
+            const int32_t c = col[k];
+            if (c <= prev || c >= n) return false;
+            prev = c;
+            const double v = promote_t<VK>(vals, k);
+            if (!std::isfinite(v)) return false;
+            const double v2 = v * v;
+            s = s + v2;
+            if (cnt) {
+                cnt[c]++;
+                cn2[c] += v2;
+            }
+        }
+        w[i] = s;
+    }
+    mu_out = mu;
+    return true;
+}
+
+template <int VK>
+static asyrk_status validate_t(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col, const void *vals,
+                               SetupResult &out) {
+    const int64_t nnz = row_ptr[m];
+    out.w.resize(m);
+    std::vector<int32_t> cnt(n, 0);
+    std::vector<double> cn2(n, 0.0);
+    unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+    if (m < 65536) nt = 1;
+    int64_t mu = 0;
+    if (nt == 1) {
+        if (!scan_rows<VK>(0, m, n, row_ptr, col, vals, out.w.data(), mu, cnt.data(), cn2.data()))
+            return ASYRK_ERR_INVALID_ARG;
+    } else {
+        std::vector<int> bad(nt, 0);
+        std::vector<int64_t> mu_t(nt, 0);
+        std::vector<std::thread> th;
+        const int64_t chunk = (m + nt - 1) / nt;
+        for (unsigned t = 0; t < nt; ++t) {
+            const int64_t lo = t * chunk, hi = std::min<int64_t>(m, lo + chunk);
+            if (lo >= hi) break;
+            th.emplace_back([&, t, lo, hi]() {
+                bad[t] = !scan_rows<VK>(lo, hi, n, row_ptr, col, vals, out.w.data(), mu_t[t], nullptr, nullptr);
+            });
+        }
+        for (auto &x : th) x.join();
+        for (unsigned t = 0; t < nt; ++t) {
+            if (bad[t]) return ASYRK_ERR_INVALID_ARG;
+            mu = std::max(mu, mu_t[t]);
+        }
+        for (int64_t k = 0; k < nnz; ++k) {
+            const double v = promote_t<VK>(vals, k);
+            cnt[col[k]]++;
+            cn2[col[k]] += v * v;
+        }
+    }
+    for (int64_t i = 0; i < m; ++i)
+        if (!(out.w[i] > 0.0)) return ASYRK_ERR_ZERO_ROW;
+    out.mu = mu;
+    out.nu = *std::max_element(cnt.begin(), cnt.end());
+    out.max_col_norm2 = *std::max_element(cn2.begin(), cn2.end());
+    out.fixed_nnz = row_ptr[1] - row_ptr[0];
+    for (int64_t i = 1; i < m && out.fixed_nnz > 0; ++i)
+        if (row_ptr[i + 1] - row_ptr[i] != out.fixed_nnz) out.fixed_nnz = 0;
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < m; ++i) fro2 = fro2 + out.w[i];
+    out.fro2 = fro2;
+    out.nnz = nnz;
+    return ASYRK_OK;
+}
+
 // Validation of A and b; fills the row weights w_i = ||a_i||^2 (FP64 from the
 // stored values, summed in CSR order) and the column-count statistics.
 asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -57,69 +154,11 @@ asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const
     if (nnz > 0 && (!col || !vals)) return ASYRK_ERR_INVALID_ARG;
     for (int64_t i = 0; i < m; ++i)
         if (!std::isfinite(b[i])) return ASYRK_ERR_INVALID_ARG;
-
-    out.w.assign(m, 0.0);
-    std::vector<int> bad_t(16, 0);
-    std::vector<int64_t> mu_t(16, 0);
-    int tix = 0;
-    std::vector<std::pair<int64_t, int64_t>> ranges;
-    {
-        unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
-        if (m < 65536) nt = 1;
-        const int64_t chunk = (m + nt - 1) / nt;
-        for (unsigned t = 0; t < nt; ++t) {
-            const int64_t lo = t * chunk, hi = std::min<int64_t>(m, lo + chunk);
-            if (lo < hi) ranges.emplace_back(lo, hi);
-        }
+    switch (vk) {
+        case ASYRK_F64: return validate_t<ASYRK_F64>(m, n, row_ptr, col, vals, out);
+        case ASYRK_F32: return validate_t<ASYRK_F32>(m, n, row_ptr, col, vals, out);
+        default: return validate_t<ASYRK_BF16>(m, n, row_ptr, col, vals, out);
     }
-    std::vector<std::thread> th;
-    for (auto &rg : ranges) {
-        const int me = tix++;
-        th.emplace_back([&, me, rg]() {
-            int64_t mu = 0;
-            for (int64_t i = rg.first; i < rg.second; ++i) {
-                const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
-                mu = std::max(mu, end - beg);
-                double s = 0.0;
-                int32_t prev = -1;
-                for (int64_t k = beg; k < end; ++k) {
-                    const int32_t c = col[k];
-                    if (c <= prev || c >= n) { bad_t[me] = 1; return; }
-                    prev = c;
-                    const double v = promote(vals, vk, k);
-                    if (!std::isfinite(v)) { bad_t[me] = 1; return; }
-                    s = s + v * v;
-                }
-                out.w[i] = s;
-            }
-            mu_t[me] = mu;
-        });
-    }
-    for (auto &x : th) x.join();
-    for (int t = 0; t < tix; ++t)
-        if (bad_t[t]) return ASYRK_ERR_INVALID_ARG;
-    for (int64_t i = 0; i < m; ++i)
-        if (!(out.w[i] > 0.0)) return ASYRK_ERR_ZERO_ROW;
-
-    out.mu = 0;
-    for (int t = 0; t < tix; ++t) out.mu = std::max(out.mu, mu_t[t]);
-    std::vector<int32_t> cnt(n, 0);
-    std::vector<double> cn2(n, 0.0);
-    for (int64_t k = 0; k < nnz; ++k) {
-        const double v = promote(vals, vk, k);
-        cnt[col[k]]++;
-        cn2[col[k]] += v * v;
-    }
-    out.nu = *std::max_element(cnt.begin(), cnt.end());
-    out.max_col_norm2 = *std::max_element(cn2.begin(), cn2.end());
-    out.fixed_nnz = row_ptr[1] - row_ptr[0];
-    for (int64_t i = 1; i < m && out.fixed_nnz > 0; ++i)
-        if (row_ptr[i + 1] - row_ptr[i] != out.fixed_nnz) out.fixed_nnz = 0;
-    double fro2 = 0.0;
-    for (int64_t i = 0; i < m; ++i) fro2 = fro2 + out.w[i];
-    out.fro2 = fro2;
-    out.nnz = nnz;
-    return ASYRK_OK;
 }
 
 // Vose's alias method for P(i) = w_i / sum(w): p_i = (w_i m) / W with W
@@ -247,58 +286,97 @@ static int64_t choose_stride(int64_t raw) {
     return sec64 <= avg16 - 1e-9 ? pad64 : raw;
 }
 
-asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
-                          int vk, const double *b, SetupResult &res) {
+asyrk_status plan_records(int64_t m, const int64_t *row_ptr, int vk, SetupResult &res, int64_t *total_bytes) {
     const Geom g = geom_of(vk);
-    std::vector<uint32_t> thresh;
-    std::vector<int32_t> alias;
-    build_alias(res.w, thresh, alias);
-
     auto raw_bytes = [&](int64_t nnz) { return (int64_t)g.HB + (nnz + g.U - 1) / g.U * g.UB; };
-    std::vector<int64_t> off;
     int64_t total;
     if (res.fixed_nnz > 0) {
         res.stride = choose_stride(raw_bytes(res.fixed_nnz));
+        res.loc.clear();
         total = res.stride * m;
     } else {
         res.stride = 0;
-        off.resize(m + 1);
-        off[0] = 0;
-        for (int64_t i = 0; i < m; ++i) off[i + 1] = off[i] + raw_bytes(row_ptr[i + 1] - row_ptr[i]);
-        total = off[m];
-        if (total / 16 >= (int64_t)UINT32_MAX) return ASYRK_ERR_INVALID_ARG;
         res.loc.resize(m);
-        for (int64_t i = 0; i < m; ++i)
-            res.loc[i] = RowLoc{(uint32_t)(off[i] / 16), (uint32_t)(row_ptr[i + 1] - row_ptr[i])};
+        int64_t off = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t nnz = row_ptr[i + 1] - row_ptr[i];
+            if (off / 16 >= (int64_t)UINT32_MAX) return ASYRK_ERR_INVALID_ARG;
+            res.loc[i] = RowLoc{(uint32_t)(off / 16), (uint32_t)nnz};
+            off += raw_bytes(nnz);
+        }
+        total = off;
+        if (total / 16 >= (int64_t)UINT32_MAX) return ASYRK_ERR_INVALID_ARG;
     }
+    *total_bytes = total;
+    return ASYRK_OK;
+}
+
+// Rows lo..hi-1 written in full: header, whole units, the last unit padded
+// with (0, 0) entries, and (equal-length rows) zeros up to the stride.
+template <int VK>
+static void write_rows(int64_t lo, int64_t hi, const int64_t *row_ptr, const int32_t *col, const void *vals,
+                       const double *b, const SetupResult &res, const uint32_t *thresh, const int32_t *alias,
+                       uint8_t *dst) {
+    using T = VT<VK>;
+    using val_t = typename T::val_t;
+    const val_t *vv = static_cast<const val_t *>(vals);
+    const bool fixed = res.fixed_nnz > 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint8_t *r = dst + (fixed ? i * res.stride : (int64_t)res.loc[i].off16 * 16);
+        const double inv_w = 1.0 / res.w[i];
+        if constexpr (VK == ASYRK_F64) {
+            const HdrF64 h{b[i], inv_w, thresh[i], alias[i], 0};
+            std::memcpy(r, &h, sizeof h);
+        } else {
+            const HdrF32 h{(float)b[i], (float)inv_w, thresh[i], alias[i]};
+            std::memcpy(r, &h, sizeof h);
+        }
+        const int64_t beg = row_ptr[i], nnz = row_ptr[i + 1] - beg;
+        const int32_t *c = col + beg;
+        const val_t *v = vv + beg;
+        uint8_t *u = r + T::HB;
+        int64_t k = 0;
+        for (; k + T::U <= nnz; k += T::U, u += T::UB) {
+            std::memcpy(u, c + k, 4 * T::U);
+            std::memcpy(u + T::COLB, v + k, T::VB * T::U);
+        }
+        if (k < nnz) {
+            const int64_t rem = nnz - k;
+            std::memset(u, 0, T::UB);
+            std::memcpy(u, c + k, 4 * rem);
+            std::memcpy(u + T::COLB, v + k, T::VB * rem);
+            u += T::UB;
+        }
+        if (fixed) std::memset(u, 0, (size_t)(r + res.stride - u));
+    }
+}
+
+void write_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals, int vk,
+                   const double *b, const SetupResult &res, const uint32_t *thresh, const int32_t *alias,
+                   uint8_t *dst) {
+    parallel_rows(m, [&](int64_t lo, int64_t hi) {
+        switch (vk) {
+            case ASYRK_F64: write_rows<ASYRK_F64>(lo, hi, row_ptr, col, vals, b, res, thresh, alias, dst); break;
+            case ASYRK_F32: write_rows<ASYRK_F32>(lo, hi, row_ptr, col, vals, b, res, thresh, alias, dst); break;
+            default: write_rows<ASYRK_BF16>(lo, hi, row_ptr, col, vals, b, res, thresh, alias, dst); break;
+        }
+    });
+}
+
+asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
+                          int vk, const double *b, SetupResult &res) {
+    std::vector<uint32_t> thresh;
+    std::vector<int32_t> alias;
+    build_alias(res.w, thresh, alias);
+    int64_t total = 0;
+    asyrk_status rc = plan_records(m, row_ptr, vk, res, &total);
+    if (rc) return rc;
     try {
-        res.rec.assign((size_t)total, 0);
+        res.rec.resize((size_t)total);
     } catch (...) {
         return ASYRK_ERR_OOM;
     }
-    uint8_t *base = res.rec.data();
-    const std::vector<double> &w = res.w;
-    parallel_rows(m, [&](int64_t lo, int64_t hi) {
-        for (int64_t i = lo; i < hi; ++i) {
-            uint8_t *r = base + (res.fixed_nnz > 0 ? i * res.stride : off[i]);
-            const double inv_w = 1.0 / w[i];
-            if (vk == ASYRK_F64) {
-                HdrF64 h{b[i], inv_w, thresh[i], alias[i], 0};
-                std::memcpy(r, &h, sizeof h);
-            } else {
-                HdrF32 h{(float)b[i], (float)inv_w, thresh[i], alias[i]};
-                std::memcpy(r, &h, sizeof h);
-            }
-            const int64_t beg = row_ptr[i], nnz = row_ptr[i + 1] - beg;
-            for (int64_t k = 0; k < nnz; ++k) {
-                uint8_t *u = r + g.HB + (k / g.U) * g.UB;
-                const int e = (int)(k % g.U);
-                std::memcpy(u + 4 * e, &col[beg + k], 4);
-                std::memcpy(u + g.COLB + g.VB * e, static_cast<const uint8_t *>(vals) + (beg + k) * g.VB,
-                            g.VB);
-            }
-        }
-    });
+    write_records(m, row_ptr, col, vals, vk, b, res, thresh.data(), alias.data(), res.rec.data());
     return ASYRK_OK;
 }
 

@@ -38,7 +38,16 @@ asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const
                              const void *vals, int vk, const double *b, SetupResult &out);
 void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
                  std::vector<int32_t> &alias);
+// Alias table, layout and records in res.rec.
 asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
                           int vk, const double *b, SetupResult &res);
+// The two halves of pack_records for callers that place the records
+// themselves: plan_records fixes the layout of a validated system (res.stride,
+// or res.loc for rows of different length) and its size in bytes;
+// write_records fills dst (that many bytes) completely, padding included.
+asyrk_status plan_records(int64_t m, const int64_t *row_ptr, int vk, SetupResult &res, int64_t *total_bytes);
+void write_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals, int vk,
+                   const double *b, const SetupResult &res, const uint32_t *thresh, const int32_t *alias,
+                   uint8_t *dst);
 
 }  // namespace asyrk
