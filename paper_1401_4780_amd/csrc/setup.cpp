@@ -27,18 +27,28 @@ static inline double promote(const void *vals, int vk, int64_t k) {
     }
 }
 
+// Host threads for a pass over m rows: one per 8192 rows, at most 16 and at
+// most the hardware's.
+static unsigned threads_for(int64_t m) {
+    const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(hw, m / 8192));
+}
+
+// fn(lo, hi) over `parts` contiguous row ranges, the first on the calling thread.
 template <class F>
-static void parallel_rows(int64_t m, F fn) {
-    unsigned nt = std::thread::hardware_concurrency();
-    nt = std::max(1u, std::min(nt, 16u));
-    if (m < 65536) nt = 1;
+static void parallel_rows(int64_t m, unsigned parts, F fn) {
+    if (parts <= 1) {
+        fn((int64_t)0, m);
+        return;
+    }
     std::vector<std::thread> th;
-    const int64_t chunk = (m + nt - 1) / nt;
-    for (unsigned t = 0; t < nt; ++t) {
+    const int64_t chunk = (m + parts - 1) / parts;
+    for (unsigned t = 1; t < parts; ++t) {
         const int64_t lo = t * chunk, hi = std::min<int64_t>(m, lo + chunk);
         if (lo >= hi) break;
         th.emplace_back([=]() { fn(lo, hi); });
     }
+    fn((int64_t)0, std::min<int64_t>(m, chunk));
     for (auto &x : th) x.join();
 }
 
@@ -57,12 +67,18 @@ static inline double promote_t(const void *vals, int64_t k) {
 }
 
 // Rows lo..hi-1: sorted in-range columns, finite values, w_i (FP64, CSR
-// order).  With cnt/cn2 the column statistics are accumulated in the same pass
+// order).  With cs the column statistics are accumulated in the same pass
 // (entries in increasing k, as the separate pass would).  Returns false on an
 // invalid entry.
+// Per-column entry count and sum of squares, side by side (one cache line per update).
+struct ColStat {
+    double sq;
+    int64_t cnt;
+};
+
 template <int VK>
 static bool scan_rows(int64_t lo, int64_t hi, int64_t n, const int64_t *row_ptr, const int32_t *col,
-                      const void *vals, double *w, int64_t &mu_out, int32_t *cnt, double *cn2) {
+                      const void *vals, double *w, int64_t &mu_out, ColStat *cs) {
     int64_t mu = 0;
     for (int64_t i = lo; i < hi; ++i) {
         const int64_t beg = row_ptr[i], end = row_ptr[i + 1];
@@ -77,9 +93,9 @@ static bool scan_rows(int64_t lo, int64_t hi, int64_t n, const int64_t *row_ptr,
             if (!std::isfinite(v)) return false;
             const double v2 = v * v;
             s = s + v2;
-            if (cnt) {
-                cnt[c]++;
-                cn2[c] += v2;
+            if (cs) {
+                cs[c].cnt++;
+                cs[c].sq += v2;
             }
         }
         w[i] = s;
@@ -93,42 +109,56 @@ static asyrk_status validate_t(int64_t m, int64_t n, const int64_t *row_ptr, con
                                SetupResult &out) {
     const int64_t nnz = row_ptr[m];
     out.w.resize(m);
-    std::vector<int32_t> cnt(n, 0);
-    std::vector<double> cn2(n, 0.0);
-    unsigned nt = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
-    if (m < 65536) nt = 1;
+    std::vector<ColStat> cs(n, ColStat{0.0, 0});
+    const unsigned nt = threads_for(m);
     int64_t mu = 0;
     if (nt == 1) {
-        if (!scan_rows<VK>(0, m, n, row_ptr, col, vals, out.w.data(), mu, cnt.data(), cn2.data()))
+        if (!scan_rows<VK>(0, m, n, row_ptr, col, vals, out.w.data(), mu, cs.data()))
             return ASYRK_ERR_INVALID_ARG;
     } else {
-        std::vector<int> bad(nt, 0);
-        std::vector<int64_t> mu_t(nt, 0);
+        // nt - 1 threads scan row ranges while the calling thread accumulates
+        // the column statistics over every entry in order (the same sums as
+        // the single-threaded pass), checking each index against n itself
+        // since the row scan runs at the same time.
+        const unsigned parts = nt - 1;
+        std::vector<int> bad(parts, 0);
+        std::vector<int64_t> mu_t(parts, 0);
         std::vector<std::thread> th;
-        const int64_t chunk = (m + nt - 1) / nt;
-        for (unsigned t = 0; t < nt; ++t) {
+        const int64_t chunk = (m + parts - 1) / parts;
+        for (unsigned t = 0; t < parts; ++t) {
             const int64_t lo = t * chunk, hi = std::min<int64_t>(m, lo + chunk);
             if (lo >= hi) break;
             th.emplace_back([&, t, lo, hi]() {
-                bad[t] = !scan_rows<VK>(lo, hi, n, row_ptr, col, vals, out.w.data(), mu_t[t], nullptr, nullptr);
+                bad[t] = !scan_rows<VK>(lo, hi, n, row_ptr, col, vals, out.w.data(), mu_t[t], nullptr);
             });
         }
+        bool in_range = true;
+        for (int64_t k = 0; k < nnz; ++k) {
+            const int32_t c = col[k];
+            if (c < 0 || c >= n) {
+                in_range = false;
+                break;
+            }
+            const double v = promote_t<VK>(vals, k);
+            cs[c].cnt++;
+            cs[c].sq += v * v;
+        }
         for (auto &x : th) x.join();
-        for (unsigned t = 0; t < nt; ++t) {
+        for (unsigned t = 0; t < parts; ++t) {
             if (bad[t]) return ASYRK_ERR_INVALID_ARG;
             mu = std::max(mu, mu_t[t]);
         }
-        for (int64_t k = 0; k < nnz; ++k) {
-            const double v = promote_t<VK>(vals, k);
-            cnt[col[k]]++;
-            cn2[col[k]] += v * v;
-        }
+        if (!in_range) return ASYRK_ERR_INVALID_ARG;
     }
     for (int64_t i = 0; i < m; ++i)
         if (!(out.w[i] > 0.0)) return ASYRK_ERR_ZERO_ROW;
     out.mu = mu;
-    out.nu = *std::max_element(cnt.begin(), cnt.end());
-    out.max_col_norm2 = *std::max_element(cn2.begin(), cn2.end());
+    out.nu = 0;
+    out.max_col_norm2 = cs[0].sq;
+    for (const ColStat &c : cs) {
+        out.nu = std::max(out.nu, c.cnt);
+        out.max_col_norm2 = std::max(out.max_col_norm2, c.sq);
+    }
     out.fixed_nnz = row_ptr[1] - row_ptr[0];
     for (int64_t i = 1; i < m && out.fixed_nnz > 0; ++i)
         if (row_ptr[i + 1] - row_ptr[i] != out.fixed_nnz) out.fixed_nnz = 0;
@@ -174,31 +204,31 @@ void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
     double total = 0.0;
     for (int64_t i = 0; i < m; ++i) total = total + w[i];
     std::vector<double> p(m);
-    std::vector<int64_t> small, large;
-    small.reserve(m);
-    large.reserve(m);
+    // Both work lists share one array: the small list grows up from the
+    // front, the large list down from the back (each index is on at most one
+    // list, so they never meet); both are used last-in first-out.
+    std::vector<int32_t> lists(m);
+    int64_t ns = 0, nl = 0;
     for (int64_t i = 0; i < m; ++i) {
         p[i] = (w[i] * (double)m) / total;
         if (p[i] < 1.0)
-            small.push_back(i);
+            lists[ns++] = (int32_t)i;
         else
-            large.push_back(i);
+            lists[m - 1 - nl++] = (int32_t)i;
     }
     thresh.assign(m, 0xffffffffu);
     alias.resize(m);
     for (int64_t i = 0; i < m; ++i) alias[i] = (int32_t)i;
-    while (!small.empty() && !large.empty()) {
-        const int64_t s = small.back();
-        small.pop_back();
-        const int64_t l = large.back();
-        large.pop_back();
-        thresh[s] = (uint32_t)(uint64_t)(p[s] * 4294967296.0);
-        alias[s] = (int32_t)l;
-        p[l] = (p[l] + p[s]) - 1.0;
+    while (ns > 0 && nl > 0) {
+        const int64_t sm = lists[--ns];
+        const int64_t l = lists[m - nl--];
+        thresh[sm] = (uint32_t)(uint64_t)(p[sm] * 4294967296.0);
+        alias[sm] = (int32_t)l;
+        p[l] = (p[l] + p[sm]) - 1.0;
         if (p[l] < 1.0)
-            small.push_back(l);
+            lists[ns++] = (int32_t)l;
         else
-            large.push_back(l);
+            lists[m - 1 - nl++] = (int32_t)l;
     }
     // leftovers keep thresh = 2^32 - 1 and alias = self
 }
@@ -354,7 +384,7 @@ static void write_rows(int64_t lo, int64_t hi, const int64_t *row_ptr, const int
 void write_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals, int vk,
                    const double *b, const SetupResult &res, const uint32_t *thresh, const int32_t *alias,
                    uint8_t *dst) {
-    parallel_rows(m, [&](int64_t lo, int64_t hi) {
+    parallel_rows(m, threads_for(m), [&](int64_t lo, int64_t hi) {
         switch (vk) {
             case ASYRK_F64: write_rows<ASYRK_F64>(lo, hi, row_ptr, col, vals, b, res, thresh, alias, dst); break;
             case ASYRK_F32: write_rows<ASYRK_F32>(lo, hi, row_ptr, col, vals, b, res, thresh, alias, dst); break;
