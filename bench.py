@@ -441,7 +441,10 @@ def run_serving(args):
                 # row updates per second of round time on the GPU, and the share of
                 # wall time the GPU spent in rounds
                 "gpu_rows_per_s": (st1["row_updates"] - st0["row_updates"]) / max(gpu_s, 1e-9),
-                "gpu_busy_frac": gpu_s / (t_end - t0), "rounds": st1["rounds"] - st0["rounds"]}
+                "gpu_busy_frac": gpu_s / (t_end - t0), "rounds": st1["rounds"] - st0["rounds"],
+                "workers_per_round": (st1["round_workers"] - st0["round_workers"]) / max(1, st1["rounds"] - st0["rounds"]),
+                "systems_per_round": (st1["round_systems"] - st0["round_systems"]) / max(1, st1["rounds"] - st0["rounds"]),
+                "pipelined_rounds": st1["pipelined_rounds"] - st0["pipelined_rounds"]}
 
     # saturation: every request present at t = 0
     sat = drive(0, n_req, np.zeros(n_req))

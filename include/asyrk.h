@@ -181,6 +181,10 @@ typedef struct asyrk_system_info {
     double max_col_norm2;      /* max_j ||column j||^2, a lower bound on lambda_max */
     int64_t default_in_flight; /* R used when in_flight = 0: Corollary 1's bound with
                                   lambda = max(lambda_mp, max_col_norm2), in [1, 65536] */
+    int64_t iterate_stride;    /* bytes between consecutive elements of the device-side sweep
+                                  iterate: 256 for n <= 2^20, 64 for n <= 2^23, else 8.
+                                  Columns sharing a cache line make their gathers and atomics
+                                  queue behind each other; the caller's x stays dense */
 } asyrk_system_info;
 
 /* Version of this ABI (ASYRK_ABI_VERSION). */
@@ -366,6 +370,9 @@ typedef struct asyrk_request_stats {
 typedef struct asyrk_server_stats {
     int64_t submitted, admitted, completed, active, queued, rounds, row_updates, arena_used;
     double gpu_seconds;    /* time of the rounds on the GPU (HIP events) */
+    int64_t round_workers;     /* row workers summed over rounds (/ rounds = mean per round) */
+    int64_t round_systems;     /* active systems summed over rounds */
+    int64_t pipelined_rounds;  /* rounds that ran the pipelined worker loop */
 } asyrk_server_stats;
 
 /* Defaults for asyrk_server_config. */

@@ -76,6 +76,7 @@ class SystemInfo(C.Structure):
         ("vals_dtype", C.c_int32), ("iter_dtype", C.c_int32), ("fro2", C.c_double),
         ("lambda_mp", C.c_double), ("record_bytes_per_row", C.c_int64),
         ("max_col_norm2", C.c_double), ("default_in_flight", C.c_int64),
+        ("iterate_stride", C.c_int64),
     ]
 
 
@@ -102,6 +103,7 @@ class ServerStats(C.Structure):
         ("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
         ("active", C.c_int64), ("queued", C.c_int64), ("rounds", C.c_int64),
         ("row_updates", C.c_int64), ("arena_used", C.c_int64), ("gpu_seconds", C.c_double),
+        ("round_workers", C.c_int64), ("round_systems", C.c_int64), ("pipelined_rounds", C.c_int64),
     ]
 
 

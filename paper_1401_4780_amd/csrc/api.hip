@@ -23,7 +23,8 @@ struct asyrk_system {
     uint8_t *d_rec = nullptr;
     RowLoc *d_loc = nullptr;
     double *d_b64 = nullptr;
-    void *d_x = nullptr;          // sweep iterate (float or double; n * 8 bytes)
+    void *d_x = nullptr;          // sweep iterate: element c at byte c * xstride (float or double)
+    int64_t xstride = 8;          // bytes per iterate element (a power of two >= 8)
     double2 *d_side = nullptr;    // {b_i, 1/w_i} in FP64 for FP64 iterates over FP32/BF16 records
     double *d_x64 = nullptr;      // FP64 master iterate
     double *d_xref = nullptr;     // FP64 reference for the error monitor
@@ -133,6 +134,9 @@ int auto_lanes(const asyrk_system *s, int64_t R) {
     return G;
 }
 
+// log2 of the iterate's element stride for an FP32 or FP64 iterate
+int xshift_of(const asyrk_system *s, bool f32) { return stride_shift(s->xstride, f32 ? 4 : 8); }
+
 double lambda_mp(const asyrk_system *s) {
     const double r = std::sqrt((double)s->n / (double)s->m);
     return (1.0 + r) * (1.0 + r) * s->fro2 / (double)s->n;
@@ -157,15 +161,15 @@ struct Monitor {
 };
 
 // Monitored error of an iterate on the device (x of the sweep dtype or FP64).
-asyrk_status monitored_error(asyrk_system *s, const Monitor &mon, const void *x, int x_f32, double *err) {
+asyrk_status monitored_error(asyrk_system *s, const Monitor &mon, const void *x, int x_f32, int xsh, double *err) {
     double v = 0.0;
     if (mon.use_ref) {
-        HIP_OK(launch_sumsq_diff(x, x_f32, s->d_xref, s->n, s->d_part, kResidualBlocks, s->st));
+        HIP_OK(launch_sumsq_diff(x, x_f32, xsh, s->d_xref, s->n, s->d_part, kResidualBlocks, s->st));
         asyrk_status rc = fetch_scalar(s, kResidualBlocks, &v);
         if (rc) return rc;
         *err = mon.ref_norm2 > 0 ? std::sqrt(v / mon.ref_norm2) : std::sqrt(v);
     } else {
-        HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, x, x_f32, nullptr, 0, s->d_part, kResidualBlocks, s->st));
+        HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, x, x_f32, xsh, nullptr, 0, s->d_part, kResidualBlocks, s->st));
         asyrk_status rc = fetch_scalar(s, kResidualBlocks, &v);
         if (rc) return rc;
         *err = mon.b_norm2 > 0 ? std::sqrt(v / mon.b_norm2) : std::sqrt(v);
@@ -290,7 +294,8 @@ static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, c
     TRY(dmalloc(s, &s->d_rec, res.rec.size()));
     if (res.fixed_nnz == 0) TRY(dmalloc(s, &s->d_loc, res.loc.size() * sizeof(RowLoc)));
     TRY(dmalloc(s, &s->d_b64, (size_t)m * sizeof(double)));
-    TRY(dmalloc(s, &s->d_x, (size_t)n * 8));
+    s->xstride = iterate_stride(n);
+    TRY(dmalloc(s, &s->d_x, (size_t)n * (size_t)s->xstride));
     TRY(dmalloc(s, &s->d_x64, (size_t)n * sizeof(double)));
     TRY(dmalloc(s, &s->d_xref, (size_t)n * sizeof(double)));
     TRY(dmalloc(s, &s->d_part, (size_t)kResidualBlocks * sizeof(double)));
@@ -382,6 +387,7 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
         (int64_t)std::llround((double)s->nnz / (double)s->m * (4 + g.VB)) + 2 * sc + 4;
     info->max_col_norm2 = s->max_col_norm2;
     info->default_in_flight = auto_in_flight(s);
+    info->iterate_stride = s->xstride;
     return ASYRK_OK;
 }
 
@@ -412,7 +418,7 @@ asyrk_status asyrk_residual(asyrk_system *s, const double *x, double *r_out, dou
         else
             HIP_OK(hipMalloc((void **)&r_dev, (size_t)s->m * sizeof(double)));
     }
-    hipError_t e = launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, r_dev, 0, s->d_part,
+    hipError_t e = launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, 0, r_dev, 0, s->d_part,
                                    kResidualBlocks, s->st);
     double v = 0.0;
     asyrk_status rc = e == hipSuccess ? fetch_scalar(s, kResidualBlocks, &v) : dev_fail(e);
@@ -458,22 +464,22 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
     asyrk_status rc = ASYRK_OK;
     if (e == hipSuccess) e = launch_random_fill(v, s->n, (uint32_t)seed, (uint32_t)(seed >> 32), s->st);
     // v <- v / ||v||
-    if (e == hipSuccess) e = launch_sumsq_diff(v, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
+    if (e == hipSuccess) e = launch_sumsq_diff(v, 0, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
     if (e == hipSuccess) e = launch_finish_sum(s->d_part, kResidualBlocks, s->d_scalar, s->st);
     if (e == hipSuccess) e = launch_scale(v, s->n, s->d_scalar, s->st);
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
         // y = -A v (residual with b = 0), z = A^T y, v = z / ||z||
-        e = launch_residual(s->vk, s->rows, nullptr, v, 0, y, 0, s->d_part, kResidualBlocks, s->st);
+        e = launch_residual(s->vk, s->rows, nullptr, v, 0, 0, y, 0, s->d_part, kResidualBlocks, s->st);
         if (e == hipSuccess) e = launch_zero(z, s->n * 8, s->st);
         if (e == hipSuccess) e = launch_scatter_rows(s->vk, s->rows, y, z, s->st);
-        if (e == hipSuccess) e = launch_sumsq_diff(z, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
+        if (e == hipSuccess) e = launch_sumsq_diff(z, 0, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st);
         if (e == hipSuccess) e = launch_finish_sum(s->d_part, kResidualBlocks, s->d_scalar, s->st);
         if (e == hipSuccess) e = launch_scale(z, s->n, s->d_scalar, s->st);
         if (e == hipSuccess) std::swap(v, z);
     }
     // Rayleigh quotient ||A v||^2 with ||v|| = 1
     if (e == hipSuccess)
-        e = launch_residual(s->vk, s->rows, nullptr, v, 0, nullptr, 0, s->d_part, kResidualBlocks, s->st);
+        e = launch_residual(s->vk, s->rows, nullptr, v, 0, 0, nullptr, 0, s->d_part, kResidualBlocks, s->st);
     if (e == hipSuccess) {
         rc = fetch_scalar(s, kResidualBlocks, &nrm2);
         lam = nrm2;
@@ -516,7 +522,7 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
         p.pipeline = pipe;
         for (int k = 0; k < 7; ++k) {
             const int G = cands[k];
-            HIP_OK(launch_zero(s->d_x, s->n * 8, s->st));
+            HIP_OK(launch_zero(s->d_x, s->n * s->xstride, s->st));
             double gpu_s = 0.0, a = 0, b = 0, c = 0;
             asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &a, &b, &c);
             if (rc) return rc;
@@ -567,6 +573,7 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     SweepArgs a{};
     a.rows = s->rows;
     a.x = s->d_x;
+    a.xshift = xshift_of(s, xk == ASYRK_F32);
     a.side = s->d_side;
     a.t_begin = t_begin;
     a.t_end = t_end;
@@ -649,6 +656,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
     }
     const bool f32 = xk == ASYRK_F32;
+    const int xsh = xshift_of(s, f32);
     const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2h = s->mem == ASYRK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 
@@ -666,11 +674,11 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.x_ref) {
         mon.use_ref = true;
         HIP_OK(hipMemcpyAsync(s->d_xref, p.x_ref, (size_t)s->n * 8, h2d, s->st));
-        HIP_OK(launch_sumsq_diff(s->d_xref, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st));
+        HIP_OK(launch_sumsq_diff(s->d_xref, 0, 0, nullptr, s->n, s->d_part, kResidualBlocks, s->st));
         asyrk_status rc = fetch_scalar(s, kResidualBlocks, &mon.ref_norm2);
         if (rc) return rc;
     } else {
-        HIP_OK(launch_sumsq_diff(s->d_b64, 0, nullptr, s->m, s->d_part, kResidualBlocks, s->st));
+        HIP_OK(launch_sumsq_diff(s->d_b64, 0, 0, nullptr, s->m, s->d_part, kResidualBlocks, s->st));
         asyrk_status rc = fetch_scalar(s, kResidualBlocks, &mon.b_norm2);
         if (rc) return rc;
     }
@@ -704,9 +712,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     int64_t done = 0;
 
     if (!p.refine) {
-        HIP_OK(launch_cast_to_iter(s->d_x64, s->d_x, f32, s->n, s->st));
+        HIP_OK(launch_cast_to_iter(s->d_x64, s->d_x, f32, xsh, s->n, s->st));
         if (monitor) {
-            asyrk_status rc = monitored_error(s, mon, s->d_x, f32, &err0);
+            asyrk_status rc = monitored_error(s, mon, s->d_x, f32, xsh, &err0);
             if (rc) return rc;
             push_hist(err0);
             S.final_err = err0;
@@ -721,7 +729,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
             done += c;
             if (monitor || done == sweeps) {
                 double e = 0.0;
-                rc = monitored_error(s, mon, s->d_x, f32, &e);
+                rc = monitored_error(s, mon, s->d_x, f32, xsh, &e);
                 if (rc) return rc;
                 S.final_err = e;
                 push_hist(e);
@@ -737,7 +745,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
             }
         }
         // x is returned untouched when no sweep ran (no FP32 round trip)
-        if (done > 0) HIP_OK(launch_iter_to_f64(s->d_x, f32, s->d_x64, s->n, 0, s->st));
+        if (done > 0) HIP_OK(launch_iter_to_f64(s->d_x, f32, xsh, s->d_x64, s->n, 0, s->st));
         if (result == ASYRK_OK && p.tol > 0.0 && !(S.final_err <= p.tol)) result = ASYRK_ERR_NOT_CONVERGED;
     } else {
         // FP64 iterative refinement: x64 master, FP32 correction d on A d = fp32(b - A x64).
@@ -746,17 +754,17 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         // ||r32|| is <= 1e-6 or stops improving (the FP32 floor), at most 40.
         const bool adaptive = p.inner_sweeps == 0;
         const int64_t inner = adaptive ? 40 : p.inner_sweeps;
-        asyrk_status rc = monitored_error(s, mon, s->d_x64, 0, &err0);
+        asyrk_status rc = monitored_error(s, mon, s->d_x64, 0, 0, &err0);
         if (rc) return rc;
         push_hist(err0);
         S.final_err = err0;
         bool ok = p.tol > 0.0 && err0 <= p.tol;
         while (!ok && done < sweeps) {
             // r = b - A x64 into the records' b fields (FP32), d = 0
-            HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, nullptr, 1, s->d_part, kResidualBlocks,
+            HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, 0, nullptr, 1, s->d_part, kResidualBlocks,
                                    s->st));
             s->rec_b_dirty = true;
-            HIP_OK(launch_zero(s->d_x, (int64_t)s->n * 4, s->st));
+            HIP_OK(launch_zero(s->d_x, s->n * s->xstride, s->st));
             const int64_t budget = std::min<int64_t>(inner, sweeps - done);
             if (!adaptive) {
                 rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + budget * s->m, &gpu_s, &wmax, &wsum,
@@ -766,7 +774,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                 done += budget;
             } else {
                 double r0 = 0.0, prev = 1.0;
-                HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, nullptr, 0, s->d_part, kResidualBlocks,
+                HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, xsh, nullptr, 0, s->d_part, kResidualBlocks,
                                        s->st, 1));
                 rc = fetch_scalar(s, kResidualBlocks, &r0);
                 if (rc) return rc;
@@ -776,7 +784,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                     ticket += s->m;
                     done += 1;
                     double rk = 0.0;
-                    HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, nullptr, 0, s->d_part,
+                    HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, xsh, nullptr, 0, s->d_part,
                                            kResidualBlocks, s->st, 1));
                     rc = fetch_scalar(s, kResidualBlocks, &rk);
                     if (rc) return rc;
@@ -785,10 +793,10 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                     prev = rel;
                 }
             }
-            HIP_OK(launch_iter_to_f64(s->d_x, 1, s->d_x64, s->n, 1, s->st));
+            HIP_OK(launch_iter_to_f64(s->d_x, 1, xsh, s->d_x64, s->n, 1, s->st));
             S.outer_iters++;
             double e = 0.0;
-            rc = monitored_error(s, mon, s->d_x64, 0, &e);
+            rc = monitored_error(s, mon, s->d_x64, 0, 0, &e);
             if (rc) return rc;
             S.final_err = e;
             push_hist(e);

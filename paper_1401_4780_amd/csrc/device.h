@@ -62,6 +62,14 @@ __device__ __forceinline__ void atomic_add(T *p, T v) {
     (void)__hip_atomic_fetch_add((ASYRK_GLOBAL T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Element c of an iterate stored with a stride of 2^sh elements: columns that
+// would share a cache line get lines of their own, so their gathers and
+// atomics do not queue behind each other.
+template <class T>
+__device__ __forceinline__ T *xat(T *x, int32_t c, int sh) {
+    return x + ((int64_t)c << sh);
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits) { return __uint_as_float(bits << 16); }
 
 __device__ __forceinline__ void locate(const Rows &r, uint32_t i, const uint8_t *&rec, int &nnz) {
@@ -170,7 +178,7 @@ template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; }
 // `alias_ok` = false keeps row i whatever its header says.
 template <int VK, int XK, int G, int UPL = Upl<G>::value, bool SAMPLED = true>
 __device__ __forceinline__ uint64_t process_ticket(
-    const Rows &rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
+    const Rows &rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
     const double2 *side, int64_t j, uint32_t stream_id, uint32_t k0, uint32_t k1, int uniform,
     int update_one, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl,
     int trace, uint32_t given_row = 0) {
@@ -224,7 +232,7 @@ __device__ __forceinline__ uint64_t process_ticket(
             if (uu < nunits) {
 #pragma unroll
                 for (int e = 0; e < U; ++e) {
-                    if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                    if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(xat(x, un[q].c[e], xsh)), acc);
                 }
             }
         }
@@ -243,7 +251,7 @@ __device__ __forceinline__ uint64_t process_ticket(
                 if (uu < nunits) {
 #pragma unroll
                     for (int e = 0; e < U; ++e)
-                        if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(x + un[q].c[e]), acc);
+                        if (uu * U + e < nnz) acc = fma((X)un[q].v[e], load_agent(xat(x, un[q].c[e], xsh)), acc);
                 }
             }
         }
@@ -272,7 +280,7 @@ __device__ __forceinline__ uint64_t process_ticket(
                 if (uu < nunits) {
 #pragma unroll
                     for (int e = 0; e < U; ++e)
-                        if (uu * U + e < nnz) atomic_add(x + un[q].c[e], -s * (X)un[q].v[e]);
+                        if (uu * U + e < nnz) atomic_add(xat(x, un[q].c[e], xsh), -s * (X)un[q].v[e]);
                 }
             }
         } else {
@@ -284,7 +292,7 @@ __device__ __forceinline__ uint64_t process_ticket(
                         un[q].load(rec + T::HB + (int64_t)uu * T::UB);
 #pragma unroll
                         for (int e = 0; e < U; ++e)
-                            if (uu * U + e < nnz) atomic_add(x + un[q].c[e], -s * (X)un[q].v[e]);
+                            if (uu * U + e < nnz) atomic_add(xat(x, un[q].c[e], xsh), -s * (X)un[q].v[e]);
                     }
                 }
             }
@@ -296,7 +304,7 @@ __device__ __forceinline__ uint64_t process_ticket(
         typename VT<VK>::x_t v;
         load_entry<VK>(rec, t, c, v);
         const X s1 = gamma * (X)nnz * r * inv_w;
-        atomic_add(x + c, -s1 * (X)v);
+        atomic_add(xat(x, c, xsh), -s1 * (X)v);
     }
     return trace ? wall_clock64() - t0 : 0;
 }
@@ -324,7 +332,7 @@ __device__ __forceinline__ uint64_t process_ticket(
 // equals the sequential oracle to 1e-12).
 template <int VK, int XK, int G, int UPL = Upl<G>::value>
 __device__ __forceinline__ void run_tickets_pipelined(
-    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x,
+    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
     const double2 *side, int64_t j, int64_t j_end, int64_t step, uint32_t stream_id, uint32_t k0,
     uint32_t k1, int uniform, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma,
     int gl) {
@@ -353,7 +361,7 @@ __device__ __forceinline__ void run_tickets_pipelined(
 #pragma unroll
             for (int e = 0; e < U; ++e) {
                 const bool ok = (base + gl + q * G) * U + e < nnz;
-                xv[q][e] = load_agent(x + (ok ? cu[q].c[e] : 0));
+                xv[q][e] = load_agent(xat(x, ok ? cu[q].c[e] : 0, xsh));
             }
     };
     // ... and consumed
@@ -372,7 +380,7 @@ __device__ __forceinline__ void run_tickets_pipelined(
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
             for (int e = 0; e < U; ++e)
-                if ((base + gl + q * G) * U + e < nnz) atomic_add(x + cu[q].c[e], -s * (X)cu[q].v[e]);
+                if ((base + gl + q * G) * U + e < nnz) atomic_add(xat(x, cu[q].c[e], xsh), -s * (X)cu[q].v[e]);
     };
     // a row's locator is loaded in one ticket and used in the next, so the
     // loaded word is carried raw (a value used at once would be waited for at once)

@@ -19,10 +19,29 @@ struct Rows {
     int32_t m;
 };
 
+// Bytes per element of a sweep iterate over n columns.  Gathers and atomics
+// on columns that share a cache line queue behind each other in the memory
+// system, so the iterate is spread out when that costs little memory: a line
+// of its own per column up to 2^20 columns (256 MB), 64 bytes up to 2^23,
+// dense beyond.
+inline int64_t iterate_stride(int64_t n) {
+    if (n <= ((int64_t)1 << 20)) return 256;
+    if (n <= ((int64_t)1 << 23)) return 64;
+    return 8;
+}
+
+// log2(stride_bytes / elem_bytes) for power-of-two sizes
+inline int stride_shift(int64_t stride_bytes, int elem_bytes) {
+    int sh = 0;
+    while (((int64_t)elem_bytes << sh) < stride_bytes) ++sh;
+    return sh;
+}
+
 // Arguments of the sweep kernel.
 struct SweepArgs {
     Rows rows;
-    void *x;               // iterate: float[n] or double[n]
+    void *x;               // iterate: element c at x[c << xshift] (float or double)
+    int32_t xshift;        // log2 of the iterate's element stride
     const double2 *side;   // FP64 iterate over FP32/BF16 records: {b_i, 1/w_i} per row
     int64_t t_begin;       // first ticket
     int64_t t_end;         // one past the last ticket
@@ -84,14 +103,15 @@ __device__ __forceinline__ U4 draw(int64_t j, uint32_t stream_id, uint32_t k0, u
 hipError_t launch_sweep(int vk, int xk, int G, const SweepArgs &a, hipStream_t st);
 hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStream_t st);
 hipError_t launch_build_side(int vk, const Rows &rows, const double *b64, double2 *side, hipStream_t st);
-hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
+// xsh: log2 of the element stride of x (0 = dense; the sweep iterate has its own)
+hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32, int xsh,
                            double *r_out, int write_rec_b, double *partials, int nblocks,
                            hipStream_t st, int rhs_from_rec = 0);
-hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int64_t n,
+hipError_t launch_sumsq_diff(const void *x, int x_is_f32, int xsh, const double *xr, int64_t n,
                              double *partials, int nblocks, hipStream_t st);
 hipError_t launch_finish_sum(const double *partials, int nparts, double *out, hipStream_t st);
-hipError_t launch_cast_to_iter(const double *x64, void *xit, int xit_is_f32, int64_t n, hipStream_t st);
-hipError_t launch_iter_to_f64(const void *xit, int xit_is_f32, double *x64, int64_t n, int accumulate,
+hipError_t launch_cast_to_iter(const double *x64, void *xit, int xit_is_f32, int xsh, int64_t n, hipStream_t st);
+hipError_t launch_iter_to_f64(const void *xit, int xit_is_f32, int xsh, double *x64, int64_t n, int accumulate,
                               hipStream_t st);
 hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_set_rec_b(int vk, const Rows &rows, const double *b64, hipStream_t st);

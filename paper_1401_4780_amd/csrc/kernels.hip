@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     const X gamma = (X)a.gamma;
     uint64_t tr_max = 0, tr_sum = 0, tr_cnt = 0;
     for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R) {
-        const uint64_t w = process_ticket<VK, XK, G>(a.rows, x, a.side, j, a.stream_id, a.key0, a.key1,
+        const uint64_t w = process_ticket<VK, XK, G>(a.rows, x, a.xshift, a.side, j, a.stream_id, a.key0, a.key1,
                                                      a.uniform, a.update_one, gamma, gl,
                                                      a.trace != nullptr);
         if (a.trace) {
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t worker = wave * (64 / G) + (lane / G);
     if (worker >= a.R) return;
-    run_tickets_pipelined<VK, XK, G>(a.rows, reinterpret_cast<X *>(a.x), a.side, a.t_begin + worker, a.t_end,
+    run_tickets_pipelined<VK, XK, G>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, a.t_begin + worker, a.t_end,
                                      a.R, a.stream_id, a.key0, a.key1, a.uniform, (X)a.gamma, gl);
 }
 
@@ -85,8 +85,8 @@ __global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
                                    (uint32_t)worker, 0x5C4E3D2Bu, a.key0, a.key1);
         for (int64_t k = 0; k < Lw; ++k) {
             const uint32_t i = (uint32_t)(start + slice_perm((uint32_t)k, (uint32_t)Lw, u));
-            process_ticket<VK, XK, G, Upl<G>::value, false>(a.rows, x, a.side, 0, 0u, 0u, 0u, 1, 0, gamma, gl, 0,
-                                                             i);
+            process_ticket<VK, XK, G, Upl<G>::value, false>(a.rows, x, a.xshift, a.side, 0, 0u, 0u, 0u, 1, 0, gamma,
+                                                             gl, 0, i);
             if (a.replay) __threadfence();
         }
     }
@@ -243,25 +243,25 @@ hipError_t launch_finish_sum(const double *partials, int nparts, double *out, hi
 }
 
 template <class XI>
-__global__ __launch_bounds__(256) void sumsq_diff_kernel(const XI *x, const double *xr, int64_t n,
+__global__ __launch_bounds__(256) void sumsq_diff_kernel(const XI *x, int xsh, const double *xr, int64_t n,
                                                           double *partials) {
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) {
-        const double d = (double)x[c] - (xr ? xr[c] : 0.0);
+        const double d = (double)x[c << xsh] - (xr ? xr[c] : 0.0);
         s += d * d;
     }
     block_sum_store(s, partials);
 }
 
-hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int64_t n,
+hipError_t launch_sumsq_diff(const void *x, int x_is_f32, int xsh, const double *xr, int64_t n,
                              double *partials, int nblocks, hipStream_t st) {
     if (x_is_f32)
         hipLaunchKernelGGL(sumsq_diff_kernel<float>, dim3(nblocks), dim3(256), 0, st,
-                           (const float *)x, xr, n, partials);
+                           (const float *)x, xsh, xr, n, partials);
     else
         hipLaunchKernelGGL(sumsq_diff_kernel<double>, dim3(nblocks), dim3(256), 0, st,
-                           (const double *)x, xr, n, partials);
+                           (const double *)x, xsh, xr, n, partials);
     return hipGetLastError();
 }
 
@@ -271,7 +271,7 @@ hipError_t launch_sumsq_diff(const void *x, int x_is_f32, const double *xr, int6
 // i.e. the right-hand side the sweeps currently solve for).
 // One group of 4 lanes per row, rows in order (coalesced record stream).
 template <int VK, class XI>
-__global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const double *b64, const XI *x,
+__global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const double *b64, const XI *x, int xsh,
                                                         double *r_out, int write_rec_b, double *partials,
                                                         int rhs_from_rec) {
     using T = VT<VK>;
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const do
             un.load(rec + T::HB + (int64_t)uu * T::UB);
 #pragma unroll
             for (int e = 0; e < T::U; ++e)
-                if (uu * T::U + e < nnz) acc = fma((double)un.v[e], (double)x[un.c[e]], acc);
+                if (uu * T::U + e < nnz) acc = fma((double)un.v[e], (double)x[(int64_t)un.c[e] << xsh], acc);
         }
         acc = group_sum<G>(acc);
         double bi = b64 ? b64[i] : 0.0;
@@ -310,25 +310,25 @@ __global__ __launch_bounds__(256) void residual_kernel(const Rows rows, const do
 }
 
 template <int VK>
-static hipError_t launch_residual_vk(const Rows &rows, const double *b64, const void *x, int x_is_f32,
+static hipError_t launch_residual_vk(const Rows &rows, const double *b64, const void *x, int x_is_f32, int xsh,
                                      double *r_out, int write_rec_b, double *partials, int nblocks,
                                      int rhs_from_rec, hipStream_t st) {
     if (x_is_f32)
         hipLaunchKernelGGL((residual_kernel<VK, float>), dim3(nblocks), dim3(256), 0, st, rows, b64,
-                           (const float *)x, r_out, write_rec_b, partials, rhs_from_rec);
+                           (const float *)x, xsh, r_out, write_rec_b, partials, rhs_from_rec);
     else
         hipLaunchKernelGGL((residual_kernel<VK, double>), dim3(nblocks), dim3(256), 0, st, rows, b64,
-                           (const double *)x, r_out, write_rec_b, partials, rhs_from_rec);
+                           (const double *)x, xsh, r_out, write_rec_b, partials, rhs_from_rec);
     return hipGetLastError();
 }
 
-hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32,
+hipError_t launch_residual(int vk, const Rows &rows, const double *b64, const void *x, int x_is_f32, int xsh,
                            double *r_out, int write_rec_b, double *partials, int nblocks,
                            hipStream_t st, int rhs_from_rec) {
     switch (vk) {
-        case ASYRK_F32: return launch_residual_vk<ASYRK_F32>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
-        case ASYRK_BF16: return launch_residual_vk<ASYRK_BF16>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
-        case ASYRK_F64: return launch_residual_vk<ASYRK_F64>(rows, b64, x, x_is_f32, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
+        case ASYRK_F32: return launch_residual_vk<ASYRK_F32>(rows, b64, x, x_is_f32, xsh, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
+        case ASYRK_BF16: return launch_residual_vk<ASYRK_BF16>(rows, b64, x, x_is_f32, xsh, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
+        case ASYRK_F64: return launch_residual_vk<ASYRK_F64>(rows, b64, x, x_is_f32, xsh, r_out, write_rec_b, partials, nblocks, rhs_from_rec, st);
     }
     return hipErrorInvalidValue;
 }
@@ -361,16 +361,16 @@ hipError_t launch_set_rec_b(int vk, const Rows &rows, const double *b64, hipStre
 // ---------------------------------------------------------------- vectors
 
 template <class XO>
-__global__ __launch_bounds__(256) void cast_to_iter_kernel(const double *x64, XO *xo, int64_t n) {
+__global__ __launch_bounds__(256) void cast_to_iter_kernel(const double *x64, XO *xo, int xsh, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) xo[c] = (XO)x64[c];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) xo[c << xsh] = (XO)x64[c];
 }
 
 template <class XI>
-__global__ __launch_bounds__(256) void iter_to_f64_kernel(const XI *xi, double *x64, int64_t n, int acc) {
+__global__ __launch_bounds__(256) void iter_to_f64_kernel(const XI *xi, int xsh, double *x64, int64_t n, int acc) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride)
-        x64[c] = acc ? x64[c] + (double)xi[c] : (double)xi[c];
+        x64[c] = acc ? x64[c] + (double)xi[c << xsh] : (double)xi[c << xsh];
 }
 
 static int vec_grid(int64_t n) {
@@ -378,20 +378,20 @@ static int vec_grid(int64_t n) {
     return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
 }
 
-hipError_t launch_cast_to_iter(const double *x64, void *xit, int xit_is_f32, int64_t n, hipStream_t st) {
+hipError_t launch_cast_to_iter(const double *x64, void *xit, int xit_is_f32, int xsh, int64_t n, hipStream_t st) {
     if (xit_is_f32)
-        hipLaunchKernelGGL(cast_to_iter_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (float *)xit, n);
+        hipLaunchKernelGGL(cast_to_iter_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (float *)xit, xsh, n);
     else
-        hipLaunchKernelGGL(cast_to_iter_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (double *)xit, n);
+        hipLaunchKernelGGL(cast_to_iter_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, x64, (double *)xit, xsh, n);
     return hipGetLastError();
 }
 
-hipError_t launch_iter_to_f64(const void *xit, int xit_is_f32, double *x64, int64_t n, int accumulate,
+hipError_t launch_iter_to_f64(const void *xit, int xit_is_f32, int xsh, double *x64, int64_t n, int accumulate,
                               hipStream_t st) {
     if (xit_is_f32)
-        hipLaunchKernelGGL(iter_to_f64_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, (const float *)xit, x64, n, accumulate);
+        hipLaunchKernelGGL(iter_to_f64_kernel<float>, dim3(vec_grid(n)), dim3(256), 0, st, (const float *)xit, xsh, x64, n, accumulate);
     else
-        hipLaunchKernelGGL(iter_to_f64_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, (const double *)xit, x64, n, accumulate);
+        hipLaunchKernelGGL(iter_to_f64_kernel<double>, dim3(vec_grid(n)), dim3(256), 0, st, (const double *)xit, xsh, x64, n, accumulate);
     return hipGetLastError();
 }
 

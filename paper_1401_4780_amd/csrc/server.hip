@@ -51,7 +51,7 @@ struct SlotDesc {
     Rows rows;
     double *b64;
     double *x64;
-    double *d;        // correction, FP64 (FP64 atomics are the faster ones)
+    double *d;        // correction, FP64 (FP64 atomics are the faster ones), element c at d[c << xshift]
     double2 *side;    // per row {r_i, 1/||a_i||^2}: the correction system's right-hand side
     int64_t n;
     int64_t R;        // row workers of this system
@@ -61,6 +61,8 @@ struct SlotDesc {
     int64_t t_begin, t_end;
     uint32_t key0, key1;
     double gamma;
+    int32_t xshift;   // log2 of the correction's element stride
+    int32_t pad;
 };
 
 struct TableHead {
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, cons
     if (tid < nact) norm2[tid] = 0.0;
     for (int64_t q = tid; q < total; q += stride) {
         const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
-        sl[s].d[q - sl[s].col_off] = 0.0;
+        sl[s].d[(q - sl[s].col_off) << sl[s].xshift] = 0.0;
     }
 }
 
@@ -110,11 +112,11 @@ __device__ __forceinline__ void srv_sweep_body(const TableHead *th, const SlotDe
     const SlotDesc d = sl[s];  // a copy: the scatter cannot be taken to alias it
     const int64_t w = worker - d.w_off;
     if constexpr (PIPE) {
-        run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.side, d.t_begin + w, d.t_end, d.R,
+        run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.xshift, d.side, d.t_begin + w, d.t_end, d.R,
                                                                0u, d.key0, d.key1, 0, d.gamma, gl);
     } else {
         for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
-            process_ticket<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.side, j, 0u, d.key0, d.key1, 0, 0,
+            process_ticket<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.xshift, d.side, j, 0u, d.key0, d.key1, 0, 0,
                                                              d.gamma, gl, 0);
     }
 }
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, cons
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
         const int s = find_slot(nact, q, [&](int k) { return sl[k].col_off; });
         const int64_t c = q - sl[s].col_off;
-        sl[s].x64[c] += sl[s].d[c];
+        sl[s].x64[c] += sl[s].d[c << sl[s].xshift];
     }
 }
 
@@ -253,6 +255,7 @@ struct Request {
     int64_t off_rec = -1, off_loc = -1, off_b = -1, off_side = -1, off_x = -1, off_d = -1;
     int64_t bytes = 0;
     int64_t rec_bytes = 0;    // packed record bytes
+    int64_t dstride = 8;      // bytes per element of the correction d
     int64_t pin_off = -1;     // staging block rec | loc | b64 | side in the pinned arena, or -1
     int64_t pin_bytes = 0;
     int64_t ticket = 0;
@@ -294,9 +297,10 @@ struct asyrk_server {
     int64_t next_id = 1;
 
     std::vector<std::unique_ptr<Request>> active;  // progress() thread only
-    std::vector<std::unique_ptr<Request>> staged;  // uploading during the current round; join the next
-    std::atomic<int64_t> n_active{0};              // active + staged, for other threads
-    int64_t workers_in_use = 0;
+    std::vector<std::unique_ptr<Request>> staged;  // uploading during the current round
+    std::deque<std::unique_ptr<Request>> ready;    // uploaded, waiting for room in a round
+    std::atomic<int64_t> n_active{0};              // active + staged + ready, for other threads
+    int64_t workers_in_use = 0;                    // R over active, staged and ready requests
     asyrk_server_stats stats{};
 };
 
@@ -318,7 +322,7 @@ asyrk_status srv_fail(hipError_t e) {
 int64_t request_bytes(const Request &r) {
     return Arena::round_up(r.rec_bytes) + Arena::round_up((int64_t)r.pack.loc.size() * 8) +
            Arena::round_up(r.m * 8) + Arena::round_up(r.m * 16) + Arena::round_up(r.n * 8) +
-           Arena::round_up(r.n * 8) + 6 * 256;
+           Arena::round_up(r.n * r.dstride) + 6 * 256;
 }
 
 hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
@@ -480,6 +484,7 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     r->fro2 = r->pack.fro2;
     const double q = std::sqrt((double)n / (double)m);
     r->lam = std::max((1.0 + q) * (1.0 + q) * r->fro2 / (double)n, r->pack.max_col_norm2);
+    r->dstride = iterate_stride(n);
     r->bytes = request_bytes(*r);
     if (r->bytes > s->cfg.budget_bytes) return ASYRK_ERR_OOM;
     // The records, locators, b and the first round's side records
@@ -536,8 +541,9 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
     if (!s) return ASYRK_ERR_INVALID_ARG;
     const asyrk_server_config &cfg = s->cfg;
-    // ---- join the requests staged by the previous call: their uploads ran on
-    // the copy stream while that call's round computed
+    // ---- the requests staged by the previous call uploaded on the copy
+    // stream while that call's round computed; they wait in `ready` and join
+    // the rounds, oldest first, while the active workers fit max_workers
     if (!s->staged.empty()) {
         SRV_OK(hipEventSynchronize(s->ev_copy));
         std::lock_guard<std::mutex> lk(s->mu);
@@ -546,26 +552,38 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
                 s->pinned.release(r->pin_off, r->pin_bytes);
                 r->pin_off = -1;
             }
-            s->active.push_back(std::move(r));
+            s->ready.push_back(std::move(r));
         }
         s->staged.clear();
     }
-    // ---- admit.  While the active systems keep the GPU busy (more workers
-    // than a pipelined round takes), new requests upload during this round
-    // and join the next; otherwise this round waits for their upload.
     int64_t active_workers = 0;
     for (const auto &r : s->active) active_workers += r->R;
+    while (!s->ready.empty() && active_workers + s->ready.front()->R <= cfg.max_workers) {
+        active_workers += s->ready.front()->R;
+        s->active.push_back(std::move(s->ready.front()));
+        s->ready.pop_front();
+    }
+    // ---- admit.  While the active systems keep the GPU busy (more workers
+    // than a pipelined round takes), new requests upload during this round
+    // and join a later one; requests may then take up to half of max_workers
+    // beyond it, so that uploads run ahead of the rounds instead of holding
+    // back workers of the running set.  Otherwise this round waits for their
+    // upload.
     const bool defer = active_workers > cfg.pipe_workers && active_workers > 0;
+    const int64_t admit_limit = cfg.max_workers + (defer ? cfg.max_workers / 2 : 0);
     bool admitted = false;
     for (;;) {
         std::unique_ptr<Request> r;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->queue.empty() || (int)(s->active.size() + s->staged.size()) >= cfg.max_slots) break;
+            if (s->queue.empty() ||
+                (int64_t)(s->active.size() + s->staged.size() + s->ready.size()) >= cfg.max_slots)
+                break;
             Request &f = *s->queue.front();
             int64_t R = (int64_t)std::floor(f.fro2 / (2.0 * M_E * f.lam));
             R = std::max<int64_t>(1, std::min<int64_t>(R, cfg.max_workers / 4));
-            if (s->workers_in_use + R > cfg.max_workers) break;
+            if (s->workers_in_use + R > admit_limit) break;
+            if (!defer && active_workers + R > cfg.max_workers) break;
             f.R = R;
             const int64_t off = s->arena.alloc(f.bytes);
             if (off < 0) break;  // wait for memory
@@ -602,6 +620,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         q.t_admit = now_s();
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
         s->workers_in_use += q.R;
+        if (!defer) active_workers += q.R;
         (defer ? s->staged : s->active).push_back(std::move(r));
         {
             std::lock_guard<std::mutex> lk(s->mu);  // stats are read by other threads
@@ -613,9 +632,9 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         SRV_OK(hipEventRecord(s->ev_copy, s->cst));
         if (!defer) SRV_OK(hipStreamWaitEvent(s->st, s->ev_copy, 0));
     }
-    s->n_active.store((int64_t)(s->active.size() + s->staged.size()));
+    s->n_active.store((int64_t)(s->active.size() + s->staged.size() + s->ready.size()));
     if (s->active.empty()) {
-        if (n_active) *n_active = 0;
+        if (n_active) *n_active = (int32_t)(s->staged.size() + s->ready.size());
         if (n_queued) {
             std::lock_guard<std::mutex> lk(s->mu);
             *n_queued = (int32_t)s->queue.size();
@@ -649,9 +668,16 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         d.key0 = (uint32_t)q.seed;
         d.key1 = (uint32_t)(q.seed >> 32);
         d.gamma = cfg.gamma;
+        d.xshift = stride_shift(q.dstride, 8);
+        d.pad = 0;
         wo += q.R;
         ro += q.m;
         co += q.n;
+    }
+    // the captured grids cover max_workers workers (pipelined: pipe_workers)
+    if (wo > cfg.max_workers) {
+        g_srv_last = "internal: active workers exceed max_workers";
+        return ASYRK_ERR_DEVICE;
     }
     h.total_workers = wo;
     h.total_rows = ro;
@@ -682,6 +708,9 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         s->stats.gpu_seconds += ms * 1e-3;
         s->stats.rounds++;
         s->stats.row_updates += round_rows;
+        s->stats.round_workers += h.total_workers;
+        s->stats.round_systems += h.nact;
+        s->stats.pipelined_rounds += pipe;
     }
     // ---- bookkeeping and retirement: every finished x is copied out, then one wait
     std::vector<std::unique_ptr<Request>> keep, out;
@@ -704,7 +733,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         }
     }
     s->active.swap(keep);
-    s->n_active.store((int64_t)(s->active.size() + s->staged.size()));
+    s->n_active.store((int64_t)(s->active.size() + s->staged.size() + s->ready.size()));
     if (!out.empty()) {
         SRV_OK(hipStreamSynchronize(s->st));
         const double t = now_s();
@@ -719,7 +748,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             s->done[r->id] = std::move(r);
         }
     }
-    if (n_active) *n_active = (int32_t)(s->active.size() + s->staged.size());
+    if (n_active) *n_active = (int32_t)(s->active.size() + s->staged.size() + s->ready.size());
     if (n_queued) {
         std::lock_guard<std::mutex> lk(s->mu);
         *n_queued = (int32_t)s->queue.size();
