@@ -416,19 +416,23 @@ def run_serving(args):
         st0 = srv.stats()
         futs = [sub_pool.submit(submit, k) for k in range(count)]
         done, lat, sweeps, bad = {}, [], [], 0
-        while len(done) < count:
-            active, queued = srv.progress()
-            if active == 0 and queued == 0:
-                time.sleep(0.0005)
-            for rid in srv.take_completed():
-                while rid not in id_of:  # its submit call is still returning
-                    time.sleep(0.0001)
-                k = id_of[rid]
-                status, st, _ = srv.poll(rid)
-                done[k] = st
-                lat.append(st["t_done"] - (t0 + arrivals[k]))
-                sweeps.append(st["sweeps"])
-                bad += status != "OK" or st["rel_residual"] > tol
+        srv.start()  # the library's round loop on its own thread
+        try:
+            while len(done) < count:
+                ids_done = srv.take_completed()
+                if not ids_done:
+                    time.sleep(0.0002)
+                for rid in ids_done:
+                    while rid not in id_of:  # its submit call is still returning
+                        time.sleep(0.0001)
+                    k = id_of[rid]
+                    status, st, _ = srv.poll(rid)
+                    done[k] = st
+                    lat.append(st["t_done"] - (t0 + arrivals[k]))
+                    sweeps.append(st["sweeps"])
+                    bad += status != "OK" or st["rel_residual"] > tol
+        finally:
+            srv.stop()
         for f in futs:
             f.result()
         t_end = max(st["t_done"] for st in done.values())

@@ -397,6 +397,14 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
  * n_queued (nullable) receive the counts after the round.  Errors: DEVICE. */
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued);
 
+/* The round loop on the calling thread: progress() until *stop becomes
+ * nonzero (the caller owns the flag and sets it from another thread); while
+ * nothing is active or queued it sleeps until a submit, waking at least
+ * every millisecond to read the flag.  Only one thread may run rounds on a
+ * server at a time.  Errors: INVALID_ARG, or progress()'s DEVICE, which ends
+ * the loop. */
+asyrk_status asyrk_server_run(asyrk_server *s, const volatile int32_t *stop);
+
 /* Result of a finished request: x_out (nullable, HOST double[n]) and stats
  * (nullable).  Returns the request's final status, ASYRK_PENDING while it is
  * queued or active, INVALID_ARG for an unknown or already-polled id. */

@@ -147,6 +147,7 @@ def lib():
     L.asyrk_server_destroy.argtypes = [P]
     L.asyrk_server_submit.argtypes = [P, i64, i64, P, P, P, P, dbl, u64, P]
     L.asyrk_server_progress.argtypes = [P, P, P]
+    L.asyrk_server_run.argtypes = [P, P]
     L.asyrk_server_poll.argtypes = [P, i64, P, P]
     L.asyrk_server_stats_get.argtypes = [P, P]
     L.asyrk_server_take_completed.argtypes = [P, P, i64, P]
@@ -156,7 +157,8 @@ def lib():
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
-                 "asyrk_server_poll", "asyrk_server_stats_get", "asyrk_server_take_completed"):
+                 "asyrk_server_poll", "asyrk_server_stats_get", "asyrk_server_take_completed",
+                 "asyrk_server_run"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -381,7 +383,8 @@ def now() -> float:
 
 class Server:
     """Continuous-batching solve server (asyrk_server_*): submit systems with
-    FP32 values from any thread, drive rounds with progress() from one thread,
+    FP32 values from any thread, drive rounds with progress() from one thread
+    or with start() (the library's own round loop on a background thread),
     collect results with poll()."""
 
     def __init__(self, **cfg):
@@ -396,11 +399,39 @@ class Server:
         _check(L.asyrk_server_create(C.byref(h), C.byref(c)), "asyrk_server_create")
         self._h = h
         self.config = {f: getattr(c, f) for f, _ in ServerConfig._fields_}
+        self._runner = None
+
+    def start(self):
+        """Run rounds on a background thread (asyrk_server_run: the loop is
+        native, so it runs outside the GIL) until stop()."""
+        import threading
+        if self._runner is not None:
+            raise RuntimeError("the round loop is already running")
+        self._stop = C.c_int32(0)
+        self._run_rc = None
+
+        def body():
+            self._run_rc = lib().asyrk_server_run(self._h, C.byref(self._stop))
+
+        self._runner = threading.Thread(target=body, daemon=True)
+        self._runner.start()
+
+    def stop(self):
+        """End the round loop started by start(); raises if it ended on an error."""
+        if getattr(self, "_runner", None) is None:
+            return
+        self._stop.value = 1
+        self._runner.join()
+        self._runner = None
+        _check(self._run_rc, "asyrk_server_run")
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().asyrk_server_destroy(self._h)
-            self._h = None
+            try:
+                self.stop()
+            finally:
+                lib().asyrk_server_destroy(self._h)
+                self._h = None
 
     def __del__(self):
         try:

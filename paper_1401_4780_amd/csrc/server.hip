@@ -290,6 +290,7 @@ struct asyrk_server {
     int sweep_blocks[2] = {0, 0};
 
     std::mutex mu;
+    std::condition_variable cv_submit;  // signalled by submit for an idle run loop
     std::deque<std::unique_ptr<Request>> queue;
     std::unordered_map<int64_t, std::unique_ptr<Request>> done;
     std::unordered_set<int64_t> live;  // submitted and not yet polled
@@ -535,6 +536,7 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     s->live.insert(r->id);
     s->queue.push_back(std::move(r));
     s->stats.submitted++;
+    s->cv_submit.notify_one();
     return ASYRK_OK;
 }
 
@@ -752,6 +754,21 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     if (n_queued) {
         std::lock_guard<std::mutex> lk(s->mu);
         *n_queued = (int32_t)s->queue.size();
+    }
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_server_run(asyrk_server *s, const volatile int32_t *stop) {
+    if (!s || !stop) return ASYRK_ERR_INVALID_ARG;
+    while (*stop == 0) {
+        int32_t act = 0, q = 0;
+        const asyrk_status rc = asyrk_server_progress(s, &act, &q);
+        if (rc) return rc;
+        if (act == 0 && q == 0) {
+            // idle: sleep until a submit (or 1 ms, to see the stop flag)
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->queue.empty()) s->cv_submit.wait_for(lk, std::chrono::milliseconds(1));
+        }
     }
     return ASYRK_OK;
 }

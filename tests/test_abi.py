@@ -151,6 +151,7 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_server_progress(None, None, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_poll(None, 1, None, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_take_completed(None, None, 0, None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_server_run(None, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_destroy(None)] == "OK"
 
 

@@ -189,3 +189,55 @@ def test_lane_widths_and_completion_list(lanes, pipe_workers, pipe_lanes):
         assert srv.take_completed() == []
         for k, s in enumerate(systems):
             _check(s, out[k])
+
+
+def test_native_round_loop_with_concurrent_submitters():
+    """start() runs the library's round loop (asyrk_server_run) on its own
+    thread: requests submitted from several threads while it runs all finish
+    to tolerance, an idle loop wakes for a late submit, and stop() ends it."""
+    import threading
+    import time
+    _say("server native round loop")
+    systems = _systems(range(700, 716), [1000 + 900 * k for k in range(16)])
+    ids = [None] * len(systems)
+    with P.Server(budget_bytes=1 << 30) as srv:
+        srv.start()
+        with pytest.raises(RuntimeError):
+            srv.start()
+
+        def worker(lo):
+            for k in range(lo, len(systems) - 1, 3):
+                s = systems[k]
+                ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(3)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        out = {}
+
+        def collect(want):
+            t_end = time.monotonic() + 60.0
+            while len(out) < want and time.monotonic() < t_end:
+                got = srv.take_completed()
+                if not got:
+                    time.sleep(0.001)
+                for rid in got:
+                    k = ids.index(rid)
+                    out[k] = srv.poll(rid, n=systems[k].n)
+
+        collect(len(systems) - 1)
+        assert len(out) == len(systems) - 1
+        # the loop is idle now; a late request wakes it
+        time.sleep(0.01)
+        s = systems[-1]
+        ids[-1] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=99)
+        collect(len(systems))
+        srv.stop()
+        srv.stop()  # a second stop is a no-op
+        assert len(out) == len(systems)
+        for k, s in enumerate(systems):
+            _check(s, out[k])
+        st = srv.stats()
+        assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
+        srv.start()  # close() ends a running loop before destroying the server
