@@ -134,8 +134,14 @@ int auto_lanes(const asyrk_system *s, int64_t R) {
     return G;
 }
 
-// log2 of the iterate's element stride for an FP32 or FP64 iterate
-int xshift_of(const asyrk_system *s, bool f32) { return stride_shift(s->xstride, f32 ? 4 : 8); }
+// log2 of the iterate's element stride for an FP32 or FP64 iterate.  The
+// single-coordinate update (Algorithm 1) issues one atomic per row against
+// its gathers, so it is bound by gathers, which a dense iterate serves better
+// from the caches: it uses the buffer densely.
+int xshift_of(const asyrk_system *s, bool f32, const asyrk_solve_params &p) {
+    if (p.update == ASYRK_UPDATE_ONE) return 0;
+    return stride_shift(s->xstride, f32 ? 4 : 8);
+}
 
 double lambda_mp(const asyrk_system *s) {
     const double r = std::sqrt((double)s->n / (double)s->m);
@@ -573,7 +579,7 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     SweepArgs a{};
     a.rows = s->rows;
     a.x = s->d_x;
-    a.xshift = xshift_of(s, xk == ASYRK_F32);
+    a.xshift = xshift_of(s, xk == ASYRK_F32, p);
     a.side = s->d_side;
     a.t_begin = t_begin;
     a.t_end = t_end;
@@ -656,7 +662,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
     }
     const bool f32 = xk == ASYRK_F32;
-    const int xsh = xshift_of(s, f32);
+    const int xsh = xshift_of(s, f32, p);
     const hipMemcpyKind h2d = s->mem == ASYRK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const hipMemcpyKind d2h = s->mem == ASYRK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
 
