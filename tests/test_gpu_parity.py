@@ -618,3 +618,39 @@ def test_replay_bf16_ragged_slices_and_alg1_norm2():
                       iter_dtype="f64")
     assert np.linalg.norm(x - ref1["x"]) <= 1e-12 * np.linalg.norm(ref1["x"])
     sysm.close()
+
+
+# ------------------------------------------------------------------ iterate stride regimes
+
+@pytest.mark.parametrize("n,stride", [(3000, 256), ((1 << 20) + 17, 64), ((1 << 23) + 5, 8)])
+def test_iterate_stride_regimes_match_oracle(n, stride):
+    """The device-side iterate keeps one element per 256 B (n <= 2^20), per
+    64 B (n <= 2^23) or is dense; the caller's x is dense in every case.  With
+    few rows over many columns (most columns empty), the single-worker replay
+    (FP64 values), a single pipelined worker (FP32 values, FP64 iterate) and
+    the FP32-iterate replay all follow the oracle in every regime: 1e-12 for
+    the FP64 iterates, the FP32 floor (1e-6 of ||x*||) for the FP32 one."""
+    m = 3000
+    _say(f"iterate stride n={n} expect={stride}")
+    s64 = synth.uniform_rows(m, n, 12, seed=21, dtype="f64", normalize=False, require_full_columns=False)
+    ref = oracle_run(s64, 1.0, 3, 4)
+    sysm = make_system(s64, device=True)
+    assert sysm.info()["iterate_stride"] == stride
+    x, st = gpu_solve(sysm, s64, True, gamma=1.0, sweeps=3, seed=4, mode="replay", history=8)
+    assert st["status"] == "OK"
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    sysm.close()
+
+    s32 = synth.uniform_rows(m, n, 12, seed=22, dtype="f32", normalize=False, require_full_columns=False)
+    ref = oracle_run(s32, 1.0, 3, 5)
+    sysm = make_system(s32, device=True)
+    assert sysm.info()["iterate_stride"] == stride
+    x, st = gpu_solve(sysm, s32, True, gamma=1.0, sweeps=3, seed=5, in_flight=1, lanes=4, pipeline=True,
+                      iter_dtype="f64", history=8)
+    assert st["status"] == "OK" and st["pipelined"] == 1
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    x, st = gpu_solve(sysm, s32, True, gamma=1.0, sweeps=3, seed=5, mode="replay", iter_dtype="f32")
+    assert st["status"] == "OK"
+    assert np.linalg.norm(x - ref["x"]) <= 1e-6 * np.linalg.norm(s32.x_star)  # FP32 floor
+    sysm.close()
