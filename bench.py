@@ -394,7 +394,8 @@ def run_serving(args):
                    **({"lanes": args.lanes} if args.lanes in (4, 8) else {}),
                    **({"max_workers": args.max_workers} if args.max_workers else {}),
                    **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}),
-                   **({"pipe_lanes": args.pipe_lanes} if args.pipe_lanes else {}))
+                   **({"pipe_lanes": args.pipe_lanes} if args.pipe_lanes else {}),
+                   fixed_rounds=int(args.fixed_rounds))
 
     def drive(first, count, arrivals):
         """Submit requests first..first+count-1 at their arrival times (seconds
@@ -484,7 +485,7 @@ def run_serving(args):
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
                        "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"],
-                       "submit_threads": args.submit_threads},
+                       "submit_threads": args.submit_threads, "fixed_rounds": srv.config["fixed_rounds"]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
@@ -497,6 +498,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
+    ap.add_argument("--fixed-rounds", action="store_true",
+                    help="serving: every round runs the full inner sweeps (no sizing of later rounds)")
     ap.add_argument("--submit-threads", type=int, default=8,
                     help="serving: client threads calling submit (each packs its own requests)")
     ap.add_argument("--lanes", type=int, default=0)

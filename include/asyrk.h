@@ -339,7 +339,8 @@ typedef struct asyrk_server asyrk_server;
 typedef struct asyrk_server_config {
     int64_t budget_bytes;  /* device memory for resident systems (one arena), default 64 GiB */
     int32_t max_slots;     /* systems active at once, default 1024 */
-    int32_t inner_sweeps;  /* sweeps per round (refinement inner solve), default 8 */
+    int32_t inner_sweeps;  /* sweeps per round (refinement inner solve), default 8; a request's
+                              later rounds may run fewer (see fixed_rounds) */
     int64_t max_workers;   /* row workers over all active systems, default 65536 */
     int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
     int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */
@@ -354,7 +355,10 @@ typedef struct asyrk_server_config {
                               default 8192; 0 = never */
     int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 8 (fewer
                               entries per lane shorten each latency-bound ticket) */
-    int32_t reserved;      /* must be 0 */
+    int32_t fixed_rounds;  /* 0 (default): after each round a request's next round runs the
+                              sweeps its measured contraction per sweep predicts it still needs
+                              to reach tol, plus one, at most inner_sweeps; 1: always
+                              inner_sweeps */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {

@@ -260,6 +260,7 @@ struct Request {
     int64_t pin_bytes = 0;
     int64_t ticket = 0;
     int32_t rounds = 0;
+    int32_t next_sweeps = 0;  // sweeps of the request's next round
     int64_t sweeps = 0;
     double rel = 1.0;
     int32_t status = ASYRK_OK;
@@ -400,7 +401,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
         !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 4 && cfg.lanes != 8) || cfg.pipe_workers < 0 ||
-        (cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) || cfg.reserved != 0)
+        (cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) ||
+        (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1))
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
@@ -621,6 +623,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         SRV_OK(launch_zero(base + q.off_x, q.n * 8, s->cst));
         q.t_admit = now_s();
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
+        q.next_sweeps = cfg.inner_sweeps;
         s->workers_in_use += q.R;
         if (!defer) active_workers += q.R;
         (defer ? s->staged : s->active).push_back(std::move(r));
@@ -666,7 +669,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         d.row_off = ro;
         d.col_off = co;
         d.t_begin = q.ticket;
-        d.t_end = q.ticket + (int64_t)cfg.inner_sweeps * q.m;
+        d.t_end = q.ticket + (int64_t)q.next_sweeps * q.m;
         d.key0 = (uint32_t)q.seed;
         d.key1 = (uint32_t)(q.seed >> 32);
         d.gamma = cfg.gamma;
@@ -699,7 +702,7 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     float ms = 0.f;
     SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
     int64_t round_rows = 0;
-    for (int k = 0; k < h.nact; ++k) round_rows += (int64_t)cfg.inner_sweeps * s->active[k]->m;
+    for (int k = 0; k < h.nact; ++k) round_rows += (int64_t)s->active[k]->next_sweeps * s->active[k]->m;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &r : s->active)
@@ -718,10 +721,12 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     std::vector<std::unique_ptr<Request>> keep, out;
     for (int k = 0; k < h.nact; ++k) {
         std::unique_ptr<Request> &r = s->active[k];
-        r->ticket += (int64_t)cfg.inner_sweeps * r->m;
-        r->sweeps += cfg.inner_sweeps;
+        const int ns = r->next_sweeps;
+        r->ticket += (int64_t)ns * r->m;
+        r->sweeps += ns;
         r->rounds++;
         const double nr = s->h_norm2[k];
+        const double prev = r->rel;
         r->rel = r->b_norm2 > 0 ? std::sqrt(nr / r->b_norm2) : std::sqrt(nr);
         const bool conv = r->rel <= r->tol;
         const bool bad = !std::isfinite(r->rel);
@@ -731,6 +736,18 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
             SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, s->st));
             out.push_back(std::move(r));
         } else {
+            // Size the next round from this one: RK contracts the residual by
+            // a roughly constant factor per sweep, so the sweeps still needed
+            // are log(tol / rel) / log(rho), rho the factor measured over the
+            // round just run; one more for safety, at most inner_sweeps.
+            int nxt = cfg.inner_sweeps;
+            if (!cfg.fixed_rounds && prev > 0.0 && r->rel > 0.0 && r->rel < prev) {
+                const double rho = std::pow(r->rel / prev, 1.0 / ns);
+                const double need = std::log(r->tol / r->rel) / std::log(rho);
+                if (std::isfinite(need))
+                    nxt = (int)std::min<double>(cfg.inner_sweeps, std::max(1.0, std::ceil(need) + 1.0));
+            }
+            r->next_sweeps = nxt;
             keep.push_back(std::move(r));
         }
     }

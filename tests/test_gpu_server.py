@@ -241,3 +241,23 @@ def test_native_round_loop_with_concurrent_submitters():
         st = srv.stats()
         assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
         srv.start()  # close() ends a running loop before destroying the server
+
+
+def test_sized_later_rounds_vs_fixed_rounds():
+    """By default a request's later rounds run only the sweeps its measured
+    contraction predicts (at most inner_sweeps); fixed_rounds = 1 runs
+    inner_sweeps every round.  Both reach the tolerance; the sized rounds take
+    fewer sweeps over the batch."""
+    _say("server sized vs fixed rounds")
+    systems = _systems(range(800, 808), [2000, 9000, 30000, 1500, 60000, 4000, 12000, 25000])
+    sweeps = {}
+    for fixed in (0, 1):
+        with P.Server(budget_bytes=1 << 30, fixed_rounds=fixed) as srv:
+            assert srv.config["fixed_rounds"] == fixed
+            res = _run_all(srv, systems)
+            for s, r in zip(systems, res):
+                _check(s, r)
+            sweeps[fixed] = [r[1]["sweeps"] for r in res]
+            if fixed:
+                assert all(v % srv.config["inner_sweeps"] == 0 for v in sweeps[fixed])
+    assert sum(sweeps[0]) < sum(sweeps[1])
