@@ -10,7 +10,9 @@
 //   * row records stream from HBM with 16-byte loads, one unit per lane;
 //   * x is read with agent-scope relaxed atomic loads (global_load sc1) so a
 //     read sees every atomic already performed by any XCD, and written with
-//     no-return global_atomic_add_f32/f64; x (4-16 MB) lives in the caches;
+//     no-return global_atomic_add_f32/f64; each element of x has a cache line
+//     of its own (element c at x[c << xshift]) so that accesses to
+//     neighbouring columns do not queue behind each other;
 //   * no LDS and no MFMA: there is no dense contraction in this method.
 #include "device.h"
 
