@@ -48,10 +48,15 @@ R_SWEEP = (1024, 2048, 4096, 8192, 16384, 32768, 65536)
 
 
 def kernel_source_hash() -> str:
+    """Hash of the code (comments and blank lines removed) of the sweep kernels,
+    their launch geometry, the iterate stride and the record layout."""
     h = hashlib.sha256()
-    # the sweep kernels, their launch geometry, the iterate stride and the record layout
     for f in ("kernels.hip", "device.h", "internal.h", "layout.h", "setup.cpp"):
-        h.update((ROOT / "paper_1401_4780_amd" / "csrc" / f).read_bytes())
+        text = (ROOT / "paper_1401_4780_amd" / "csrc" / f).read_text()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
