@@ -422,7 +422,7 @@ def run_serving(args):
 
         st0 = srv.stats()
         futs = [sub_pool.submit(submit, k) for k in range(count)]
-        done, lat, sweeps, bad = {}, [], [], 0
+        done, lat, sweeps, bad, parts = {}, [], [], 0, []
         srv.start()  # the library's round loop on its own thread
         try:
             while len(done) < count:
@@ -436,6 +436,8 @@ def run_serving(args):
                     status, st, _ = srv.poll(rid)
                     done[k] = st
                     lat.append(st["t_done"] - (t0 + arrivals[k]))
+                    parts.append((st["t_submit"] - (t0 + arrivals[k]), st["t_admit"] - st["t_submit"],
+                                  st["t_done"] - st["t_admit"]))
                     sweeps.append(st["sweeps"])
                     bad += status != "OK" or st["rel_residual"] > tol
         finally:
@@ -448,6 +450,10 @@ def run_serving(args):
         gpu_s = st1["gpu_seconds"] - st0["gpu_seconds"]
         return {"solves_per_s": count / (t_end - t0), "latency_s_p50": float(np.percentile(lat, 50)),
                 "latency_s_p99": float(np.percentile(lat, 99)), "mean_sweeps": float(np.mean(sweeps)),
+                # medians of the latency's parts: packing on the client's thread,
+                # queueing until admission, admission to completion
+                "latency_parts_s_p50": {name: float(np.median([q[i] for q in parts]))
+                                        for i, name in enumerate(("pack", "queue", "rounds"))},
                 "failed": int(bad),
                 # row updates per second of round time on the GPU, and the share of
                 # wall time the GPU spent in rounds
