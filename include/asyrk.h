@@ -353,7 +353,7 @@ typedef struct asyrk_server_config {
     int32_t pipe_workers;  /* rounds whose active systems hold at most this many row workers
                               run the pipelined worker loop (see asyrk_solve_params.pipeline),
                               default 8192; 0 = never */
-    int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 8 (fewer
+    int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 16 (fewer
                               entries per lane shorten each latency-bound ticket) */
     int32_t fixed_rounds;  /* 0 (default): after each round a request's next round runs the
                               sweeps its measured contraction per sweep predicts it still needs

@@ -387,7 +387,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->pinned_bytes = (int64_t)4 << 30;
     c->lanes = 4;
     c->pipe_workers = 8192;
-    c->pipe_lanes = 8;
+    c->pipe_lanes = 16;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
