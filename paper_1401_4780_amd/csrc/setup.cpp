@@ -27,11 +27,11 @@ static inline double promote(const void *vals, int vk, int64_t k) {
     }
 }
 
-// Host threads for a pass over m rows: one per 8192 rows, at most 16 and at
+// Host threads for a pass over m rows: one per 4096 rows, at most 16 and at
 // most the hardware's.
 static unsigned threads_for(int64_t m) {
     const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(hw, m / 8192));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(hw, m / 4096));
 }
 
 // fn(lo, hi) over `parts` contiguous row ranges, the first on the calling thread.
