@@ -261,3 +261,58 @@ def test_sized_later_rounds_vs_fixed_rounds():
             if fixed:
                 assert all(v % srv.config["inner_sweeps"] == 0 for v in sweeps[fixed])
     assert sum(sweeps[0]) < sum(sweeps[1])
+
+
+def test_invalid_submissions_are_rejected_and_the_server_goes_on():
+    """Submit validates on the caller's thread: a zero row is ZERO_ROW;
+    unsorted or out-of-range columns, a non-finite value or b, a nonpositive
+    tolerance are INVALID_ARG.  Rejected requests leave no trace (no id, no
+    staging memory), and a valid request afterwards is served normally."""
+    _say("server invalid submissions")
+    s = _systems([900], [3000])[0]
+    with P.Server(budget_bytes=1 << 30) as srv:
+        def bad(name, expect, **edit):
+            rp, col, val, b = s.row_ptr.copy(), s.col.copy(), s.val.copy(), s.b.copy()
+            tol = edit.pop("tol", TOL)
+            if "fn" in edit:
+                rp, col, val, b = edit["fn"](rp, col, val, b)
+            with pytest.raises(P.AsyrkError) as ei:
+                srv.submit(rp, col, val, b, n=s.n, tol=tol)
+            assert ei.value.name == expect, name
+
+        def empty_row(rp, col, val, b):  # row 5's stored values all zero: ||a_5|| = 0
+            val = val.copy()
+            val[int(rp[5]):int(rp[6])] = 0.0
+            return rp, col, val, b
+
+        def swap_cols(rp, col, val, b):
+            col = col.copy()
+            a = int(rp[7])
+            col[a], col[a + 1] = col[a + 1], col[a]
+            return rp, col, val, b
+
+        def col_oob(rp, col, val, b):
+            col = col.copy()
+            col[int(rp[9 + 1]) - 1] = s.n
+            return rp, col, val, b
+
+        def nan_val(rp, col, val, b):
+            val = val.copy()
+            val[11] = np.nan
+            return rp, col, val, b
+
+        def inf_b(rp, col, val, b):
+            b = b.copy()
+            b[3] = np.inf
+            return rp, col, val, b
+
+        bad("empty row", "ZERO_ROW", fn=empty_row)
+        bad("unsorted columns", "INVALID_ARG", fn=swap_cols)
+        bad("column out of range", "INVALID_ARG", fn=col_oob)
+        bad("NaN value", "INVALID_ARG", fn=nan_val)
+        bad("infinite b", "INVALID_ARG", fn=inf_b)
+        bad("zero tolerance", "INVALID_ARG", tol=0.0)
+        st = srv.stats()
+        assert st["submitted"] == 0 and st["queued"] == 0 and st["arena_used"] == 0
+        res = _run_all(srv, [s])
+        _check(s, res[0])
