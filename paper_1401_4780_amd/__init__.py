@@ -456,7 +456,10 @@ class Server:
         return rid.value
 
     def progress(self):
-        """One round; returns (active, queued) afterwards."""
+        """One round; returns (active, queued) afterwards.  Not while start()'s
+        loop runs (one thread runs rounds at a time)."""
+        if getattr(self, "_runner", None) is not None:
+            raise RuntimeError("the round loop started by start() is running; call stop() first")
         a, q = C.c_int32(), C.c_int32()
         _check(lib().asyrk_server_progress(self._h, C.byref(a), C.byref(q)), "asyrk_server_progress")
         return a.value, q.value

@@ -204,6 +204,8 @@ def test_native_round_loop_with_concurrent_submitters():
         srv.start()
         with pytest.raises(RuntimeError):
             srv.start()
+        with pytest.raises(RuntimeError):
+            srv.progress()  # one thread runs rounds at a time
 
         def worker(lo):
             for k in range(lo, len(systems) - 1, 3):
