@@ -399,6 +399,7 @@ def run_serving(args):
         return synth.serving_system(rid, m, n)
 
     srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}),
+                   **({"lanes": 0, "pipe_lanes": 0} if args.tune_lanes else {}),
                    **({"lanes": args.lanes} if args.lanes in (4, 8) else {}),
                    **({"max_workers": args.max_workers} if args.max_workers else {}),
                    **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}),
@@ -499,7 +500,8 @@ def run_serving(args):
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
                        "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"],
-                       "submit_threads": args.submit_threads, "fixed_rounds": srv.config["fixed_rounds"]},
+                       "submit_threads": args.submit_threads, "fixed_rounds": srv.config["fixed_rounds"],
+                       "lanes_in_use": [st["lanes"], st["pipe_lanes"]]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
@@ -512,6 +514,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
+    ap.add_argument("--tune-lanes", action="store_true",
+                    help="serving: the server picks lanes per row online (lanes = pipe_lanes = 0)")
     ap.add_argument("--fixed-rounds", action="store_true",
                     help="serving: every round runs the full inner sweeps (no sizing of later rounds)")
     ap.add_argument("--submit-threads", type=int, default=8,

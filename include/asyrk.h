@@ -349,12 +349,20 @@ typedef struct asyrk_server_config {
                               each), default 4 GiB; 0 = none; a request that does not fit is
                               uploaded from pageable memory */
     int32_t lanes;         /* lanes per row in the packed sweep of busy rounds: 4 or 8 (each
-                              keeps rows of up to 64 entries in registers), default 4 */
+                              keeps rows of up to 64 entries in registers), default 4; 0 =
+                              tune online, per load bucket (active workers in [w, 2w) for
+                              w = pipe_workers, 2 pipe_workers, 4 pipe_workers, and beyond):
+                              a bucket's first rounds sweep their systems once per candidate
+                              (4, 8; each twice, each first once), timed, the round's own
+                              sweep last, and the fastest total is kept for the bucket */
     int32_t pipe_workers;  /* rounds whose active systems hold at most this many row workers
                               run the pipelined worker loop (see asyrk_solve_params.pipeline),
                               default 8192; 0 = never */
     int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 16 (fewer
-                              entries per lane shorten each latency-bound ticket) */
+                              entries per lane shorten each latency-bound ticket); 0 = tune
+                              online among 4, 8, 16 as for lanes, with the buckets below
+                              pipe_workers / 4, below pipe_workers / 2, below pipe_workers,
+                              and pipe_workers */
     int32_t fixed_rounds;  /* 0 (default): after each round a request's next round runs the
                               sweeps its measured contraction per sweep predicts it still needs
                               to reach tol, plus one, at most inner_sweeps; 1: always
@@ -377,6 +385,11 @@ typedef struct asyrk_server_stats {
     int64_t round_workers;     /* row workers summed over rounds (/ rounds = mean per round) */
     int64_t round_systems;     /* active systems summed over rounds */
     int64_t pipelined_rounds;  /* rounds that ran the pipelined worker loop */
+    int32_t lanes;             /* lanes per row of the last plain round's sweep */
+    int32_t pipe_lanes;        /* lanes per row of the last pipelined round's sweep */
+    int32_t lanes_tuning;      /* bit 0 / bit 1: the last plain / pipelined round timed every
+                                  candidate width (its load bucket was still being tuned) */
+    int32_t buckets_untuned;   /* load buckets (4 per loop) not tuned yet; 0 with fixed widths */
 } asyrk_server_stats;
 
 /* Defaults for asyrk_server_config. */

@@ -104,6 +104,8 @@ class ServerStats(C.Structure):
         ("active", C.c_int64), ("queued", C.c_int64), ("rounds", C.c_int64),
         ("row_updates", C.c_int64), ("arena_used", C.c_int64), ("gpu_seconds", C.c_double),
         ("round_workers", C.c_int64), ("round_systems", C.c_int64), ("pipelined_rounds", C.c_int64),
+        ("lanes", C.c_int32), ("pipe_lanes", C.c_int32), ("lanes_tuning", C.c_int32),
+        ("buckets_untuned", C.c_int32),
     ]
 
 

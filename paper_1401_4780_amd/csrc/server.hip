@@ -46,6 +46,11 @@ using namespace asyrk;
 namespace {
 
 constexpr int kVecBlocks = 2048;     // grid of the flat vector/residual kernels
+// Candidate lane widths of the plain and the pipelined sweep, and the number
+// of load buckets the online choice keeps apart.
+constexpr int kLaneCands[2][3] = {{4, 8, 0}, {4, 8, 16}};
+constexpr int kNumCands[2] = {2, 3};
+constexpr int kBuckets = 4;
 
 struct SlotDesc {
     Rows rows;
@@ -284,11 +289,20 @@ struct asyrk_server {
     TableHead *h_head = nullptr;   // pinned
     SlotDesc *h_slots = nullptr;   // pinned
     double *h_norm2 = nullptr;     // pinned
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // plain / pipelined sweep
+    hipGraphExec_t graph[2][3] = {};  // per loop (plain / pipelined) and candidate lane width
+    int lanes_last[2] = {4, 16};   // lanes per row of the last plain / pipelined round
+    bool tuned_last[2] = {true, true};  // that round ran with a tuned (or fixed) width
+    // online choice of the lane width (config lanes / pipe_lanes = 0), per
+    // loop and per load bucket (active workers): the bucket's first rounds
+    // time every candidate on the same systems
+    bool tune_on[2] = {false, false};
+    int tuned_G[2][kBuckets] = {};   // 0 while the bucket is being tuned
+    int tune_done[2][kBuckets] = {};
+    double tune_ms[2][kBuckets][3] = {};
+    hipEvent_t te[6] = {};         // start / end of each candidate's sweep
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t cst = nullptr;     // admission uploads
     hipEvent_t ev_copy = nullptr;  // recorded on cst after the last admission batch
-    int sweep_blocks[2] = {0, 0};
 
     std::mutex mu;
     std::condition_variable cv_submit;  // signalled by submit for an idle run loop
@@ -327,33 +341,80 @@ int64_t request_bytes(const Request &r) {
            Arena::round_up(r.n * r.dstride) + 6 * 256;
 }
 
-hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe) {
-    const int wblocks = kVecBlocks;
-    const dim3 grid(s->sweep_blocks[pipe]);
-    const dim3 block(pipe ? 64 : 256);  // light rounds: one wave per block, spread over the CUs
-    hipLaunchKernelGGL(srv_zero_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+constexpr int kTunePasses = 2;  // tuning rounds per candidate (each candidate runs first once per pass)
+
+// Load bucket of a round for lane tuning: powers of two of the active
+// workers, from pipe_workers / 8 (pipelined rounds) or pipe_workers (plain).
+int load_bucket(int64_t workers, int64_t base) {
+    int b = 0;
+    for (int64_t lim = std::max<int64_t>(1, base) * 2; b < kBuckets - 1 && workers >= lim; lim *= 2) ++b;
+    return b;
+}
+
+int cand_index(int pipe, int G) {
+    for (int k = 0; k < kNumCands[pipe]; ++k)
+        if (kLaneCands[pipe][k] == G) return k;
+    return 0;
+}
+
+// zero d and the norms, then one sweep over every active system with G lanes
+// per row; the grid covers max_workers workers (pipelined: pipe_workers)
+hipError_t launch_zero_and_sweep(asyrk_server *s, hipStream_t st, int pipe, int G) {
+    hipLaunchKernelGGL(srv_zero_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+    const int64_t workers = pipe ? std::min<int64_t>(s->cfg.max_workers, s->cfg.pipe_workers) : s->cfg.max_workers;
+    const int block = pipe ? 64 : 256;  // light rounds: one wave per block, spread over the CUs
+    const dim3 grid((unsigned)((workers * G + block - 1) / block));
     if (pipe) {
-        switch (s->cfg.pipe_lanes) {
-            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, block, 0, st, s->d_head, s->d_slots); break;
-            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, block, 0, st, s->d_head, s->d_slots); break;
-            default: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, block, 0, st, s->d_head, s->d_slots); break;
+        switch (G) {
+            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            case 16: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            default: return hipErrorInvalidValue;
         }
-    } else if (s->cfg.lanes == 4) {
-        hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, block, 0, st, s->d_head, s->d_slots);
     } else {
-        hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, block, 0, st, s->d_head, s->d_slots);
+        switch (G) {
+            case 4: hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            default: return hipErrorInvalidValue;
+        }
     }
-    hipLaunchKernelGGL(srv_axpy_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots);
-    hipLaunchKernelGGL(srv_residual_kernel, dim3(wblocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
     return hipGetLastError();
+}
+
+hipError_t launch_finish(asyrk_server *s, hipStream_t st) {
+    hipLaunchKernelGGL(srv_axpy_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots);
+    hipLaunchKernelGGL(srv_residual_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe, int G) {
+    hipError_t e = launch_zero_and_sweep(s, st, pipe, G);
+    return e == hipSuccess ? launch_finish(s, st) : e;
+}
+
+// Capture the round of one sweep variant and lane width as a graph; the
+// kernels read the slot table, so one graph serves every round whatever
+// systems are active.
+hipError_t capture_round(asyrk_server *s, int pipe, int k) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_round(s, s->st, pipe, kLaneCands[pipe][k]);
+        e = hipStreamEndCapture(s->st, &g);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[pipe][k], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
 }
 
 void free_server(asyrk_server *s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
     if (s->cst) (void)hipStreamSynchronize(s->cst);
-    for (hipGraphExec_t g : s->graph)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (auto &row : s->graph)
+        for (hipGraphExec_t g : row)
+            if (g) (void)hipGraphExecDestroy(g);
     (void)hipFree(s->arena.base);
     if (s->pinned.base) (void)hipHostFree(s->pinned.base);
     (void)hipFree(s->d_head);
@@ -367,6 +428,8 @@ void free_server(asyrk_server *s) {
     if (s->st) (void)hipStreamDestroy(s->st);
     if (s->cst) (void)hipStreamDestroy(s->cst);
     if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
+    for (hipEvent_t ev : s->te)
+        if (ev) (void)hipEventDestroy(ev);
     delete s;
 }
 
@@ -400,8 +463,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         asyrk_server_config_init(&cfg);
     if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
-        !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 4 && cfg.lanes != 8) || cfg.pipe_workers < 0 ||
-        (cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) ||
+        !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 0 && cfg.lanes != 4 && cfg.lanes != 8) ||
+        cfg.pipe_workers < 0 || (cfg.pipe_lanes != 0 && cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) ||
         (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1))
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
@@ -431,28 +494,25 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         s->pinned.size = cfg.pinned_bytes;
         s->pinned.free_[0] = cfg.pinned_bytes;
     }
-    s->sweep_blocks[0] = (int)((cfg.max_workers * cfg.lanes + 255) / 256);
-    s->sweep_blocks[1] = (int)((std::min<int64_t>(cfg.max_workers, cfg.pipe_workers) * cfg.pipe_lanes + 63) / 64);
+    s->lanes_last[0] = cfg.lanes ? cfg.lanes : 4;
+    s->lanes_last[1] = cfg.pipe_lanes ? cfg.pipe_lanes : 16;
+    s->tune_on[0] = cfg.lanes == 0;
+    s->tune_on[1] = cfg.pipe_lanes == 0 && cfg.pipe_workers > 0;
+    for (int pipe = 0; pipe < 2; ++pipe)
+        for (int b = 0; b < kBuckets; ++b) s->tuned_G[pipe][b] = s->tune_on[pipe] ? 0 : s->lanes_last[pipe];
+    for (int k = 0; k < 6 && e == hipSuccess && (s->tune_on[0] || s->tune_on[1]); ++k) e = hipEventCreate(&s->te[k]);
     std::memset(s->h_head, 0, sizeof(TableHead));
     if (cfg.use_graph) {
-        // capture the four phases once per sweep variant; they read the slot
-        // table, so the same graphs serve every round whatever systems are active
+        // the four phases captured once per sweep variant and lane width in use
         for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
             if (pipe && cfg.pipe_workers == 0) break;
-            hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t le = launch_round(s, s->st, pipe);
-                e = hipStreamEndCapture(s->st, &g);
-                if (e == hipSuccess) e = le;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[pipe], g, nullptr, nullptr, 0);
-            if (g) (void)hipGraphDestroy(g);
+            for (int k = 0; k < kNumCands[pipe] && e == hipSuccess; ++k)
+                if (s->tune_on[pipe] || kLaneCands[pipe][k] == s->lanes_last[pipe]) e = capture_round(s, pipe, k);
         }
-        if (e != hipSuccess) {
-            free_server(s);
-            return srv_fail(e);
-        }
+    }
+    if (e != hipSuccess) {
+        free_server(s);
+        return srv_fail(e);
     }
     *out = s;
     return ASYRK_OK;
@@ -692,15 +752,51 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     // ---- run one round
     SRV_OK(hipEventRecord(s->e0, s->st));
     const int pipe = h.total_workers <= cfg.pipe_workers ? 1 : 0;
-    if (s->graph[pipe])
-        SRV_OK(hipGraphLaunch(s->graph[pipe], s->st));
-    else
-        SRV_OK(launch_round(s, s->st, pipe));
+    const int bucket = pipe ? load_bucket(h.total_workers, cfg.pipe_workers / 8) : load_bucket(h.total_workers, cfg.pipe_workers);
+    const bool tune = s->tuned_G[pipe][bucket] == 0;
+    const int G = tune ? 0 : s->tuned_G[pipe][bucket];
+    int order[3] = {0, 0, 0};
+    const int nc = kNumCands[pipe];
+    if (tune) {
+        for (int k = 0; k < nc; ++k) order[k] = (s->tune_done[pipe][bucket] + k) % nc;
+        // every candidate sweeps this round's systems from d = 0, timed; the
+        // last one's sweep is the round's (the order rotates so that each
+        // candidate also runs first, on cold caches)
+        for (int k = 0; k < nc; ++k) {
+            SRV_OK(hipEventRecord(s->te[2 * k], s->st));
+            SRV_OK(launch_zero_and_sweep(s, s->st, pipe, kLaneCands[pipe][order[k]]));
+            SRV_OK(hipEventRecord(s->te[2 * k + 1], s->st));
+        }
+        SRV_OK(launch_finish(s, s->st));
+    } else if (s->graph[pipe][cand_index(pipe, G)]) {
+        SRV_OK(hipGraphLaunch(s->graph[pipe][cand_index(pipe, G)], s->st));
+    } else {
+        SRV_OK(launch_round(s, s->st, pipe, G));
+    }
     SRV_OK(hipEventRecord(s->e1, s->st));
     SRV_OK(hipMemcpyAsync(s->h_norm2, s->d_norm2, sizeof(double) * h.nact, hipMemcpyDeviceToHost, s->st));
     SRV_OK(hipStreamSynchronize(s->st));
     float ms = 0.f;
     SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
+    {
+        std::lock_guard<std::mutex> lk(s->mu);  // read by stats_get
+        s->lanes_last[pipe] = tune ? kLaneCands[pipe][order[nc - 1]] : G;
+        s->tuned_last[pipe] = !tune;
+    }
+    if (tune) {
+        for (int k = 0; k < nc; ++k) {
+            float t = 0.f;
+            SRV_OK(hipEventElapsedTime(&t, s->te[2 * k], s->te[2 * k + 1]));
+            s->tune_ms[pipe][bucket][order[k]] += t;
+        }
+        if (++s->tune_done[pipe][bucket] == kTunePasses * nc) {
+            int best = 0;
+            for (int k = 1; k < nc; ++k)
+                if (s->tune_ms[pipe][bucket][k] < s->tune_ms[pipe][bucket][best]) best = k;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->tuned_G[pipe][bucket] = kLaneCands[pipe][best];
+        }
+    }
     int64_t round_rows = 0;
     for (int k = 0; k < h.nact; ++k) round_rows += (int64_t)s->active[k]->next_sweeps * s->active[k]->m;
     {
@@ -826,6 +922,13 @@ asyrk_status asyrk_server_stats_get(asyrk_server *s, asyrk_server_stats *out) {
     out->active = s->n_active.load();
     out->queued = (int64_t)s->queue.size();
     out->arena_used = s->arena.used;
+    out->lanes = s->lanes_last[0];
+    out->pipe_lanes = s->lanes_last[1];
+    out->lanes_tuning = (int32_t)!s->tuned_last[0] | ((int32_t)!s->tuned_last[1] << 1);
+    int32_t left = 0;
+    for (int pipe = 0; pipe < 2; ++pipe)
+        for (int b = 0; b < kBuckets; ++b) left += s->tuned_G[pipe][b] == 0;
+    out->buckets_untuned = left;
     return ASYRK_OK;
 }
 

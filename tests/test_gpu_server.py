@@ -318,3 +318,28 @@ def test_invalid_submissions_are_rejected_and_the_server_goes_on():
         assert st["submitted"] == 0 and st["queued"] == 0 and st["arena_used"] == 0
         res = _run_all(srv, [s])
         _check(s, res[0])
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_online_lane_tuning(use_graph):
+    """lanes = 0 / pipe_lanes = 0: the first rounds of each kind sweep their
+    systems once per candidate width, timed, and keep the fastest; results
+    are unaffected (every candidate sweeps from d = 0 on the same tickets, the
+    round's own sweep last), and once tuned the server runs the chosen widths
+    (re-captured graph)."""
+    _say(f"server online lane tuning use_graph={use_graph}")
+    with P.Server(budget_bytes=1 << 30, lanes=0, pipe_lanes=0, pipe_workers=256, inner_sweeps=2,
+                  use_graph=use_graph) as srv:
+        assert srv.stats()["buckets_untuned"] == 8
+        big = _systems(range(900, 903), [40000] * 3)       # about 2400 workers: plain rounds
+        for s, r in zip(big, _run_all(srv, big)):
+            _check(s, r)
+        small = _systems(range(903, 906), [2000] * 3)      # about 120 workers: pipelined rounds
+        for s, r in zip(small, _run_all(srv, small)):
+            _check(s, r)
+        st = srv.stats()
+        assert st["lanes_tuning"] == 0 and st["buckets_untuned"] <= 6, st  # both visited buckets tuned
+        assert st["lanes"] in (4, 8) and st["pipe_lanes"] in (4, 8, 16)
+        more = _systems(range(906, 908), [30000, 1500])
+        for s, r in zip(more, _run_all(srv, more)):
+            _check(s, r)
