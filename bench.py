@@ -61,19 +61,17 @@ def kernel_source_hash() -> str:
 
 
 def traffic_from_profile(kernel):
-    """HBM bytes per sweep launch measured with rocprofv3 counters, if the
+    """HBM bytes per sweep launch measured with rocprofv3 counters, if a
     committed summary was taken on the current kernel sources and on the same
-    kernel instance."""
-    p = ROOT / "profiles" / "sweep_kernel_c2_4Mx1M_f32values_f64iter_traffic.md"
-    if not p.exists():
-        return None
-    text = p.read_text()
-    mh = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
-    mk = re.search(r"profiled_kernel:\s*(\S+)", text)
-    mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not mh or not mk or not mb or mh.group(1) != kernel_source_hash() or mk.group(1) != kernel:
-        return None
-    return float(mb.group(1))
+    kernel instance (one summary per lane width profiled)."""
+    for p in sorted((ROOT / "profiles").glob("sweep_kernel_c2_4Mx1M_f32values_f64iter_G*_traffic.md")):
+        text = p.read_text()
+        mh = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+        mk = re.search(r"profiled_kernel:\s*(\S+)", text)
+        mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+        if mh and mk and mb and mh.group(1) == kernel_source_hash() and mk.group(1) == kernel:
+            return float(mb.group(1))
+    return None
 
 
 def log(msg):

@@ -296,7 +296,7 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
  * given iterate dtype (-1 = default), and keeps the fastest pair for later
  * solves with lanes = 0 and pipeline = -1 at that R.  Near-ties go by a fixed
  * rule: the pipelined loop only when its best rate beats the plain loop's by
- * more than 3%, then the smallest G within 2% of that loop's best.  best_lanes and
+ * more than 3%, then the smallest G within 3% of that loop's best.  best_lanes and
  * best_pipeline (nullable) receive it; rows_per_s (nullable, double[14]) the
  * rate of each candidate: [0..6] plain, [7..13] pipelined, G ascending.  The
  * system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,

@@ -540,11 +540,11 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
     // Candidates a few percent apart differ by timing noise (a saturated
     // atomic unit), so ties are broken by a fixed rule: the pipelined loop only
     // when it beats the plain one by more than 3%, then the narrowest lane
-    // group within 2% of that loop's fastest.
+    // group within 3% of that loop's fastest.
     const int best_pipe = top[1] > 1.03 * top[0] ? 1 : 0;
     int best = cands[6];
     for (int k = 0; k < 7; ++k)
-        if (rate[best_pipe][k] >= 0.98 * top[best_pipe]) {
+        if (rate[best_pipe][k] >= 0.97 * top[best_pipe]) {
             best = cands[k];
             break;
         }

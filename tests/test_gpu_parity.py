@@ -446,7 +446,7 @@ def test_autotune_picks_a_lane_width():
     best_pipe = max(r for (g, p), r in rates.items() if p)
     assert pipe == (best_pipe > 1.03 * best_plain)
     top = best_pipe if pipe else best_plain
-    assert best == min(g for (g, p), r in rates.items() if p == pipe and r >= 0.98 * top)
+    assert best == min(g for (g, p), r in rates.items() if p == pipe and r >= 0.97 * top)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
     assert st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
     # the tuned loop applies at the tuned R only; elsewhere the rule (R <= 8192)
