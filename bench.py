@@ -225,7 +225,12 @@ def run_c2(args):
         for R in R_SWEEP:
             st = solve(500 + R, R=R)
             sweep[str(R)] = {"rows_per_s": st["rows_per_s"], "sweeps": st["sweeps_done"],
-                             "status": st["status"]}
+                             "status": st["status"], "lanes": st["lanes"], "pipelined": st["pipelined"]}
+            # measured staleness at this R: one traced sweep (the plain loop,
+            # which carries the tracing)
+            x.zero_()
+            tr = sysm.solve(x, GAMMA, 1, 600 + R, in_flight=R, trace=True)
+            sweep[str(R)].update(tau_obs_mean=tr["tau_obs_mean"], tau_obs_max=tr["tau_obs_max"])
         result["in_flight_sweep"] = sweep
         x.zero_()
         st = sysm.solve(x, 0.5, BUDGET, 9, tol=TOL, x_ref=x_ref, in_flight=args.in_flight)

@@ -103,7 +103,9 @@ typedef struct asyrk_solve_params {
                                 when NULL the monitor is ||A x - b||/||b|| */
     int32_t check_every;     /* sweeps between error checks (>= 1), default 1 */
     int32_t refine;          /* 1: FP64 iterative refinement around FP32 sweeps (see asyrk_solve) */
-    int64_t inner_sweeps;    /* refinement: sweeps per inner solve, 0 = choose */
+    int64_t inner_sweeps;    /* refinement: sweeps per inner solve, 0 = choose: the first inner
+                                solve stops when its relative residual is <= 1e-6 or stops
+                                halving per sweep (at most 40), later ones run as many sweeps */
     uint32_t stream_id;      /* RNG stream (third counter word) */
     int32_t trace;           /* 1: time each worker's read-to-write window (tau_obs) */
     int64_t ticket0;         /* first ticket (resume: pass stats.next_ticket) */

@@ -765,6 +765,11 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         push_hist(err0);
         S.final_err = err0;
         bool ok = p.tol > 0.0 && err0 <= p.tol;
+        // Adaptive inner solves: the first one checks its residual after every
+        // sweep; the later ones solve with the same matrix from d = 0 and
+        // reach the FP32 floor in about as many sweeps, so they run that many
+        // without checks (the outer FP64 error still decides convergence).
+        int64_t learned = 0;
         while (!ok && done < sweeps) {
             // r = b - A x64 into the records' b fields (FP32), d = 0
             HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, 0, nullptr, 1, s->d_part, kResidualBlocks,
@@ -778,6 +783,12 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                 if (rc) return rc;
                 ticket += budget * s->m;
                 done += budget;
+            } else if (learned > 0) {
+                const int64_t k = std::min(learned, budget);
+                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + k * s->m, &gpu_s, &wmax, &wsum, &wcnt);
+                if (rc) return rc;
+                ticket += k * s->m;
+                done += k;
             } else {
                 double r0 = 0.0, prev = 1.0;
                 HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, xsh, nullptr, 0, s->d_part, kResidualBlocks,
@@ -789,6 +800,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                     if (rc) return rc;
                     ticket += s->m;
                     done += 1;
+                    learned = k + 1;
                     double rk = 0.0;
                     HIP_OK(launch_residual(s->vk, s->rows, nullptr, s->d_x, 1, xsh, nullptr, 0, s->d_part,
                                            kResidualBlocks, s->st, 1));
