@@ -214,6 +214,22 @@ def _expect(a, device, kind, name):
         raise TypeError(f"{name}: expected {kind}, got {dt}")
 
 
+def _numel(a) -> int:
+    return int(a.numel()) if _is_torch(a) else int(a.size)
+
+
+def _expect_len(a, count, name, at_least=False):
+    """The C ABI reads `count` elements through the pointer: check they exist."""
+    k = _numel(a)
+    if k < count or (not at_least and k != count):
+        raise ValueError(f"{name}: {k} elements, expected {'at least ' if at_least else ''}{count}")
+
+
+def _last(a) -> int:
+    """Last element of a 1-D integer array or tensor (nnz from row_ptr)."""
+    return int(a[-1].item()) if _is_torch(a) else int(a[-1])
+
+
 class System:
     """A consistent sparse system A x = b resident on the GPU.
 
@@ -232,6 +248,11 @@ class System:
         _expect(col, self.device, "int32", "col")
         _expect(b, self.device, "float64", "b")
         self.m = int(row_ptr.shape[0]) - 1
+        if self.m >= 1:
+            nnz = _last(row_ptr)
+            _expect_len(col, max(nnz, 0), "col", at_least=True)
+            _expect_len(val, max(nnz, 0), "val", at_least=True)
+            _expect_len(b, self.m, "b")
         if n is None:
             n = int(col.max()) + 1 if int(col.shape[0]) else 1
         self.n = int(n)
@@ -286,11 +307,16 @@ class System:
 
     def set_rhs(self, b):
         _expect(b, self.device, "float64", "b")
+        _expect_len(b, self.m, "b")
         _check(lib().asyrk_set_rhs(self._h, _ptr(b)), "asyrk_set_rhs")
 
     def residual(self, x, r_out=None) -> float:
         """||b - A x||^2 in FP64 (r_out, if given, receives b - A x)."""
         _expect(x, self.device, "float64", "x")
+        _expect_len(x, self.n, "x")
+        if r_out is not None:
+            _expect(r_out, self.device, "float64", "r_out")
+            _expect_len(r_out, self.m, "r_out")
         v = C.c_double()
         _check(lib().asyrk_residual(self._h, _ptr(x), _ptr(r_out), C.byref(v)), "asyrk_residual")
         return v.value
@@ -304,6 +330,11 @@ class System:
                 rows_out = torch.empty(count, dtype=torch.int32, device="cuda")
             else:
                 rows_out = np.empty(count, dtype=np.int32)
+        _expect(rows_out, self.device, "int32", "rows_out")
+        _expect_len(rows_out, count, "rows_out", at_least=True)
+        if coords_out is not None:
+            _expect(coords_out, self.device, "int32", "coords_out")
+            _expect_len(coords_out, count, "coords_out", at_least=True)
         _check(lib().asyrk_sample_rows(self._h, seed, stream_id, SAMPLE_UNIFORM if uniform else SAMPLE_NORM2,
                                        ticket0, count, _ptr(rows_out), _ptr(coords_out)),
                "asyrk_sample_rows")
@@ -335,8 +366,10 @@ class System:
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
         "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
         _expect(x, self.device, "float64", "x")
+        _expect_len(x, self.n, "x")
         if x_ref is not None:
             _expect(x_ref, self.device, "float64", "x_ref")
+            _expect_len(x_ref, self.n, "x_ref")
         p = SolveParams()
         lib().asyrk_solve_params_init(C.byref(p))
         p.mode = {"async": ASYNC, "replay": REPLAY}[mode]
@@ -402,6 +435,7 @@ class Server:
         self._h = h
         self.config = {f: getattr(c, f) for f, _ in ServerConfig._fields_}
         self._runner = None
+        self._n_of = {}  # request id -> n (the length poll writes)
 
     def start(self):
         """Run rounds on a background thread (asyrk_server_run: the loop is
@@ -451,10 +485,17 @@ class Server:
         for a, kind, name in ((row_ptr, "int64", "row_ptr"), (col, "int32", "col"),
                               (val, "float32", "val"), (b, "float64", "b")):
             _expect(a, False, kind, name)
+        m = int(row_ptr.shape[0]) - 1
+        if m >= 1:
+            nnz = max(int(row_ptr[-1]), 0)
+            _expect_len(col, nnz, "col", at_least=True)
+            _expect_len(val, nnz, "val", at_least=True)
+            _expect_len(b, m, "b")
         rid = C.c_int64()
-        _check(lib().asyrk_server_submit(self._h, row_ptr.shape[0] - 1, int(n), _ptr(row_ptr), _ptr(col),
+        _check(lib().asyrk_server_submit(self._h, m, int(n), _ptr(row_ptr), _ptr(col),
                                          _ptr(val), _ptr(b), float(tol), int(seed), C.byref(rid)),
                "asyrk_server_submit")
+        self._n_of[rid.value] = int(n)
         return rid.value
 
     def progress(self):
@@ -467,14 +508,21 @@ class Server:
         return a.value, q.value
 
     def poll(self, request_id, n=None):
-        """None while pending; else (status, stats dict, x) and the request is released."""
+        """None while pending; else (status, stats dict, x) and the request is
+        released.  x (length n, the request's column count) is returned when n
+        is given."""
+        rid = int(request_id)
+        known = self._n_of.get(rid)
+        if n is not None and known is not None and int(n) != known:
+            raise ValueError(f"request {rid} has n = {known}, not {n}")
         st = RequestStats()
-        x = np.empty(int(n), dtype=np.float64) if n is not None else None
-        rc = lib().asyrk_server_poll(self._h, int(request_id), _ptr(x), C.byref(st))
+        x = np.empty(known, dtype=np.float64) if (n is not None and known is not None) else None
+        rc = lib().asyrk_server_poll(self._h, rid, _ptr(x), C.byref(st))
         if rc == 9:
             return None
         if rc not in (0, 5, 6):
             _check(rc, "asyrk_server_poll")
+        self._n_of.pop(rid, None)
         return STATUS[rc], {f: getattr(st, f) for f, _ in RequestStats._fields_}, x
 
     def take_completed(self, cap=4096):

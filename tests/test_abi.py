@@ -183,6 +183,15 @@ def test_binding_type_checks():
         P.System(rp, col.astype(np.int64), val, b, n=n)
     with pytest.raises(TypeError):
         P.System(rp, col, val, b.astype(np.float32), n=n)
+    # lengths are checked before any pointer crosses the ABI
+    with pytest.raises(ValueError):
+        P.System(rp, col[:-1], val, b, n=n)
+    with pytest.raises(ValueError):
+        P.System(rp, col, val[:-3], b, n=n)
+    with pytest.raises(ValueError):
+        P.System(rp, col, val, b[:-1], n=n)
+    with pytest.raises(ValueError):
+        P.System(rp, col, val, np.concatenate([b, b])[::2], n=n)  # not contiguous
 
 
 @pytest.mark.parametrize("zeta,phi,expect", [(0.0, 1.0, "INVALID_ARG"), (1.0, -1.0, "INVALID_ARG"),

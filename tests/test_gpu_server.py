@@ -314,10 +314,17 @@ def test_invalid_submissions_are_rejected_and_the_server_goes_on():
         bad("NaN value", "INVALID_ARG", fn=nan_val)
         bad("infinite b", "INVALID_ARG", fn=inf_b)
         bad("zero tolerance", "INVALID_ARG", tol=0.0)
+        with pytest.raises(ValueError):  # arrays shorter than row_ptr says: caught before the ABI
+            srv.submit(s.row_ptr, s.col[:-1], s.val, s.b, n=s.n)
+        with pytest.raises(ValueError):
+            srv.submit(s.row_ptr, s.col, s.val, s.b[:-1], n=s.n)
         st = srv.stats()
         assert st["submitted"] == 0 and st["queued"] == 0 and st["arena_used"] == 0
         res = _run_all(srv, [s])
         _check(s, res[0])
+        rid = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL)
+        with pytest.raises(ValueError):  # poll writes the request's own n values
+            srv.poll(rid, n=s.n - 1)
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
