@@ -191,7 +191,7 @@ def run_c2(args):
         "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": traffic,
+                     "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": kernel, "algorithmic_bytes_per_row": bytes_per_row,
                      "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
     }
