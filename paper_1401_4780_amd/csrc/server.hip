@@ -3,21 +3,24 @@
 //
 //   submit()   (any thread)  validate + pack a request on the caller's thread,
 //                            queue it.
-//   progress() (one thread)  one round:
-//       retire  requests whose FP64 relative residual met their tolerance
-//               (or whose round budget ran out): copy x out, free its memory;
-//       admit   queued requests while a slot, the worker budget and the
-//               device-memory budget allow (first-fit arena: no device
-//               allocation or free in the loop);
-//       run     one packed launch per phase over every active system:
-//               zero d -> asynchronous sweeps on A d = r (FP32 values, FP64
-//               correction d and FP64 atomics) -> x += d (FP64) ->
-//               r = b - A x (FP64, written to the per-row side records as the
-//               next round's right-hand side) -> per-system ||r||^2.
-//               The four launches are captured once per sweep variant in a
-//               hipGraph (fixed grids; kernels read the device slot table).
-//   Admissions upload on a copy stream; while a busy round computes, the
-//   requests admitted during it join the round after.
+//   progress() (one thread)  serves one of two groups of active systems,
+//                            the groups taking turns, so that one group's
+//                            round computes while the host serves the other:
+//       collect the group's previous round, and retire requests whose FP64
+//               relative residual met their tolerance (or whose round budget
+//               ran out): copy x out, free its memory;
+//       admit   queued requests while the worker budget and the device-
+//               memory budget allow (first-fit arena: no device allocation or
+//               free in the loop); their uploads run on a copy stream, and a
+//               request joins a group's round once its upload has finished
+//               (waited for only when the GPU has nothing else to do);
+//       run     the group's round, one packed launch per phase over its
+//               systems: zero d -> asynchronous sweeps on A d = r (FP32
+//               values, FP64 correction d and FP64 atomics) -> x += d (FP64)
+//               -> r = b - A x (FP64, written to the per-row side records as
+//               the next round's right-hand side) -> per-system ||r||^2.
+//               The four launches are captured per group and sweep variant in
+//               a hipGraph (fixed grids; kernels read the group's slot table).
 //   poll()     (any thread)  fetch a finished request's x and statistics.
 //
 // Each system runs R_s row workers with R_s bounded by its own Corollary 1
@@ -276,13 +279,11 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-}  // namespace
-
-struct asyrk_server {
-    asyrk_server_config cfg{};
+// One of the two groups of active systems.  Their rounds alternate on two
+// streams: while the host collects one group's round (retire, admit, slot
+// table), the other group's round keeps the GPU busy.
+struct RoundGroup {
     hipStream_t st = nullptr;
-    Arena arena;
-    Arena pinned;                  // host staging arena (pinned), guarded by mu
     TableHead *d_head = nullptr;
     SlotDesc *d_slots = nullptr;
     double *d_norm2 = nullptr;
@@ -290,6 +291,27 @@ struct asyrk_server {
     SlotDesc *h_slots = nullptr;   // pinned
     double *h_norm2 = nullptr;     // pinned
     hipGraphExec_t graph[2][3] = {};  // per loop (plain / pipelined) and candidate lane width
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t te[6] = {};         // start / end of each candidate's sweep (lane tuning)
+    std::vector<std::unique_ptr<Request>> active;
+    // the round in flight (launched, not yet collected)
+    bool in_flight = false;
+    int pipe = 0, bucket = 0, G = 0;
+    bool tune = false;
+    int order[3] = {0, 0, 0};
+    int64_t workers = 0;
+};
+
+}  // namespace
+
+struct asyrk_server {
+    asyrk_server_config cfg{};
+    Arena arena;
+    Arena pinned;                  // host staging arena (pinned), guarded by mu
+    RoundGroup grp[2];
+    int next_group = 0;            // the group the next progress() call serves
+    hipEvent_t e_ref = nullptr;    // time origin of the busy-time union
+    double busy_until_ms = 0.0;
     int lanes_last[2] = {4, 16};   // lanes per row of the last plain / pipelined round
     bool tuned_last[2] = {true, true};  // that round ran with a tuned (or fixed) width
     // online choice of the lane width (config lanes / pipe_lanes = 0), per
@@ -299,10 +321,14 @@ struct asyrk_server {
     int tuned_G[2][kBuckets] = {};   // 0 while the bucket is being tuned
     int tune_done[2][kBuckets] = {};
     double tune_ms[2][kBuckets][3] = {};
-    hipEvent_t te[6] = {};         // start / end of each candidate's sweep
-    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t cst = nullptr;     // admission uploads
-    hipEvent_t ev_copy = nullptr;  // recorded on cst after the last admission batch
+    struct Upload {
+        hipEvent_t ev;             // recorded on cst after the batch's copies
+        std::vector<std::unique_ptr<Request>> reqs;
+    };
+    std::deque<Upload> uploading;  // admitted batches whose copies may still run
+    std::vector<hipEvent_t> ev_pool;
+    std::deque<std::unique_ptr<Request>> ready;  // uploaded, waiting for room in a group
 
     std::mutex mu;
     std::condition_variable cv_submit;  // signalled by submit for an idle run loop
@@ -312,11 +338,8 @@ struct asyrk_server {
     std::vector<int64_t> finished;     // completed ids not yet reported by take_completed
     int64_t next_id = 1;
 
-    std::vector<std::unique_ptr<Request>> active;  // progress() thread only
-    std::vector<std::unique_ptr<Request>> staged;  // uploading during the current round
-    std::deque<std::unique_ptr<Request>> ready;    // uploaded, waiting for room in a round
-    std::atomic<int64_t> n_active{0};              // active + staged + ready, for other threads
-    int64_t workers_in_use = 0;                    // R over active, staged and ready requests
+    std::atomic<int64_t> n_active{0};  // admitted and not finished, for other threads
+    int64_t workers_in_use = 0;        // R over admitted requests not yet finished
     asyrk_server_stats stats{};
 };
 
@@ -357,79 +380,86 @@ int cand_index(int pipe, int G) {
     return 0;
 }
 
-// zero d and the norms, then one sweep over every active system with G lanes
-// per row; the grid covers max_workers workers (pipelined: pipe_workers)
-hipError_t launch_zero_and_sweep(asyrk_server *s, hipStream_t st, int pipe, int G) {
-    hipLaunchKernelGGL(srv_zero_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+// zero d and the norms, then one sweep over every active system of a group
+// with G lanes per row; the grid covers max_workers workers (pipelined:
+// pipe_workers)
+hipError_t launch_zero_and_sweep(const asyrk_server *s, const RoundGroup &g, hipStream_t st, int pipe, int G) {
+    hipLaunchKernelGGL(srv_zero_kernel, dim3(kVecBlocks), dim3(256), 0, st, g.d_head, g.d_slots, g.d_norm2);
     const int64_t workers = pipe ? std::min<int64_t>(s->cfg.max_workers, s->cfg.pipe_workers) : s->cfg.max_workers;
     const int block = pipe ? 64 : 256;  // light rounds: one wave per block, spread over the CUs
     const dim3 grid((unsigned)((workers * G + block - 1) / block));
     if (pipe) {
         switch (G) {
-            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
-            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
-            case 16: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 16: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             default: return hipErrorInvalidValue;
         }
     } else {
         switch (G) {
-            case 4: hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
-            case 8: hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, dim3(block), 0, st, s->d_head, s->d_slots); break;
+            case 4: hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_kernel<8>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_finish(asyrk_server *s, hipStream_t st) {
-    hipLaunchKernelGGL(srv_axpy_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots);
-    hipLaunchKernelGGL(srv_residual_kernel, dim3(kVecBlocks), dim3(256), 0, st, s->d_head, s->d_slots, s->d_norm2);
+hipError_t launch_finish(const RoundGroup &g, hipStream_t st) {
+    hipLaunchKernelGGL(srv_axpy_kernel, dim3(kVecBlocks), dim3(256), 0, st, g.d_head, g.d_slots);
+    hipLaunchKernelGGL(srv_residual_kernel, dim3(kVecBlocks), dim3(256), 0, st, g.d_head, g.d_slots, g.d_norm2);
     return hipGetLastError();
 }
 
-hipError_t launch_round(asyrk_server *s, hipStream_t st, int pipe, int G) {
-    hipError_t e = launch_zero_and_sweep(s, st, pipe, G);
-    return e == hipSuccess ? launch_finish(s, st) : e;
+hipError_t launch_round(const asyrk_server *s, const RoundGroup &g, hipStream_t st, int pipe, int G) {
+    hipError_t e = launch_zero_and_sweep(s, g, st, pipe, G);
+    return e == hipSuccess ? launch_finish(g, st) : e;
 }
 
-// Capture the round of one sweep variant and lane width as a graph; the
-// kernels read the slot table, so one graph serves every round whatever
-// systems are active.
-hipError_t capture_round(asyrk_server *s, int pipe, int k) {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+// Capture a group's round of one sweep variant and lane width as a graph;
+// the kernels read the group's slot table, so one graph serves every round
+// whatever systems are active.
+hipError_t capture_round(const asyrk_server *s, RoundGroup &g, int pipe, int k) {
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamBeginCapture(g.st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_round(s, s->st, pipe, kLaneCands[pipe][k]);
-        e = hipStreamEndCapture(s->st, &g);
+        hipError_t le = launch_round(s, g, g.st, pipe, kLaneCands[pipe][k]);
+        e = hipStreamEndCapture(g.st, &gr);
         if (e == hipSuccess) e = le;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[pipe][k], g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.graph[pipe][k], gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
     return e;
 }
 
 void free_server(asyrk_server *s) {
     if (!s) return;
-    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (RoundGroup &g : s->grp)
+        if (g.st) (void)hipStreamSynchronize(g.st);
     if (s->cst) (void)hipStreamSynchronize(s->cst);
-    for (auto &row : s->graph)
-        for (hipGraphExec_t g : row)
-            if (g) (void)hipGraphExecDestroy(g);
+    for (RoundGroup &g : s->grp) {
+        for (auto &row : g.graph)
+            for (hipGraphExec_t x : row)
+                if (x) (void)hipGraphExecDestroy(x);
+        (void)hipFree(g.d_head);
+        (void)hipFree(g.d_slots);
+        (void)hipFree(g.d_norm2);
+        if (g.h_head) (void)hipHostFree(g.h_head);
+        if (g.h_slots) (void)hipHostFree(g.h_slots);
+        if (g.h_norm2) (void)hipHostFree(g.h_norm2);
+        if (g.e0) (void)hipEventDestroy(g.e0);
+        if (g.e1) (void)hipEventDestroy(g.e1);
+        for (hipEvent_t ev : g.te)
+            if (ev) (void)hipEventDestroy(ev);
+        if (g.st) (void)hipStreamDestroy(g.st);
+    }
     (void)hipFree(s->arena.base);
     if (s->pinned.base) (void)hipHostFree(s->pinned.base);
-    (void)hipFree(s->d_head);
-    (void)hipFree(s->d_slots);
-    (void)hipFree(s->d_norm2);
-    if (s->h_head) (void)hipHostFree(s->h_head);
-    if (s->h_slots) (void)hipHostFree(s->h_slots);
-    if (s->h_norm2) (void)hipHostFree(s->h_norm2);
-    if (s->e0) (void)hipEventDestroy(s->e0);
-    if (s->e1) (void)hipEventDestroy(s->e1);
-    if (s->st) (void)hipStreamDestroy(s->st);
+    if (s->e_ref) (void)hipEventDestroy(s->e_ref);
     if (s->cst) (void)hipStreamDestroy(s->cst);
-    if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
-    for (hipEvent_t ev : s->te)
-        if (ev) (void)hipEventDestroy(ev);
+    for (auto &u : s->uploading)
+        if (u.ev) (void)hipEventDestroy(u.ev);
+    for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
     delete s;
 }
 
@@ -470,20 +500,40 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
     s->cfg = cfg;
-    hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->arena.base, (size_t)cfg.budget_bytes);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->d_head, sizeof(TableHead));
-    if (e == hipSuccess) e = hipMalloc((void **)&s->d_slots, sizeof(SlotDesc) * cfg.max_slots);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->d_norm2, sizeof(double) * cfg.max_slots);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_head, sizeof(TableHead), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_slots, sizeof(SlotDesc) * cfg.max_slots, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_norm2, sizeof(double) * cfg.max_slots, hipHostMallocDefault);
+    s->lanes_last[0] = cfg.lanes ? cfg.lanes : 4;
+    s->lanes_last[1] = cfg.pipe_lanes ? cfg.pipe_lanes : 16;
+    s->tune_on[0] = cfg.lanes == 0;
+    s->tune_on[1] = cfg.pipe_lanes == 0 && cfg.pipe_workers > 0;
+    for (int pipe = 0; pipe < 2; ++pipe)
+        for (int b = 0; b < kBuckets; ++b) s->tuned_G[pipe][b] = s->tune_on[pipe] ? 0 : s->lanes_last[pipe];
+    hipError_t e = hipMalloc((void **)&s->arena.base, (size_t)cfg.budget_bytes);
+    for (RoundGroup &g : s->grp) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMalloc((void **)&g.d_head, sizeof(TableHead));
+        if (e == hipSuccess) e = hipMalloc((void **)&g.d_slots, sizeof(SlotDesc) * cfg.max_slots);
+        if (e == hipSuccess) e = hipMalloc((void **)&g.d_norm2, sizeof(double) * cfg.max_slots);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&g.h_head, sizeof(TableHead), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&g.h_slots, sizeof(SlotDesc) * cfg.max_slots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&g.h_norm2, sizeof(double) * cfg.max_slots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreate(&g.e0);
+        if (e == hipSuccess) e = hipEventCreate(&g.e1);
+        for (int k = 0; k < 6 && e == hipSuccess && (s->tune_on[0] || s->tune_on[1]); ++k) e = hipEventCreate(&g.te[k]);
+        if (e == hipSuccess) std::memset(g.h_head, 0, sizeof(TableHead));
+    }
     if (e == hipSuccess && cfg.pinned_bytes > 0)
         e = hipHostMalloc((void **)&s->pinned.base, (size_t)cfg.pinned_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreate(&s->e0);
-    if (e == hipSuccess) e = hipEventCreate(&s->e1);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&s->e_ref);
+    if (e == hipSuccess) e = hipEventRecord(s->e_ref, s->grp[0].st);
+    if (e == hipSuccess && cfg.use_graph) {
+        // the four phases captured per group, sweep variant and lane width in use
+        for (RoundGroup &g : s->grp)
+            for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
+                if (pipe && cfg.pipe_workers == 0) break;
+                for (int k = 0; k < kNumCands[pipe] && e == hipSuccess; ++k)
+                    if (s->tune_on[pipe] || kLaneCands[pipe][k] == s->lanes_last[pipe]) e = capture_round(s, g, pipe, k);
+            }
+    }
     if (e != hipSuccess) {
         free_server(s);
         return srv_fail(e);
@@ -493,26 +543,6 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     if (cfg.pinned_bytes > 0) {
         s->pinned.size = cfg.pinned_bytes;
         s->pinned.free_[0] = cfg.pinned_bytes;
-    }
-    s->lanes_last[0] = cfg.lanes ? cfg.lanes : 4;
-    s->lanes_last[1] = cfg.pipe_lanes ? cfg.pipe_lanes : 16;
-    s->tune_on[0] = cfg.lanes == 0;
-    s->tune_on[1] = cfg.pipe_lanes == 0 && cfg.pipe_workers > 0;
-    for (int pipe = 0; pipe < 2; ++pipe)
-        for (int b = 0; b < kBuckets; ++b) s->tuned_G[pipe][b] = s->tune_on[pipe] ? 0 : s->lanes_last[pipe];
-    for (int k = 0; k < 6 && e == hipSuccess && (s->tune_on[0] || s->tune_on[1]); ++k) e = hipEventCreate(&s->te[k]);
-    std::memset(s->h_head, 0, sizeof(TableHead));
-    if (cfg.use_graph) {
-        // the four phases captured once per sweep variant and lane width in use
-        for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
-            if (pipe && cfg.pipe_workers == 0) break;
-            for (int k = 0; k < kNumCands[pipe] && e == hipSuccess; ++k)
-                if (s->tune_on[pipe] || kLaneCands[pipe][k] == s->lanes_last[pipe]) e = capture_round(s, pipe, k);
-        }
-    }
-    if (e != hipSuccess) {
-        free_server(s);
-        return srv_fail(e);
     }
     *out = s;
     return ASYRK_OK;
@@ -602,52 +632,176 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     return ASYRK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Wait for a group's round, account for it, size the next round of every
+// request that goes on, and retire the ones that finished.
+asyrk_status collect_round(asyrk_server *s, RoundGroup &g) {
+    const asyrk_server_config &cfg = s->cfg;
+    SRV_OK(hipStreamSynchronize(g.st));
+    g.in_flight = false;
+    float ms = 0.f, t0 = 0.f, t1 = 0.f;
+    SRV_OK(hipEventElapsedTime(&ms, g.e0, g.e1));
+    SRV_OK(hipEventElapsedTime(&t0, s->e_ref, g.e0));
+    SRV_OK(hipEventElapsedTime(&t1, s->e_ref, g.e1));
+    const int pipe = g.pipe, bucket = g.bucket, nc = kNumCands[pipe];
+    if (g.tune) {
+        for (int k = 0; k < nc; ++k) {
+            float t = 0.f;
+            SRV_OK(hipEventElapsedTime(&t, g.te[2 * k], g.te[2 * k + 1]));
+            s->tune_ms[pipe][bucket][g.order[k]] += t;
+        }
+        if (++s->tune_done[pipe][bucket] == kTunePasses * nc) {
+            int best = 0;
+            for (int k = 1; k < nc; ++k)
+                if (s->tune_ms[pipe][bucket][k] < s->tune_ms[pipe][bucket][best]) best = k;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->tuned_G[pipe][bucket] = kLaneCands[pipe][best];
+        }
+    }
+    const int nact = (int)g.active.size();
+    int64_t round_rows = 0;
+    for (const auto &r : g.active) round_rows += (int64_t)r->next_sweeps * r->m;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);  // stats are read by other threads
+        // busy time: the union of the rounds' intervals on the two streams
+        const double a = std::max<double>(t0, s->busy_until_ms);
+        if (t1 > a) s->stats.gpu_seconds += (t1 - a) * 1e-3;
+        s->busy_until_ms = std::max<double>(s->busy_until_ms, t1);
+        s->stats.rounds++;
+        s->stats.row_updates += round_rows;
+        s->stats.round_workers += g.workers;
+        s->stats.round_systems += nact;
+        s->stats.pipelined_rounds += pipe;
+        s->lanes_last[pipe] = g.G;
+        s->tuned_last[pipe] = !g.tune;
+    }
+    (void)ms;
+    // ---- bookkeeping and retirement: every finished x is copied out, then one wait
+    uint8_t *base = s->arena.base;
+    std::vector<std::unique_ptr<Request>> keep, out;
+    for (int k = 0; k < nact; ++k) {
+        std::unique_ptr<Request> &r = g.active[k];
+        const int ns = r->next_sweeps;
+        r->ticket += (int64_t)ns * r->m;
+        r->sweeps += ns;
+        r->rounds++;
+        const double nr = g.h_norm2[k];
+        const double prev = r->rel;
+        r->rel = r->b_norm2 > 0 ? std::sqrt(nr / r->b_norm2) : std::sqrt(nr);
+        const bool conv = r->rel <= r->tol;
+        const bool bad = !std::isfinite(r->rel);
+        if (conv || bad || r->rounds >= cfg.max_rounds) {
+            r->status = conv ? ASYRK_OK : (bad ? ASYRK_ERR_DIVERGED : ASYRK_ERR_NOT_CONVERGED);
+            r->x.resize(r->n);
+            SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, g.st));
+            out.push_back(std::move(r));
+        } else {
+            // Size the next round from this one: RK contracts the residual by
+            // a roughly constant factor per sweep, so the sweeps still needed
+            // are log(tol / rel) / log(rho), rho the factor measured over the
+            // round just run; one more for safety, at most inner_sweeps.
+            int nxt = cfg.inner_sweeps;
+            if (!cfg.fixed_rounds && prev > 0.0 && r->rel > 0.0 && r->rel < prev) {
+                const double rho = std::pow(r->rel / prev, 1.0 / ns);
+                const double need = std::log(r->tol / r->rel) / std::log(rho);
+                if (std::isfinite(need))
+                    nxt = (int)std::min<double>(cfg.inner_sweeps, std::max(1.0, std::ceil(need) + 1.0));
+            }
+            r->next_sweeps = nxt;
+            keep.push_back(std::move(r));
+        }
+    }
+    g.active.swap(keep);
+    if (!out.empty()) {
+        SRV_OK(hipStreamSynchronize(g.st));
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : out) {
+            r->t_done = t;
+            s->workers_in_use -= r->R;
+            s->arena.release(r->off_rec, r->bytes);
+            r->pack = SetupResult();  // drop the packed copy
+            s->stats.completed++;
+            s->finished.push_back(r->id);
+            s->done[r->id] = std::move(r);
+        }
+    }
+    return ASYRK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
     if (!s) return ASYRK_ERR_INVALID_ARG;
     const asyrk_server_config &cfg = s->cfg;
-    // ---- the requests staged by the previous call uploaded on the copy
-    // stream while that call's round computed; they wait in `ready` and join
-    // the rounds, oldest first, while the active workers fit max_workers
-    if (!s->staged.empty()) {
-        SRV_OK(hipEventSynchronize(s->ev_copy));
+    // The two groups take turns: collect this group's previous round while
+    // the other group's round computes, admit into this group, launch its
+    // next round.
+    RoundGroup &g = s->grp[s->next_group];
+    RoundGroup &other = s->grp[s->next_group ^ 1];
+    s->next_group ^= 1;
+    if (g.in_flight) {
+        asyrk_status rc = collect_round(s, g);
+        if (rc) return rc;
+    }
+    // ---- uploads that have finished make their requests ready; when the GPU
+    // would otherwise have nothing to do, wait for the oldest batch
+    using Upload = asyrk_server::Upload;
+    auto finish_upload = [&](Upload &u) {
         std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &r : s->staged) {
+        for (auto &r : u.reqs) {
             if (r->pin_off >= 0) {
                 s->pinned.release(r->pin_off, r->pin_bytes);
                 r->pin_off = -1;
             }
             s->ready.push_back(std::move(r));
         }
-        s->staged.clear();
+        s->ev_pool.push_back(u.ev);
+    };
+    while (!s->uploading.empty()) {
+        Upload &u = s->uploading.front();
+        const hipError_t q = hipEventQuery(u.ev);
+        if (q == hipErrorNotReady) {
+            if (!g.active.empty() || other.in_flight || !s->ready.empty()) break;
+            SRV_OK(hipEventSynchronize(u.ev));
+        } else if (q != hipSuccess) {
+            return srv_fail(q);
+        }
+        finish_upload(u);
+        s->uploading.pop_front();
     }
-    int64_t active_workers = 0;
-    for (const auto &r : s->active) active_workers += r->R;
-    while (!s->ready.empty() && active_workers + s->ready.front()->R <= cfg.max_workers) {
-        active_workers += s->ready.front()->R;
-        s->active.push_back(std::move(s->ready.front()));
+    // ---- ready requests join this group: a round's worker grid covers
+    // max_workers, and both groups together hold at most one and a half times
+    // that
+    int64_t g_workers = 0, o_workers = 0;
+    for (const auto &r : g.active) g_workers += r->R;
+    for (const auto &r : other.active) o_workers += r->R;
+    const int64_t total_cap = cfg.max_workers + cfg.max_workers / 2;
+    while (!s->ready.empty() && (int64_t)g.active.size() < cfg.max_slots) {
+        const int64_t R = s->ready.front()->R;
+        if (g_workers + R > cfg.max_workers || g_workers + o_workers + R > total_cap) break;
+        g_workers += R;
+        g.active.push_back(std::move(s->ready.front()));
         s->ready.pop_front();
     }
-    // ---- admit.  While the active systems keep the GPU busy (more workers
-    // than a pipelined round takes), new requests upload during this round
-    // and join a later one; requests may then take up to half of max_workers
-    // beyond it, so that uploads run ahead of the rounds instead of holding
-    // back workers of the running set.  Otherwise this round waits for their
-    // upload.
-    const bool defer = active_workers > cfg.pipe_workers && active_workers > 0;
-    const int64_t admit_limit = cfg.max_workers + (defer ? cfg.max_workers / 2 : 0);
-    bool admitted = false;
+    // ---- admit: uploads on the copy stream, for a later call to pick up; the
+    // admitted requests may hold up to half of max_workers beyond the two
+    // groups' active workers, so that uploads run ahead of the rounds
+    Upload batch{};
     for (;;) {
         std::unique_ptr<Request> r;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->queue.empty() ||
-                (int64_t)(s->active.size() + s->staged.size() + s->ready.size()) >= cfg.max_slots)
-                break;
+            if (s->queue.empty()) break;
             Request &f = *s->queue.front();
             int64_t R = (int64_t)std::floor(f.fro2 / (2.0 * M_E * f.lam));
             R = std::max<int64_t>(1, std::min<int64_t>(R, cfg.max_workers / 4));
-            if (s->workers_in_use + R > admit_limit) break;
-            if (!defer && active_workers + R > cfg.max_workers) break;
+            if (s->workers_in_use + R > 2 * cfg.max_workers) break;
             f.R = R;
             const int64_t off = s->arena.alloc(f.bytes);
             if (off < 0) break;  // wait for memory
@@ -684,186 +838,118 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
         q.t_admit = now_s();
         q.rel = q.b_norm2 > 0 ? 1.0 : 0.0;
         q.next_sweeps = cfg.inner_sweeps;
+        batch.reqs.push_back(std::move(r));
+        std::lock_guard<std::mutex> lk(s->mu);  // stats are read by other threads
         s->workers_in_use += q.R;
-        if (!defer) active_workers += q.R;
-        (defer ? s->staged : s->active).push_back(std::move(r));
-        {
-            std::lock_guard<std::mutex> lk(s->mu);  // stats are read by other threads
-            s->stats.admitted++;
+        s->stats.admitted++;
+    }
+    if (!batch.reqs.empty()) {
+        if (s->ev_pool.empty()) {
+            hipEvent_t ev = nullptr;
+            SRV_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            s->ev_pool.push_back(ev);
         }
-        admitted = true;
-    }
-    if (admitted) {
-        SRV_OK(hipEventRecord(s->ev_copy, s->cst));
-        if (!defer) SRV_OK(hipStreamWaitEvent(s->st, s->ev_copy, 0));
-    }
-    s->n_active.store((int64_t)(s->active.size() + s->staged.size() + s->ready.size()));
-    if (s->active.empty()) {
-        if (n_active) *n_active = (int32_t)(s->staged.size() + s->ready.size());
-        if (n_queued) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            *n_queued = (int32_t)s->queue.size();
-        }
-        return ASYRK_OK;
-    }
-    // ---- slot table
-    TableHead &h = *s->h_head;
-    h.nact = (int32_t)s->active.size();
-    int64_t wo = 0, ro = 0, co = 0;
-    uint8_t *base = s->arena.base;
-    for (int k = 0; k < h.nact; ++k) {
-        Request &q = *s->active[k];
-        SlotDesc &d = s->h_slots[k];
-        d.rows.rec = base + q.off_rec;
-        d.rows.loc = q.pack.loc.empty() ? nullptr : reinterpret_cast<const RowLoc *>(base + q.off_loc);
-        d.rows.stride = q.pack.stride;
-        d.rows.fixed_nnz = (int32_t)q.pack.fixed_nnz;
-        d.rows.m = (int32_t)q.m;
-        d.b64 = reinterpret_cast<double *>(base + q.off_b);
-        d.x64 = reinterpret_cast<double *>(base + q.off_x);
-        d.d = reinterpret_cast<double *>(base + q.off_d);
-        d.side = reinterpret_cast<double2 *>(base + q.off_side);
-        d.n = q.n;
-        d.R = q.R;
-        d.w_off = wo;
-        d.row_off = ro;
-        d.col_off = co;
-        d.t_begin = q.ticket;
-        d.t_end = q.ticket + (int64_t)q.next_sweeps * q.m;
-        d.key0 = (uint32_t)q.seed;
-        d.key1 = (uint32_t)(q.seed >> 32);
-        d.gamma = cfg.gamma;
-        d.xshift = stride_shift(q.dstride, 8);
-        d.pad = 0;
-        wo += q.R;
-        ro += q.m;
-        co += q.n;
-    }
-    // the captured grids cover max_workers workers (pipelined: pipe_workers)
-    if (wo > cfg.max_workers) {
-        g_srv_last = "internal: active workers exceed max_workers";
-        return ASYRK_ERR_DEVICE;
-    }
-    h.total_workers = wo;
-    h.total_rows = ro;
-    h.total_cols = co;
-    SRV_OK(hipMemcpyAsync(s->d_head, s->h_head, sizeof(TableHead), hipMemcpyHostToDevice, s->st));
-    SRV_OK(hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(SlotDesc) * h.nact, hipMemcpyHostToDevice, s->st));
-    // ---- run one round
-    SRV_OK(hipEventRecord(s->e0, s->st));
-    const int pipe = h.total_workers <= cfg.pipe_workers ? 1 : 0;
-    const int bucket = pipe ? load_bucket(h.total_workers, cfg.pipe_workers / 8) : load_bucket(h.total_workers, cfg.pipe_workers);
-    const bool tune = s->tuned_G[pipe][bucket] == 0;
-    const int G = tune ? 0 : s->tuned_G[pipe][bucket];
-    int order[3] = {0, 0, 0};
-    const int nc = kNumCands[pipe];
-    if (tune) {
-        for (int k = 0; k < nc; ++k) order[k] = (s->tune_done[pipe][bucket] + k) % nc;
-        // every candidate sweeps this round's systems from d = 0, timed; the
-        // last one's sweep is the round's (the order rotates so that each
-        // candidate also runs first, on cold caches)
-        for (int k = 0; k < nc; ++k) {
-            SRV_OK(hipEventRecord(s->te[2 * k], s->st));
-            SRV_OK(launch_zero_and_sweep(s, s->st, pipe, kLaneCands[pipe][order[k]]));
-            SRV_OK(hipEventRecord(s->te[2 * k + 1], s->st));
-        }
-        SRV_OK(launch_finish(s, s->st));
-    } else if (s->graph[pipe][cand_index(pipe, G)]) {
-        SRV_OK(hipGraphLaunch(s->graph[pipe][cand_index(pipe, G)], s->st));
-    } else {
-        SRV_OK(launch_round(s, s->st, pipe, G));
-    }
-    SRV_OK(hipEventRecord(s->e1, s->st));
-    SRV_OK(hipMemcpyAsync(s->h_norm2, s->d_norm2, sizeof(double) * h.nact, hipMemcpyDeviceToHost, s->st));
-    SRV_OK(hipStreamSynchronize(s->st));
-    float ms = 0.f;
-    SRV_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
-    {
-        std::lock_guard<std::mutex> lk(s->mu);  // read by stats_get
-        s->lanes_last[pipe] = tune ? kLaneCands[pipe][order[nc - 1]] : G;
-        s->tuned_last[pipe] = !tune;
-    }
-    if (tune) {
-        for (int k = 0; k < nc; ++k) {
-            float t = 0.f;
-            SRV_OK(hipEventElapsedTime(&t, s->te[2 * k], s->te[2 * k + 1]));
-            s->tune_ms[pipe][bucket][order[k]] += t;
-        }
-        if (++s->tune_done[pipe][bucket] == kTunePasses * nc) {
-            int best = 0;
-            for (int k = 1; k < nc; ++k)
-                if (s->tune_ms[pipe][bucket][k] < s->tune_ms[pipe][bucket][best]) best = k;
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->tuned_G[pipe][bucket] = kLaneCands[pipe][best];
-        }
-    }
-    int64_t round_rows = 0;
-    for (int k = 0; k < h.nact; ++k) round_rows += (int64_t)s->active[k]->next_sweeps * s->active[k]->m;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &r : s->active)
-            if (r->pin_off >= 0) {
-                s->pinned.release(r->pin_off, r->pin_bytes);
-                r->pin_off = -1;
+        batch.ev = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        SRV_OK(hipEventRecord(batch.ev, s->cst));
+        s->uploading.push_back(std::move(batch));
+        if (g.active.empty() && !other.in_flight) {
+            // nothing else for the GPU: this group's round takes the batch now
+            Upload &u = s->uploading.back();
+            SRV_OK(hipEventSynchronize(u.ev));
+            // (older batches finished before it on the same stream)
+            while (!s->uploading.empty()) {
+                finish_upload(s->uploading.front());
+                s->uploading.pop_front();
             }
-        s->stats.gpu_seconds += ms * 1e-3;
-        s->stats.rounds++;
-        s->stats.row_updates += round_rows;
-        s->stats.round_workers += h.total_workers;
-        s->stats.round_systems += h.nact;
-        s->stats.pipelined_rounds += pipe;
+            while (!s->ready.empty() && (int64_t)g.active.size() < cfg.max_slots) {
+                const int64_t R = s->ready.front()->R;
+                if (g_workers + R > cfg.max_workers || g_workers + o_workers + R > total_cap) break;
+                g_workers += R;
+                g.active.push_back(std::move(s->ready.front()));
+                s->ready.pop_front();
+            }
+        }
     }
-    // ---- bookkeeping and retirement: every finished x is copied out, then one wait
-    std::vector<std::unique_ptr<Request>> keep, out;
-    for (int k = 0; k < h.nact; ++k) {
-        std::unique_ptr<Request> &r = s->active[k];
-        const int ns = r->next_sweeps;
-        r->ticket += (int64_t)ns * r->m;
-        r->sweeps += ns;
-        r->rounds++;
-        const double nr = s->h_norm2[k];
-        const double prev = r->rel;
-        r->rel = r->b_norm2 > 0 ? std::sqrt(nr / r->b_norm2) : std::sqrt(nr);
-        const bool conv = r->rel <= r->tol;
-        const bool bad = !std::isfinite(r->rel);
-        if (conv || bad || r->rounds >= cfg.max_rounds) {
-            r->status = conv ? ASYRK_OK : (bad ? ASYRK_ERR_DIVERGED : ASYRK_ERR_NOT_CONVERGED);
-            r->x.resize(r->n);
-            SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, s->st));
-            out.push_back(std::move(r));
+    if (!g.active.empty()) {
+        // ---- slot table
+        TableHead &h = *g.h_head;
+        h.nact = (int32_t)g.active.size();
+        int64_t wo = 0, ro = 0, co = 0;
+        uint8_t *base = s->arena.base;
+        for (int k = 0; k < h.nact; ++k) {
+            Request &q = *g.active[k];
+            SlotDesc &d = g.h_slots[k];
+            d.rows.rec = base + q.off_rec;
+            d.rows.loc = q.pack.loc.empty() ? nullptr : reinterpret_cast<const RowLoc *>(base + q.off_loc);
+            d.rows.stride = q.pack.stride;
+            d.rows.fixed_nnz = (int32_t)q.pack.fixed_nnz;
+            d.rows.m = (int32_t)q.m;
+            d.b64 = reinterpret_cast<double *>(base + q.off_b);
+            d.x64 = reinterpret_cast<double *>(base + q.off_x);
+            d.d = reinterpret_cast<double *>(base + q.off_d);
+            d.side = reinterpret_cast<double2 *>(base + q.off_side);
+            d.n = q.n;
+            d.R = q.R;
+            d.w_off = wo;
+            d.row_off = ro;
+            d.col_off = co;
+            d.t_begin = q.ticket;
+            d.t_end = q.ticket + (int64_t)q.next_sweeps * q.m;
+            d.key0 = (uint32_t)q.seed;
+            d.key1 = (uint32_t)(q.seed >> 32);
+            d.gamma = cfg.gamma;
+            d.xshift = stride_shift(q.dstride, 8);
+            d.pad = 0;
+            wo += q.R;
+            ro += q.m;
+            co += q.n;
+        }
+        // the captured grids cover max_workers workers (pipelined: pipe_workers)
+        if (wo > cfg.max_workers) {
+            g_srv_last = "internal: active workers exceed max_workers";
+            return ASYRK_ERR_DEVICE;
+        }
+        h.total_workers = wo;
+        h.total_rows = ro;
+        h.total_cols = co;
+        SRV_OK(hipMemcpyAsync(g.d_head, g.h_head, sizeof(TableHead), hipMemcpyHostToDevice, g.st));
+        SRV_OK(hipMemcpyAsync(g.d_slots, g.h_slots, sizeof(SlotDesc) * h.nact, hipMemcpyHostToDevice, g.st));
+        // ---- launch the round
+        g.pipe = h.total_workers <= cfg.pipe_workers ? 1 : 0;
+        g.bucket = g.pipe ? load_bucket(h.total_workers, cfg.pipe_workers / 8) : load_bucket(h.total_workers, cfg.pipe_workers);
+        g.tune = s->tuned_G[g.pipe][g.bucket] == 0;
+        g.workers = wo;
+        const int nc = kNumCands[g.pipe];
+        SRV_OK(hipEventRecord(g.e0, g.st));
+        if (g.tune) {
+            // every candidate sweeps this round's systems from d = 0, timed; the
+            // last one's sweep is the round's (the order rotates so that each
+            // candidate also runs first, on cold caches)
+            for (int k = 0; k < nc; ++k) g.order[k] = (s->tune_done[g.pipe][g.bucket] + k) % nc;
+            for (int k = 0; k < nc; ++k) {
+                SRV_OK(hipEventRecord(g.te[2 * k], g.st));
+                SRV_OK(launch_zero_and_sweep(s, g, g.st, g.pipe, kLaneCands[g.pipe][g.order[k]]));
+                SRV_OK(hipEventRecord(g.te[2 * k + 1], g.st));
+            }
+            SRV_OK(launch_finish(g, g.st));
+            g.G = kLaneCands[g.pipe][g.order[nc - 1]];
         } else {
-            // Size the next round from this one: RK contracts the residual by
-            // a roughly constant factor per sweep, so the sweeps still needed
-            // are log(tol / rel) / log(rho), rho the factor measured over the
-            // round just run; one more for safety, at most inner_sweeps.
-            int nxt = cfg.inner_sweeps;
-            if (!cfg.fixed_rounds && prev > 0.0 && r->rel > 0.0 && r->rel < prev) {
-                const double rho = std::pow(r->rel / prev, 1.0 / ns);
-                const double need = std::log(r->tol / r->rel) / std::log(rho);
-                if (std::isfinite(need))
-                    nxt = (int)std::min<double>(cfg.inner_sweeps, std::max(1.0, std::ceil(need) + 1.0));
-            }
-            r->next_sweeps = nxt;
-            keep.push_back(std::move(r));
+            g.G = s->tuned_G[g.pipe][g.bucket];
+            hipGraphExec_t gx = g.graph[g.pipe][cand_index(g.pipe, g.G)];
+            if (gx)
+                SRV_OK(hipGraphLaunch(gx, g.st));
+            else
+                SRV_OK(launch_round(s, g, g.st, g.pipe, g.G));
         }
+        SRV_OK(hipEventRecord(g.e1, g.st));
+        SRV_OK(hipMemcpyAsync(g.h_norm2, g.d_norm2, sizeof(double) * h.nact, hipMemcpyDeviceToHost, g.st));
+        g.in_flight = true;
     }
-    s->active.swap(keep);
-    s->n_active.store((int64_t)(s->active.size() + s->staged.size() + s->ready.size()));
-    if (!out.empty()) {
-        SRV_OK(hipStreamSynchronize(s->st));
-        const double t = now_s();
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &r : out) {
-            r->t_done = t;
-            s->workers_in_use -= r->R;
-            s->arena.release(r->off_rec, r->bytes);
-            r->pack = SetupResult();  // drop the packed copy
-            s->stats.completed++;
-            s->finished.push_back(r->id);
-            s->done[r->id] = std::move(r);
-        }
-    }
-    if (n_active) *n_active = (int32_t)(s->active.size() + s->staged.size() + s->ready.size());
+    int64_t act = (int64_t)(s->grp[0].active.size() + s->grp[1].active.size() + s->ready.size());
+    for (const auto &u : s->uploading) act += (int64_t)u.reqs.size();
+    s->n_active.store(act);
+    if (n_active) *n_active = (int32_t)act;
     if (n_queued) {
         std::lock_guard<std::mutex> lk(s->mu);
         *n_queued = (int32_t)s->queue.size();
