@@ -360,9 +360,9 @@ typedef struct asyrk_server_config {
     int32_t pipe_workers;  /* rounds whose active systems hold at most this many row workers
                               run the pipelined worker loop (see asyrk_solve_params.pipeline),
                               default 8192; 0 = never */
-    int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8 or 16, default 16 (fewer
+    int32_t pipe_lanes;    /* lanes per row in those rounds: 4, 8, 16 or 32, default 16 (fewer
                               entries per lane shorten each latency-bound ticket); 0 = tune
-                              online among 4, 8, 16 as for lanes, with the buckets below
+                              online among 4, 8, 16, 32 as for lanes, with the buckets below
                               pipe_workers / 4, below pipe_workers / 2, below pipe_workers,
                               and pipe_workers */
     int32_t fixed_rounds;  /* 0 (default): after each round a request's next round runs the

@@ -51,8 +51,8 @@ namespace {
 constexpr int kVecBlocks = 2048;     // grid of the flat vector/residual kernels
 // Candidate lane widths of the plain and the pipelined sweep, and the number
 // of load buckets the online choice keeps apart.
-constexpr int kLaneCands[2][3] = {{4, 8, 0}, {4, 8, 16}};
-constexpr int kNumCands[2] = {2, 3};
+constexpr int kLaneCands[2][4] = {{4, 8, 0, 0}, {4, 8, 16, 32}};
+constexpr int kNumCands[2] = {2, 4};
 constexpr int kBuckets = 4;
 
 struct SlotDesc {
@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, cons
     }
 }
 
-// G lanes per row with 16 / G units per lane: rows of up to 64 FP32 entries
+// G lanes per row with 16 / G units per lane (one for G = 32, half of the
+// lanes idle on the longest rows): rows of up to 64 FP32 entries
 // stay in registers.  PIPE: the pipelined worker loop, for rounds with few
 // workers (latency-bound); the plain loop saturates the atomic unit better
 // when many are active.
@@ -120,11 +121,11 @@ __device__ __forceinline__ void srv_sweep_body(const TableHead *th, const SlotDe
     const SlotDesc d = sl[s];  // a copy: the scatter cannot be taken to alias it
     const int64_t w = worker - d.w_off;
     if constexpr (PIPE) {
-        run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.xshift, d.side, d.t_begin + w, d.t_end, d.R,
+        run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, (G < 16 ? 16 / G : 1)>(d.rows, d.d, d.xshift, d.side, d.t_begin + w, d.t_end, d.R,
                                                                0u, d.key0, d.key1, 0, d.gamma, gl);
     } else {
         for (int64_t j = d.t_begin + w; j < d.t_end; j += d.R)
-            process_ticket<ASYRK_F32, ASYRK_F64, G, 16 / G>(d.rows, d.d, d.xshift, d.side, j, 0u, d.key0, d.key1, 0, 0,
+            process_ticket<ASYRK_F32, ASYRK_F64, G, (G < 16 ? 16 / G : 1)>(d.rows, d.d, d.xshift, d.side, j, 0u, d.key0, d.key1, 0, 0,
                                                              d.gamma, gl, 0);
     }
 }
@@ -290,15 +291,15 @@ struct RoundGroup {
     TableHead *h_head = nullptr;   // pinned
     SlotDesc *h_slots = nullptr;   // pinned
     double *h_norm2 = nullptr;     // pinned
-    hipGraphExec_t graph[2][3] = {};  // per loop (plain / pipelined) and candidate lane width
+    hipGraphExec_t graph[2][4] = {};  // per loop (plain / pipelined) and candidate lane width
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipEvent_t te[6] = {};         // start / end of each candidate's sweep (lane tuning)
+    hipEvent_t te[8] = {};         // start / end of each candidate's sweep (lane tuning)
     std::vector<std::unique_ptr<Request>> active;
     // the round in flight (launched, not yet collected)
     bool in_flight = false;
     int pipe = 0, bucket = 0, G = 0;
     bool tune = false;
-    int order[3] = {0, 0, 0};
+    int order[4] = {0, 0, 0, 0};
     int64_t workers = 0;
 };
 
@@ -320,7 +321,7 @@ struct asyrk_server {
     bool tune_on[2] = {false, false};
     int tuned_G[2][kBuckets] = {};   // 0 while the bucket is being tuned
     int tune_done[2][kBuckets] = {};
-    double tune_ms[2][kBuckets][3] = {};
+    double tune_ms[2][kBuckets][4] = {};
     hipStream_t cst = nullptr;     // admission uploads
     struct Upload {
         hipEvent_t ev;             // recorded on cst after the batch's copies
@@ -393,6 +394,7 @@ hipError_t launch_zero_and_sweep(const asyrk_server *s, const RoundGroup &g, hip
             case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             case 16: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 32: hipLaunchKernelGGL(srv_sweep_pipe_kernel<32>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -494,7 +496,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
     if (cfg.budget_bytes < (1 << 20) || cfg.pinned_bytes < 0 || cfg.max_slots < 1 || cfg.max_slots > 65536 || cfg.max_workers < 64 ||
         cfg.max_workers > ((int64_t)1 << 24) || cfg.inner_sweeps < 1 || cfg.max_rounds < 1 ||
         !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 0 && cfg.lanes != 4 && cfg.lanes != 8) ||
-        cfg.pipe_workers < 0 || (cfg.pipe_lanes != 0 && cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16) ||
+        cfg.pipe_workers < 0 || (cfg.pipe_lanes != 0 && cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16 &&
+                                  cfg.pipe_lanes != 32) ||
         (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1))
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
@@ -517,7 +520,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         if (e == hipSuccess) e = hipHostMalloc((void **)&g.h_norm2, sizeof(double) * cfg.max_slots, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreate(&g.e0);
         if (e == hipSuccess) e = hipEventCreate(&g.e1);
-        for (int k = 0; k < 6 && e == hipSuccess && (s->tune_on[0] || s->tune_on[1]); ++k) e = hipEventCreate(&g.te[k]);
+        for (int k = 0; k < 8 && e == hipSuccess && (s->tune_on[0] || s->tune_on[1]); ++k) e = hipEventCreate(&g.te[k]);
         if (e == hipSuccess) std::memset(g.h_head, 0, sizeof(TableHead));
     }
     if (e == hipSuccess && cfg.pinned_bytes > 0)

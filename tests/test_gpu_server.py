@@ -163,7 +163,8 @@ def test_concurrent_submitters_while_rounds_run(pipe_workers):
         assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
 
 
-@pytest.mark.parametrize("pipe_workers,pipe_lanes", [(0, 8), (1 << 24, 4), (1 << 24, 8), (1 << 24, 16)])
+@pytest.mark.parametrize("pipe_workers,pipe_lanes", [(0, 8), (1 << 24, 4), (1 << 24, 8), (1 << 24, 16),
+                                                     (1 << 24, 32)])
 @pytest.mark.parametrize("lanes", [4, 8])
 def test_lane_widths_and_completion_list(lanes, pipe_workers, pipe_lanes):
     """Every lane width and worker loop (plain: pipe_workers = 0; pipelined:
@@ -365,7 +366,7 @@ def test_online_lane_tuning(use_graph):
         # the systems split over the two round groups, so rounds fall in one
         # or more load buckets; at least one has finished tuning
         assert st["buckets_untuned"] <= 7, st
-        assert st["lanes"] in (4, 8) and st["pipe_lanes"] in (4, 8, 16)
+        assert st["lanes"] in (4, 8) and st["pipe_lanes"] in (4, 8, 16, 32)
         more = _systems(range(906, 908), [30000, 1500])
         for s, r in zip(more, _run_all(srv, more)):
             _check(s, r)
