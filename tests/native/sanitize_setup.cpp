@@ -105,6 +105,29 @@ int main() {
                   ASYRK_ERR_INVALID_ARG);
         }
     }
+    // systems large enough for the threaded validation and record writing
+    // (one host thread per 4096 rows), valid and with invalid entries that
+    // the concurrent column pass must not follow out of range
+    for (int trial = 0; trial < 3; ++trial) {
+        const int64_t m = 20000 + 4000 * trial, n = 3000;
+        Sys big = make(g, m, n, 1, 40);
+        for (int vk : vks) {
+            SetupResult r;
+            CHECK(validate_system(m, n, big.rp.data(), big.col.data(), big.vals(vk), vk, big.b.data(), r) == ASYRK_OK);
+            CHECK(pack_records(m, big.rp.data(), big.col.data(), big.vals(vk), vk, big.b.data(), r) == ASYRK_OK);
+            CHECK(r.nnz == big.rp[m] && r.nu >= 1 && r.mu >= 1 && r.max_col_norm2 > 0.0);
+        }
+        for (int bad = 0; bad < 3; ++bad) {
+            Sys q = big;
+            const int64_t k = q.rp[m / 2 + bad];
+            if (bad == 0) q.col[k] = (int32_t)n + 5;      // out of range
+            if (bad == 1) q.col[k] = -7;                  // negative
+            if (bad == 2) q.v64[k] = std::nan("");        // not finite
+            SetupResult rr;
+            CHECK(validate_system(m, n, q.rp.data(), q.col.data(), q.vals(ASYRK_F64), ASYRK_F64, q.b.data(), rr) ==
+                  ASYRK_ERR_INVALID_ARG);
+        }
+    }
     // invalid inputs
     Sys s = make(g, 50, 40, 2, 6);
     SetupResult r;

@@ -45,6 +45,27 @@ def test_setup_under_sanitizers(tmp_path):
          exe, "0 failed checks")
 
 
+def test_setup_under_thread_sanitizer(tmp_path):
+    """The threaded validation (row scans beside the in-order column pass)
+    and record writing under ThreadSanitizer: no data race."""
+    probe = tmp_path / "p.cpp"
+    probe.write_text("int main(){return 0;}\n")
+    if not shutil.which("g++") or subprocess.run(["g++", "-fsanitize=thread", str(probe), "-o",
+                                                  str(tmp_path / "p")], capture_output=True).returncode:
+        pytest.skip("ThreadSanitizer runtime not available")
+    exe = tmp_path / "tsan_setup"
+    csrc = ROOT / "paper_1401_4780_amd" / "csrc"
+    b = subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-ffp-contract=off", "-pthread",
+                        f"-I{csrc}", str(NATIVE / "sanitize_setup.cpp"), str(csrc / "setup.cpp"), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert b.returncode == 0, b.stderr[-3000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600,
+                       env={"TSAN_OPTIONS": "halt_on_error=1", "PATH": "/usr/bin:/bin"})
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert "0 failed checks" in r.stdout
+
+
 def test_oracle_under_sanitizers(tmp_path):
     if not _have_sanitizers(tmp_path):
         pytest.skip("gcc sanitizer runtime not available")
