@@ -379,7 +379,7 @@ def run_skewed(args):
             "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
 
 
-def run_serving(args):
+def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
     """Poisson stream of independent systems (m log-uniform in [1k, 200k],
     n = m/4, 8..64 entries per row, FP32 values, FP64 refinement to 1e-8
     relative residual) through the continuous-batching server; arrival rate
@@ -393,7 +393,6 @@ def run_serving(args):
 
     tol = 1e-8
     n_req = args.requests
-    rates = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
     specs = synth.serving_specs(n_req * (len(rates) + 1), seed=4)
     pool = ThreadPoolExecutor(16)
 
@@ -483,18 +482,20 @@ def run_serving(args):
     srv.close()
 
     # baseline: the same kind of requests one at a time, plain FP64 sweeps
-    dev = torch.device("cuda:0")
-    nb = min(40, n_req)
-    base_sys = list(pool.map(gen, range(nb)))
-    t0 = time.perf_counter()
-    for s in base_sys:
-        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
-        sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n)
-        x = torch.zeros(s.n, dtype=torch.float64, device=dev)
-        sysm.solve(x, 1.0, 400, 1, tol=tol, iter_dtype="f64")
-        sysm.close()
-    torch.cuda.synchronize()
-    base = nb / (time.perf_counter() - t0)
+    base = None
+    if baseline:
+        dev = torch.device("cuda:0")
+        nb = min(40, n_req)
+        base_sys = list(pool.map(gen, range(nb)))
+        t0 = time.perf_counter()
+        for s in base_sys:
+            d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+            sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n)
+            x = torch.zeros(s.n, dtype=torch.float64, device=dev)
+            sysm.solve(x, 1.0, 400, 1, tol=tol, iter_dtype="f64")
+            sysm.close()
+        torch.cuda.synchronize()
+        base = nb / (time.perf_counter() - t0)
     return {"metric": "solves/s and p50/p99 solve latency (serving)", "value": sat["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
             "vs_baseline": None, "data": "synthetic", "dtype": "f64",
@@ -507,7 +508,7 @@ def run_serving(args):
                        "lanes_in_use": [st["lanes"], st["pipe_lanes"]]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
-            "speedup_vs_sequential_fp64": sat["solves_per_s"] / base,
+            "speedup_vs_sequential_fp64": sat["solves_per_s"] / base if base else None,
             "server_stats": st}
 
 
@@ -533,6 +534,8 @@ def main():
                     help="serving: pipelined rounds up to this many workers (-1: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="c2: skip the short serving leg (150 requests at saturation and at a quarter of it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (a single system's "
@@ -541,7 +544,23 @@ def main():
         sys.exit(2)
     fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed,
           "serving": run_serving}[args.workload]
-    print(json.dumps(fn(args)), flush=True)
+    result = fn(args)
+    if args.workload == "c2" and not args.no_serving:
+        # the serving stream in brief, so that one default run reports both
+        # halves of the metric (the full sweep: --workload serving)
+        import copy
+        sargs = copy.copy(args)
+        sargs.requests = 150
+        sv = run_serving(sargs, rates=(0.25, 1.0), baseline=False)
+        result["serving"] = {
+            "workload": sv["config"]["workload"], "requests_per_point": 150,
+            "solves_per_s_saturation": sv["value"],
+            "latency_s_p50_p99": {f"load {k}": [v["latency_s_p50"], v["latency_s_p99"]]
+                                  for k, v in sv["by_load"].items()},
+            "failed": sv["saturation"]["failed"] + sum(v["failed"] for v in sv["by_load"].values()),
+        }
+        log(f"serving leg: {result['serving']}")
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":
