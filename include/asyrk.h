@@ -328,10 +328,13 @@ asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_
  * ||b - A x|| <= tol ||b|| by asynchronous sweeps (row workers bounded by the
  * system's own Corollary 1 limit; FP64 correction and FP64 atomics over the
  * FP32 values) inside an FP64 refinement loop (r = b - A x, d from A d = r,
- * x += d).  One progress() call runs one
- * round over every active system in one packed launch per phase; requests
- * that arrive meanwhile are admitted as slots, workers and device memory
- * free up.  A request's result does not depend on what else is in the batch
+ * x += d).  The active systems form two groups whose rounds alternate on
+ * two streams; one progress() call collects one group's previous round
+ * (retiring finished requests), lets uploaded requests join it, admits
+ * queued requests (uploads on a copy stream) and launches the group's next
+ * round, one packed launch per phase over its systems, while the other
+ * group's round computes.  Requests that arrive meanwhile are admitted as
+ * slots, workers and device memory free up.  A request's result does not depend on what else is in the batch
  * beyond the nondeterminism of asynchronous execution.
  * Threads: submit/poll/stats may be called from any thread; progress from one
  * thread at a time.
@@ -340,10 +343,11 @@ typedef struct asyrk_server asyrk_server;
 
 typedef struct asyrk_server_config {
     int64_t budget_bytes;  /* device memory for resident systems (one arena), default 64 GiB */
-    int32_t max_slots;     /* systems active at once, default 1024 */
+    int32_t max_slots;     /* systems active at once in each round group, default 1024 */
     int32_t inner_sweeps;  /* sweeps per round (refinement inner solve), default 8; a request's
                               later rounds may run fewer (see fixed_rounds) */
-    int64_t max_workers;   /* row workers over all active systems, default 65536 */
+    int64_t max_workers;   /* row workers of one group's round, default 65536 (both groups
+                              together: 1.5 times that; admitted, uploading: twice that) */
     int32_t max_rounds;    /* per request; then NOT_CONVERGED, default 60 */
     int32_t use_graph;     /* 1: the round runs as one captured hipGraph, default 1 */
     double gamma;          /* step length in (0, 2), default 1 */
@@ -383,7 +387,9 @@ typedef struct asyrk_request_stats {
 
 typedef struct asyrk_server_stats {
     int64_t submitted, admitted, completed, active, queued, rounds, row_updates, arena_used;
-    double gpu_seconds;    /* time of the rounds on the GPU (HIP events) */
+                           /* active: admitted and not finished (uploading, ready or in a group) */
+    double gpu_seconds;    /* time the GPU spent in rounds: the union of the rounds' intervals
+                              on the two group streams (HIP events) */
     int64_t round_workers;     /* row workers summed over rounds (/ rounds = mean per round) */
     int64_t round_systems;     /* active systems summed over rounds */
     int64_t pipelined_rounds;  /* rounds that ran the pipelined worker loop */
@@ -397,7 +403,8 @@ typedef struct asyrk_server_stats {
 /* Defaults for asyrk_server_config. */
 void asyrk_server_config_init(asyrk_server_config *c);
 
-/* Create a server (its own non-blocking HIP stream; allocates the arena).
+/* Create a server (non-blocking HIP streams of its own: one per round group and
+ * one for uploads; allocates the arena).
  * Errors: INVALID_ARG, OOM, DEVICE. */
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg);
 
@@ -412,8 +419,10 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
                                  const int32_t *col_idx, const float *vals, const double *b, double tol,
                                  uint64_t seed, int64_t *request_id);
 
-/* Admit what fits, run one round, retire finished requests.  n_active /
- * n_queued (nullable) receive the counts after the round.  Errors: DEVICE. */
+/* Serve one round group: collect its previous round and retire finished
+ * requests, add uploaded requests, admit what fits, launch its next round
+ * (returns without waiting for it).  n_active / n_queued (nullable) receive
+ * the counts afterwards.  Errors: DEVICE. */
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued);
 
 /* The round loop on the calling thread: progress() until *stop becomes
