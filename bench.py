@@ -60,16 +60,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel):
+def traffic_from_profile(kernel, in_flight):
     """HBM bytes per sweep launch measured with rocprofv3 counters, if a
-    committed summary was taken on the current kernel sources and on the same
-    kernel instance (one summary per lane width profiled)."""
-    for p in sorted((ROOT / "profiles").glob("sweep_kernel_c2_4Mx1M_f32values_f64iter_G*_traffic.md")):
+    committed summary was taken on the current kernel sources, on the same
+    kernel instance and at the same R (one summary per configuration profiled)."""
+    for p in sorted((ROOT / "profiles").glob("sweep*_c2_4Mx1M_f32values_f64iter_*traffic.md")):
         text = p.read_text()
         mh = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
         mk = re.search(r"profiled_kernel:\s*(\S+)", text)
+        mr = re.search(r"profiled_in_flight:\s*(\d+)", text)
         mb = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-        if mh and mk and mb and mh.group(1) == kernel_source_hash() and mk.group(1) == kernel:
+        if (mh and mk and mr and mb and mh.group(1) == kernel_source_hash() and mk.group(1) == kernel
+                and int(mr.group(1)) == in_flight):
             return float(mb.group(1))
     return None
 
@@ -121,10 +123,11 @@ def run_c2(args):
     x = torch.zeros(N, dtype=torch.float64, device=dev)
     tuned = None
     if args.lanes == 0:
-        best, pipe, rates = sysm.autotune(GAMMA, in_flight=args.in_flight)
-        tuned = {"best_lanes": best, "pipelined": pipe,
+        # the library's choice of R (in_flight = 0) is left to the autotuner too
+        best, pipe, rates = sysm.autotune(GAMMA, in_flight=args.in_flight or "auto")
+        tuned = {"best_lanes": best, "pipelined": pipe, "in_flight": sysm.info()["tuned_in_flight"] or args.in_flight,
                  "rows_per_s": {f"G={g}{' pipelined' if p else ''}": r for (g, p), r in rates.items()}}
-        log(f"autotune: G={best} pipelined={pipe} {tuned['rows_per_s']}")
+        log(f"autotune: R={tuned['in_flight']} G={best} pipelined={pipe} {tuned['rows_per_s']}")
 
     def solve(seed, R=args.in_flight):
         x.zero_()
@@ -156,7 +159,7 @@ def run_c2(args):
     achieved = bytes_per_row * M / per_launch_s / 1e9
     kernel = (("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
               + f"<F32,F64,{sts[0]['lanes']}>")
-    traffic = traffic_from_profile(kernel)
+    traffic = traffic_from_profile(kernel, sts[0]["in_flight"])
 
     result = {
         "metric": "row updates/s + time-to-1e-6 residual vs plain RK; p50/p99 solve latency",

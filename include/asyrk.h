@@ -187,6 +187,8 @@ typedef struct asyrk_system_info {
                                   iterate: 256 for n <= 2^20, 64 for n <= 2^23, else 8.
                                   Columns sharing a cache line make their gathers and atomics
                                   queue behind each other; the caller's x stays dense */
+    int64_t tuned_in_flight;   /* R chosen by asyrk_autotune(in_flight = -1) for the FP64
+                                  iterate, used by solves with in_flight = 0; 0 if none */
 } asyrk_system_info;
 
 /* Version of this ABI (ASYRK_ABI_VERSION). */
@@ -296,7 +298,12 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
  * lane-group width G in {1, 2, 4, 8, 16, 32, 64} and each worker loop (plain,
  * pipelined) on this system, at in_flight workers (0 = the default R) and the
  * given iterate dtype (-1 = default), and keeps the fastest pair for later
- * solves with lanes = 0 and pipeline = -1 at that R.  Near-ties go by a fixed
+ * solves with lanes = 0 and pipeline = -1 at that R.  in_flight = -1 chooses R
+ * as well: each power of two from 1024 below the default R, and the default R,
+ * is timed with its best pair, and the smallest R within 2% of the fastest is
+ * kept (the same throughput with less staleness); later asynchronous,
+ * all-coordinate solves with replacement and in_flight = 0 then use it
+ * (asyrk_system_info.tuned_in_flight); other kinds keep the default R.  Near-ties go by a fixed
  * rule: the pipelined loop only when its best rate beats the plain loop's by
  * more than 3%, then the smallest G within 3% of that loop's best.  best_lanes and
  * best_pipeline (nullable) receive it; rows_per_s (nullable, double[14]) the

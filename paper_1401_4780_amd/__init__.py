@@ -76,7 +76,7 @@ class SystemInfo(C.Structure):
         ("vals_dtype", C.c_int32), ("iter_dtype", C.c_int32), ("fro2", C.c_double),
         ("lambda_mp", C.c_double), ("record_bytes_per_row", C.c_int64),
         ("max_col_norm2", C.c_double), ("default_in_flight", C.c_int64),
-        ("iterate_stride", C.c_int64),
+        ("iterate_stride", C.c_int64), ("tuned_in_flight", C.c_int64),
     ]
 
 
@@ -349,7 +349,11 @@ class System:
 
     def autotune(self, gamma=1.0, iter_dtype=None, in_flight=0):
         """Time one sweep per lane-group width and worker loop; the fastest pair
-        becomes the default at this R.  Returns (best G, pipelined?, {(G, pipelined): rows/s})."""
+        becomes the default at this R (in_flight = 0: the default R; "auto":
+        the autotuner picks R too, see info()["tuned_in_flight"]).  Returns
+        (best G, pipelined?, {(G, pipelined): rows/s}) at that R."""
+        if in_flight == "auto":
+            in_flight = -1
         best, pipe = C.c_int32(), C.c_int32()
         rates = (C.c_double * 14)()
         _check(lib().asyrk_autotune(self._h, float(gamma), {None: -1, "f32": F32, "f64": F64}[iter_dtype],

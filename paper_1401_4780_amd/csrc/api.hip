@@ -38,6 +38,7 @@ struct asyrk_system {
     int tuned_G[2] = {0, 0};      // autotuned lanes per row for F64 / F32 iterates (0 = none)
     int tuned_pipe[2] = {0, 0};   // autotuned worker loop (1 = pipelined) for F64 / F32 iterates
     int64_t tuned_R[2] = {0, 0};  // the R those were tuned at
+    bool tuned_auto_R[2] = {false, false};  // R chosen by the autotuner: solves with in_flight = 0 use it
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
@@ -398,6 +399,7 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
     info->max_col_norm2 = s->max_col_norm2;
     info->default_in_flight = auto_in_flight(s);
     info->iterate_stride = s->xstride;
+    info->tuned_in_flight = s->tuned_auto_R[0] ? s->tuned_R[0] : 0;
     return ASYRK_OK;
 }
 
@@ -507,23 +509,12 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
     return ASYRK_OK;
 }
 
-asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
-                            int32_t *best_lanes, int32_t *best_pipeline, double *rows_per_s_out) {
-    if (!s || !(gamma > 0.0 && gamma < 2.0) || in_flight < 0) return ASYRK_ERR_INVALID_ARG;
-    if (iter_dtype != -1 && iter_dtype != ASYRK_F32 && iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
-    const int xk = iter_dtype >= 0 ? iter_dtype : ASYRK_F64;
-    if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
-    if (s->rec_b_dirty) {
-        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
-        s->rec_b_dirty = false;
-    }
-    if (xk == ASYRK_F64 && s->vk != ASYRK_F64 && !s->d_side) {
-        HIP_OK(dmalloc(s, &s->d_side, (size_t)s->m * sizeof(double2)));
-        HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
-    }
+// Time every lane-group width and worker loop at R workers; returns the
+// chosen pair and its rate (the near-tie rule below) and the rates of all 14.
+static asyrk_status tune_at(asyrk_system *s, int xk, int64_t R, double gamma, int *G_out, int *pipe_out,
+                            double *rate_out, double *rates14) {
     asyrk_solve_params p;
     asyrk_solve_params_init(&p);
-    const int64_t R = in_flight ? in_flight : auto_in_flight(s);
     // at least one sweep and at least 2M tickets per candidate
     const int64_t tickets = std::max<int64_t>(s->m, (int64_t)2 << 20);
     const int cands[7] = {1, 2, 4, 8, 16, 32, 64};
@@ -538,7 +529,7 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
             if (rc) return rc;
             rate[pipe][k] = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
             top[pipe] = std::max(top[pipe], rate[pipe][k]);
-            if (rows_per_s_out) rows_per_s_out[7 * pipe + k] = rate[pipe][k];
+            if (rates14) rates14[7 * pipe + k] = rate[pipe][k];
         }
     }
     // Candidates a few percent apart differ by timing noise (a saturated
@@ -546,18 +537,69 @@ asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, i
     // when it beats the plain one by more than 3%, then the narrowest lane
     // group within 3% of that loop's fastest.
     const int best_pipe = top[1] > 1.03 * top[0] ? 1 : 0;
-    int best = cands[6];
+    int k_best = 6;
     for (int k = 0; k < 7; ++k)
         if (rate[best_pipe][k] >= 0.97 * top[best_pipe]) {
-            best = cands[k];
+            k_best = k;
             break;
         }
+    *G_out = cands[k_best];
+    *pipe_out = best_pipe;
+    *rate_out = rate[best_pipe][k_best];
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_autotune(asyrk_system *s, double gamma, int32_t iter_dtype, int64_t in_flight,
+                            int32_t *best_lanes, int32_t *best_pipeline, double *rows_per_s_out) {
+    if (!s || !(gamma > 0.0 && gamma < 2.0) || in_flight < -1) return ASYRK_ERR_INVALID_ARG;
+    if (iter_dtype != -1 && iter_dtype != ASYRK_F32 && iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
+    const int xk = iter_dtype >= 0 ? iter_dtype : ASYRK_F64;
+    if (s->vk == ASYRK_F64 && xk == ASYRK_F32) return ASYRK_ERR_UNSUPPORTED;
+    if (s->rec_b_dirty) {
+        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+        s->rec_b_dirty = false;
+    }
+    if (xk == ASYRK_F64 && s->vk != ASYRK_F64 && !s->d_side) {
+        HIP_OK(dmalloc(s, &s->d_side, (size_t)s->m * sizeof(double2)));
+        HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
+    }
+    const int64_t R_max = auto_in_flight(s);
+    int G = 0, pipe = 0;
+    double r_best = 0.0;
+    int64_t R = in_flight > 0 ? in_flight : R_max;
+    if (in_flight == -1) {
+        // The in-flight count too: powers of two from 1024 up to Corollary 1's
+        // bound, and the bound itself.  The smallest R within 2% of the
+        // fastest wins: the same throughput with less staleness.
+        std::vector<int64_t> Rs;
+        for (int64_t r = 1024; r < R_max; r *= 2) Rs.push_back(r);
+        Rs.push_back(R_max);
+        std::vector<double> rr(Rs.size(), 0.0);
+        std::vector<int> gg(Rs.size(), 0), pp(Rs.size(), 0);
+        double top = 0.0;
+        for (size_t k = 0; k < Rs.size(); ++k) {
+            asyrk_status rc = tune_at(s, xk, Rs[k], gamma, &gg[k], &pp[k], &rr[k], nullptr);
+            if (rc) return rc;
+            top = std::max(top, rr[k]);
+        }
+        size_t kb = Rs.size() - 1;
+        for (size_t k = 0; k < Rs.size(); ++k)
+            if (rr[k] >= 0.98 * top) {
+                kb = k;
+                break;
+            }
+        R = Rs[kb];
+    }
+    // the chosen R's candidates, timed again for the reported rates
+    asyrk_status rc = tune_at(s, xk, R, gamma, &G, &pipe, &r_best, rows_per_s_out);
+    if (rc) return rc;
     const int xi = xk == ASYRK_F32 ? 1 : 0;
-    s->tuned_G[xi] = best;
-    s->tuned_pipe[xi] = best_pipe;
+    s->tuned_G[xi] = G;
+    s->tuned_pipe[xi] = pipe;
     s->tuned_R[xi] = R;
-    if (best_lanes) *best_lanes = best;
-    if (best_pipeline) *best_pipeline = best_pipe;
+    s->tuned_auto_R[xi] = in_flight == -1;
+    if (best_lanes) *best_lanes = G;
+    if (best_pipeline) *best_pipeline = pipe;
     return ASYRK_OK;
 }
 
@@ -655,7 +697,13 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (sweeps > (INT64_MAX - p.ticket0) / s->m) return ASYRK_ERR_INVALID_ARG;
 
     const int xi = xk == ASYRK_F32 ? 1 : 0;
-    int64_t R = p.mode == ASYRK_REPLAY ? 1 : (p.in_flight ? p.in_flight : auto_in_flight(s));
+    // an R the autotuner chose holds for the solves it timed: asynchronous,
+    // all-coordinate, with replacement (traced or not)
+    const bool tuned_kind = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && p.order == 0;
+    int64_t R = p.mode == ASYRK_REPLAY ? 1
+                : p.in_flight          ? p.in_flight
+                : (tuned_kind && s->tuned_auto_R[xi]) ? s->tuned_R[xi]
+                                                      : auto_in_flight(s);
     // the autotuned pair holds at the R it was measured at
     const int tuned = s->tuned_R[xi] == R ? s->tuned_G[xi] : 0;
     const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R));

@@ -452,6 +452,20 @@ def test_autotune_picks_a_lane_width():
     # the tuned loop applies at the tuned R only; elsewhere the rule (R <= 8192)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=20_000)
     assert st["pipelined"] == 0
+    assert sysm.info()["tuned_in_flight"] == 0
+    # in_flight = "auto": R is tuned too, from 1024 up to the default R, and
+    # later solves with in_flight = 0 use it with the tuned pair
+    R_max = sysm.info()["default_in_flight"]
+    best, pipe, rates = sysm.autotune(in_flight="auto")
+    R = sysm.info()["tuned_in_flight"]
+    assert R == R_max or (R >= 1024 and R < R_max and R & (R - 1) == 0)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6)
+    assert st["in_flight"] == R and st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
+    # other kinds of solve were not timed at that R: they keep the default one
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, order="slices")
+    assert st["in_flight"] == R_max
+    x, st = gpu_solve(sysm, s, True, gamma=0.5, sweeps=1, seed=1, update="one")
+    assert st["in_flight"] == R_max
     sysm.close()
 
 
