@@ -222,6 +222,11 @@ def run_c2(args):
     ceil["rows_per_s_bound_gathers_and_atomics_serialized"] = serial_bound
     ceil["frac_of_atomic_bound"] = result["kernel_rows_per_s"] / atomic_bound
     result["ceilings"] = ceil
+    # the ceiling that binds: no-return FP64 atomics, nnz per row update, against
+    # the rate the probe above measures on this device (performed beyond the L2s)
+    result["roofline"]["atomic"] = {"achieved": result["kernel_rows_per_s"] * NNZ,
+                                    "peak": ceil[f"atomic_{ITER}_per_s"], "unit": "atomics/s",
+                                    "frac": ceil["frac_of_atomic_bound"]}
 
     if not args.no_sweep:
         sweep = {}
