@@ -215,6 +215,11 @@ void asyrk_solve_params_init(asyrk_solve_params *p);
  * Sweeps run in FP64 (values F64) or, by default, FP32 (values F32/BF16);
  * asyrk_solve_params.iter_dtype = ASYRK_F64 runs FP32/BF16 values with an
  * FP64 iterate and FP64 atomics.
+ * With ASYRK_MEM_DEVICE only row_ptr and the row weights pass through host
+ * memory: the entries are validated, weighed and packed into the row records
+ * on the device, from the caller's arrays (which are read during the call
+ * only), with the same records, statuses and statistics as host inputs give
+ * (max_col_norm2 up to the rounding order of its sums).
  * Errors: INVALID_ARG (shape, ordering, range, non-finite), ZERO_ROW, OOM,
  * DEVICE.  On error *out is set to NULL.
  */
@@ -246,6 +251,16 @@ asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b);
 
 /* Sizes and derived quantities of the system. */
 asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *info);
+
+/*
+ * Copy of the packed row records (headers {b_i, 1/w_i, alias bucket}, the
+ * rows' (column, value) units and their padding, laid out as the sweep reads
+ * them) into host memory dst of cap bytes, for checking the setup; the
+ * headers carry the current b.  *bytes_out (nullable) receives the image's
+ * size; dst = NULL only queries it.  INVALID_ARG for s = NULL or cap below
+ * the size.  Synchronizes the system's stream.
+ */
+asyrk_status asyrk_records_get(asyrk_system *s, void *dst, int64_t cap, int64_t *bytes_out);
 
 /*
  * Run the method from x (double[n], in: x0, out: the final iterate).

@@ -123,6 +123,13 @@ def lib():
         return _lib
     if not LIB_PATH.exists():
         raise LibraryMissing(f"{LIB_PATH} is not built; run `python -m paper_1401_4780_amd.build`")
+    # torch ships its own HIP runtime under the same soname: loaded first, it
+    # serves this library too.  Loaded after the system runtime, it would be a
+    # second runtime in the process, and torch would then see no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(str(LIB_PATH))
     P, i64, u64, u32, i32, dbl = C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
     L.asyrk_abi_version.restype = C.c_int
@@ -136,6 +143,7 @@ def lib():
     L.asyrk_destroy.argtypes = [P]
     L.asyrk_set_rhs.argtypes = [P, P]
     L.asyrk_system_info_get.argtypes = [P, P]
+    L.asyrk_records_get.argtypes = [P, P, i64, P]
     L.asyrk_solve.argtypes = [P, P, dbl, i64, u64, P, P]
     L.asyrk_residual.argtypes = [P, P, P, P]
     L.asyrk_sample_rows.argtypes = [P, u64, u32, i32, i64, i64, P, P]
@@ -156,6 +164,7 @@ def lib():
     L.asyrk_now.argtypes = []
     L.asyrk_now.restype = dbl
     for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
+                 "asyrk_records_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
@@ -304,6 +313,15 @@ class System:
         inf = SystemInfo()
         _check(lib().asyrk_system_info_get(self._h, C.byref(inf)), "asyrk_system_info_get")
         return {f: getattr(inf, f) for f, _ in SystemInfo._fields_}
+
+    def records(self) -> np.ndarray:
+        """The packed row records as the sweep reads them (uint8), copied to
+        the host, for checking the setup."""
+        size = C.c_int64(0)
+        _check(lib().asyrk_records_get(self._h, None, 0, C.byref(size)), "asyrk_records_get")
+        out = np.empty(size.value, np.uint8)
+        _check(lib().asyrk_records_get(self._h, out.ctypes.data, size.value, None), "asyrk_records_get")
+        return out
 
     def set_rhs(self, b):
         _expect(b, self.device, "float64", "b")

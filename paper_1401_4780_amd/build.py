@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> Path:
     o = OUT / "setup.o"
     _run(["g++", *HOST_FLAGS, "-c", str(CSRC / "setup.cpp"), "-o", str(o)], verbose)
     objs.append(o)
-    for src in ("kernels.hip", "api.hip", "server.hip"):
+    for src in ("kernels.hip", "setup_dev.hip", "api.hip", "server.hip"):
         o = OUT / (src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", str(CSRC / src), "-o", str(o)], verbose)
         objs.append(o)

@@ -1,6 +1,7 @@
 // C ABI of the asynchronous randomized Kaczmarz library (include/asyrk.h):
 // system creation, the solve driver (async, replay, refinement), residual,
 // sampler exposure, lambda_max and device ceilings.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -9,6 +10,7 @@
 
 #include "internal.h"
 #include "setup.h"
+#include "setup_dev.h"
 
 using namespace asyrk;
 
@@ -21,6 +23,7 @@ struct asyrk_system {
     double fro2 = 0.0, max_col_norm2 = 0.0;
     Rows rows{};
     uint8_t *d_rec = nullptr;
+    int64_t rec_bytes = 0;        // size of the record image
     RowLoc *d_loc = nullptr;
     double *d_b64 = nullptr;
     void *d_x = nullptr;          // sweep iterate: element c at byte c * xstride (float or double)
@@ -197,6 +200,9 @@ double now_s() {
 static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
                                uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
                                double *win_max_ticks, double *win_sum_ticks, double *win_cnt);
+static asyrk_status create_from_device(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                                       const int32_t *col, const void *vals, int32_t vals_dtype, const double *b,
+                                       void *stream);
 static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, const int64_t *rp,
                                      const int32_t *cl, const uint8_t *vl, int32_t vals_dtype, const double *bb,
                                      int32_t mem, void *stream);
@@ -246,6 +252,7 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     if (vals_dtype != ASYRK_F64 && vals_dtype != ASYRK_F32 && vals_dtype != ASYRK_BF16)
         return ASYRK_ERR_INVALID_ARG;
     if (!row_ptr || !b) return ASYRK_ERR_INVALID_ARG;
+    if (mem == ASYRK_MEM_DEVICE) return create_from_device(out, m, n, row_ptr, col_idx, vals, vals_dtype, b, stream);
 
     asyrk_system tmp_for_copy;
     std::vector<int64_t> rp_buf;
@@ -272,15 +279,10 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
     return create_from_host(out, m, n, rp, cl, vl, vals_dtype, bb, mem, stream);
 }
 
-static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, const int64_t *rp,
-                                     const int32_t *cl, const uint8_t *vl, int32_t vals_dtype, const double *bb,
-                                     int32_t mem, void *stream) {
-    SetupResult res;
-    asyrk_status rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, res);
-    if (rc) return rc;
-    rc = pack_records(m, rp, cl, vl, vals_dtype, bb, res);
-    if (rc) return rc;
-
+// The device state of a system whose layout `res` describes; the records
+// (rec_bytes), locators and b are left for the caller to fill.
+static asyrk_status alloc_system(asyrk_system *&out, int64_t m, int64_t n, int32_t vals_dtype, int32_t mem,
+                                 void *stream, const SetupResult &res, int64_t rec_bytes) {
     asyrk_system *s = new (std::nothrow) asyrk_system();
     if (!s) return ASYRK_ERR_OOM;
     s->m = m;
@@ -295,6 +297,7 @@ static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, c
     s->stride = res.stride;
     s->fro2 = res.fro2;
     s->max_col_norm2 = res.max_col_norm2;
+    s->rec_bytes = rec_bytes;
 
     hipError_t e = hipSuccess;
 #define TRY(expr)                       \
@@ -302,7 +305,7 @@ static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, c
         e = (expr);                     \
         if (e != hipSuccess) goto fail; \
     } while (0)
-    TRY(dmalloc(s, &s->d_rec, res.rec.size()));
+    TRY(dmalloc(s, &s->d_rec, (size_t)rec_bytes));
     if (res.fixed_nnz == 0) TRY(dmalloc(s, &s->d_loc, res.loc.size() * sizeof(RowLoc)));
     TRY(dmalloc(s, &s->d_b64, (size_t)m * sizeof(double)));
     s->xstride = iterate_stride(n);
@@ -314,23 +317,167 @@ static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, c
     TRY(hipHostMalloc((void **)&s->h_pin, 4 * sizeof(double), hipHostMallocDefault));
     TRY(hipEventCreate(&s->e0));
     TRY(hipEventCreate(&s->e1));
-    TRY(hipMemcpyAsync(s->d_rec, res.rec.data(), res.rec.size(), hipMemcpyHostToDevice, s->st));
-    if (res.fixed_nnz == 0)
-        TRY(hipMemcpyAsync(s->d_loc, res.loc.data(), res.loc.size() * sizeof(RowLoc), hipMemcpyHostToDevice,
-                           s->st));
-    TRY(hipMemcpyAsync(s->d_b64, bb, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s->st));
-    TRY(hipStreamSynchronize(s->st));
 #undef TRY
     s->rows.rec = s->d_rec;
     s->rows.loc = s->d_loc;
     s->rows.stride = s->stride;
     s->rows.fixed_nnz = (int32_t)s->fixed_nnz;
     s->rows.m = (int32_t)m;
-    *out = s;
+    out = s;
     return ASYRK_OK;
 fail:
     free_system(s);
     return dev_fail(e);
+}
+
+static asyrk_status create_from_host(asyrk_system **out, int64_t m, int64_t n, const int64_t *rp,
+                                     const int32_t *cl, const uint8_t *vl, int32_t vals_dtype, const double *bb,
+                                     int32_t mem, void *stream) {
+    SetupResult res;
+    asyrk_status rc = validate_system(m, n, rp, cl, vl, vals_dtype, bb, res);
+    if (rc) return rc;
+    rc = pack_records(m, rp, cl, vl, vals_dtype, bb, res);
+    if (rc) return rc;
+    asyrk_system *s = nullptr;
+    rc = alloc_system(s, m, n, vals_dtype, mem, stream, res, (int64_t)res.rec.size());
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(s->d_rec, res.rec.data(), res.rec.size(), hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess && res.fixed_nnz == 0)
+        e = hipMemcpyAsync(s->d_loc, res.loc.data(), res.loc.size() * sizeof(RowLoc), hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_b64, bb, (size_t)m * sizeof(double), hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) {
+        free_system(s);
+        return dev_fail(e);
+    }
+    *out = s;
+    return ASYRK_OK;
+}
+
+// Device temporaries of one call, freed when it returns.
+struct DevScratch {
+    std::vector<void *> ptrs;
+    hipError_t alloc(void **p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    ~DevScratch() {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+};
+
+// Inputs in device memory: row_ptr comes to the host (the record plan and the
+// checks of the row boundaries), the entries are validated, weighed and
+// packed on the device, and only the row weights make the round trip for the
+// alias table.  Same statuses, records and statistics as the host path, the
+// column norms up to rounding order.
+static asyrk_status create_from_device(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
+                                       const int32_t *col, const void *vals, int32_t vals_dtype, const double *b,
+                                       void *stream) {
+    const hipStream_t st = (hipStream_t)stream;
+    SetupResult res;
+    std::vector<int64_t> rp;
+    try {
+        rp.resize((size_t)m + 1);
+        res.w.resize((size_t)m);
+    } catch (...) {
+        return ASYRK_ERR_OOM;
+    }
+    HIP_OK(hipMemcpyAsync(rp.data(), row_ptr, ((size_t)m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (rp[0] != 0) return ASYRK_ERR_INVALID_ARG;
+    int64_t mu = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) return ASYRK_ERR_INVALID_ARG;
+        mu = std::max(mu, rp[i + 1] - rp[i]);
+    }
+    const int64_t nnz = rp[m];
+    if (nnz >= (int64_t)INT32_MAX) return ASYRK_ERR_INVALID_ARG;
+    if (nnz > 0 && (!col || !vals)) return ASYRK_ERR_INVALID_ARG;
+
+    DevScratch tmp;
+    double *d_w = nullptr, *d_sq = nullptr;
+    uint32_t *d_cnt = nullptr;
+    unsigned long long *d_misc = nullptr;  // flags, max column count, bits of the max column norm
+    HIP_OK(tmp.alloc((void **)&d_w, (size_t)m * sizeof(double)));
+    HIP_OK(tmp.alloc((void **)&d_cnt, (size_t)n * sizeof(uint32_t)));
+    HIP_OK(tmp.alloc((void **)&d_sq, (size_t)n * sizeof(double)));
+    HIP_OK(tmp.alloc((void **)&d_misc, 3 * sizeof(unsigned long long)));
+    HIP_OK(hipMemsetAsync(d_cnt, 0, (size_t)n * sizeof(uint32_t), st));
+    HIP_OK(hipMemsetAsync(d_sq, 0, (size_t)n * sizeof(double), st));
+    HIP_OK(hipMemsetAsync(d_misc, 0, 3 * sizeof(unsigned long long), st));
+    HIP_OK(launch_scan_rows_dev(vals_dtype, m, n, row_ptr, col, vals, b, d_w, d_cnt, d_sq, (uint32_t *)d_misc, st));
+    HIP_OK(launch_col_max_dev(d_cnt, d_sq, n, d_misc + 1, st));
+    unsigned long long misc[3] = {0, 0, 0};
+    HIP_OK(hipMemcpyAsync(res.w.data(), d_w, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(misc, d_misc, sizeof misc, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if ((uint32_t)misc[0] != 0) return ASYRK_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < m; ++i)
+        if (!(res.w[i] > 0.0)) return ASYRK_ERR_ZERO_ROW;
+
+    res.nnz = nnz;
+    res.mu = mu;
+    res.nu = (int64_t)misc[1];
+    std::memcpy(&res.max_col_norm2, &misc[2], sizeof(double));
+    res.fixed_nnz = rp[1] - rp[0];
+    for (int64_t i = 1; i < m && res.fixed_nnz > 0; ++i)
+        if (rp[i + 1] - rp[i] != res.fixed_nnz) res.fixed_nnz = 0;
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < m; ++i) fro2 = fro2 + res.w[i];
+    res.fro2 = fro2;
+    int64_t total = 0;
+    asyrk_status rc = plan_records(m, rp.data(), vals_dtype, res, &total);
+    if (rc) return rc;
+
+    std::vector<RowAux> aux;
+    {
+        std::vector<uint32_t> thresh;
+        std::vector<int32_t> alias;
+        try {
+            build_alias(res.w, thresh, alias);
+            aux.resize((size_t)m);
+        } catch (...) {
+            return ASYRK_ERR_OOM;
+        }
+        for (int64_t i = 0; i < m; ++i) aux[i] = RowAux{1.0 / res.w[i], thresh[i], alias[i]};
+    }
+    RowAux *d_aux = nullptr;
+    HIP_OK(tmp.alloc((void **)&d_aux, (size_t)m * sizeof(RowAux)));
+    HIP_OK(hipMemcpyAsync(d_aux, aux.data(), (size_t)m * sizeof(RowAux), hipMemcpyHostToDevice, st));
+
+    asyrk_system *s = nullptr;
+    rc = alloc_system(s, m, n, vals_dtype, ASYRK_MEM_DEVICE, stream, res, total);
+    if (rc) return rc;
+    hipError_t e = hipSuccess;
+    if (res.fixed_nnz == 0)
+        e = hipMemcpyAsync(s->d_loc, res.loc.data(), res.loc.size() * sizeof(RowLoc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_write_records_dev(vals_dtype, m, row_ptr, col, vals, b, d_aux, res.stride,
+                                     res.fixed_nnz == 0 ? s->d_loc : nullptr, s->d_rec, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_b64, b, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_system(s);
+        return dev_fail(e);
+    }
+    *out = s;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_records_get(asyrk_system *s, void *dst, int64_t cap, int64_t *bytes_out) {
+    if (!s) return ASYRK_ERR_INVALID_ARG;
+    if (bytes_out) *bytes_out = s->rec_bytes;
+    if (!dst) return ASYRK_OK;
+    if (cap < s->rec_bytes) return ASYRK_ERR_INVALID_ARG;
+    if (s->rec_b_dirty) {  // a refinement left its residual in the headers
+        HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
+        s->rec_b_dirty = false;
+    }
+    HIP_OK(hipStreamSynchronize(s->st));
+    HIP_OK(hipMemcpy(dst, s->d_rec, (size_t)s->rec_bytes, hipMemcpyDeviceToHost));
+    return ASYRK_OK;
 }
 
 asyrk_status asyrk_destroy(asyrk_system *s) {
