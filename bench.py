@@ -114,9 +114,12 @@ def run_c2(args):
     def d(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
+    csr = [d(s.row_ptr), d(s.col), d(s.val), d(s.b)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=N)
+    sysm = P.System(*csr, n=N)
     setup_s = time.perf_counter() - t0
+    del csr
     info = sysm.info()
     log(f"setup {setup_s:.1f}s stride={info['record_stride']} device_bytes={info['device_bytes']}")
     x_ref = d(s.x_star)

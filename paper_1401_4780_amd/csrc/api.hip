@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -431,21 +432,17 @@ static asyrk_status create_from_device(asyrk_system **out, int64_t m, int64_t n,
     asyrk_status rc = plan_records(m, rp.data(), vals_dtype, res, &total);
     if (rc) return rc;
 
-    std::vector<RowAux> aux;
+    std::unique_ptr<RowAux[]> aux(new (std::nothrow) RowAux[m]);
     {
-        std::vector<uint32_t> thresh;
-        std::vector<int32_t> alias;
-        try {
-            build_alias(res.w, thresh, alias);
-            aux.resize((size_t)m);
-        } catch (...) {
-            return ASYRK_ERR_OOM;
-        }
-        for (int64_t i = 0; i < m; ++i) aux[i] = RowAux{1.0 / res.w[i], thresh[i], alias[i]};
+        std::unique_ptr<uint32_t[]> thresh(new (std::nothrow) uint32_t[m]);
+        std::unique_ptr<int32_t[]> alias(new (std::nothrow) int32_t[m]);
+        if (!aux || !thresh || !alias) return ASYRK_ERR_OOM;
+        build_alias(res.w.data(), m, thresh.get(), alias.get());
+        row_aux(res.w.data(), m, thresh.get(), alias.get(), aux.get());
     }
     RowAux *d_aux = nullptr;
     HIP_OK(tmp.alloc((void **)&d_aux, (size_t)m * sizeof(RowAux)));
-    HIP_OK(hipMemcpyAsync(d_aux, aux.data(), (size_t)m * sizeof(RowAux), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_aux, aux.get(), (size_t)m * sizeof(RowAux), hipMemcpyHostToDevice, st));
 
     asyrk_system *s = nullptr;
     rc = alloc_system(s, m, n, vals_dtype, ASYRK_MEM_DEVICE, stream, res, total);

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -198,27 +199,47 @@ asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const
 // p_l <- (p_l + p_s) - 1.  Buckets left on either list keep their own row
 // (threshold stored as 2^32 - 1 with alias = itself, which selects the
 // bucket's row for every u2).
-void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
-                 std::vector<int32_t> &alias) {
-    const int64_t m = (int64_t)w.size();
+void build_alias(const double *w, int64_t m, uint32_t *thresh, int32_t *alias) {
     double total = 0.0;
     for (int64_t i = 0; i < m; ++i) total = total + w[i];
-    std::vector<double> p(m);
+    std::unique_ptr<double[]> p(new double[m]);
     // Both work lists share one array: the small list grows up from the
     // front, the large list down from the back (each index is on at most one
     // list, so they never meet); both are used last-in first-out.
-    std::vector<int32_t> lists(m);
-    int64_t ns = 0, nl = 0;
-    for (int64_t i = 0; i < m; ++i) {
-        p[i] = (w[i] * (double)m) / total;
-        if (p[i] < 1.0)
-            lists[ns++] = (int32_t)i;
-        else
-            lists[m - 1 - nl++] = (int32_t)i;
+    std::unique_ptr<int32_t[]> lists(new int32_t[m]);
+    // p_i, the default entries and the lists, over row ranges in parallel:
+    // each range counts its small rows first, so that it knows where its
+    // share of either list starts, then fills it in index order.
+    const unsigned parts = threads_for(m);
+    const int64_t chunk = (m + parts - 1) / parts;
+    std::vector<int64_t> n_small(parts, 0);
+    parallel_rows(m, parts, [&](int64_t lo, int64_t hi) {
+        int64_t c = 0;
+        for (int64_t i = lo; i < hi; ++i) {
+            const double q = (w[i] * (double)m) / total;
+            p[i] = q;
+            c += q < 1.0;
+            thresh[i] = 0xffffffffu;
+            alias[i] = (int32_t)i;
+        }
+        n_small[lo / chunk] = c;
+    });
+    std::vector<int64_t> small_at(parts, 0);
+    int64_t ns = 0;
+    for (unsigned t = 0; t < parts; ++t) {
+        small_at[t] = ns;
+        ns += n_small[t];
     }
-    thresh.assign(m, 0xffffffffu);
-    alias.resize(m);
-    for (int64_t i = 0; i < m; ++i) alias[i] = (int32_t)i;
+    int64_t nl = m - ns;
+    parallel_rows(m, parts, [&](int64_t lo, int64_t hi) {
+        int64_t sp = small_at[lo / chunk], lp = lo - sp;  // large rows before this range
+        for (int64_t i = lo; i < hi; ++i) {
+            if (p[i] < 1.0)
+                lists[sp++] = (int32_t)i;
+            else
+                lists[m - 1 - lp++] = (int32_t)i;
+        }
+    });
     while (ns > 0 && nl > 0) {
         const int64_t sm = lists[--ns];
         const int64_t l = lists[m - nl--];
@@ -231,6 +252,19 @@ void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
             lists[m - 1 - nl++] = (int32_t)l;
     }
     // leftovers keep thresh = 2^32 - 1 and alias = self
+}
+
+void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
+                 std::vector<int32_t> &alias) {
+    thresh.resize(w.size());
+    alias.resize(w.size());
+    build_alias(w.data(), (int64_t)w.size(), thresh.data(), alias.data());
+}
+
+void row_aux(const double *w, int64_t m, const uint32_t *thresh, const int32_t *alias, RowAux *aux) {
+    parallel_rows(m, threads_for(m), [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) aux[i] = RowAux{1.0 / w[i], thresh[i], alias[i]};
+    });
 }
 
 // Store a FP64 value in the dtype (BF16: nearest, ties to even, of the FP32 value).
@@ -395,9 +429,10 @@ void write_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const 
 
 asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
                           int vk, const double *b, SetupResult &res) {
-    std::vector<uint32_t> thresh;
-    std::vector<int32_t> alias;
-    build_alias(res.w, thresh, alias);
+    const int64_t mm = (int64_t)res.w.size();
+    std::unique_ptr<uint32_t[]> thresh(new uint32_t[mm]);
+    std::unique_ptr<int32_t[]> alias(new int32_t[mm]);
+    build_alias(res.w.data(), mm, thresh.get(), alias.get());
     int64_t total = 0;
     asyrk_status rc = plan_records(m, row_ptr, vk, res, &total);
     if (rc) return rc;
@@ -406,7 +441,7 @@ asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col,
     } catch (...) {
         return ASYRK_ERR_OOM;
     }
-    write_records(m, row_ptr, col, vals, vk, b, res, thresh.data(), alias.data(), res.rec.data());
+    write_records(m, row_ptr, col, vals, vk, b, res, thresh.get(), alias.get(), res.rec.data());
     return ASYRK_OK;
 }
 

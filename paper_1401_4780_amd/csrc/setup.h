@@ -36,8 +36,22 @@ asyrk_status build_augmented(int64_t m, int64_t n, const int64_t *row_ptr, const
 
 asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                              const void *vals, int vk, const double *b, SetupResult &out);
+// Alias table of the weights w[0..m-1] into thresh and alias (m entries each,
+// caller memory; see setup.cpp for the construction).
+void build_alias(const double *w, int64_t m, uint32_t *thresh, int32_t *alias);
 void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
                  std::vector<int32_t> &alias);
+
+// Per-row values the host derives from the row weights for records written
+// on the device: 1/w_i and the alias bucket of row i.
+struct RowAux {
+    double inv_w;
+    uint32_t thresh;
+    int32_t alias;
+};
+static_assert(sizeof(RowAux) == 16, "RowAux");
+// aux[i] = {1 / w[i], thresh[i], alias[i]} for i < m.
+void row_aux(const double *w, int64_t m, const uint32_t *thresh, const int32_t *alias, RowAux *aux);
 // Alias table, layout and records in res.rec.
 asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col, const void *vals,
                           int vk, const double *b, SetupResult &res);

@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "layout.h"
+#include "setup.h"  // RowAux
 
 namespace asyrk {
 
@@ -17,15 +18,6 @@ enum : uint32_t {
     kBadEntry = 1u,   // a column out of range or not increasing within its row, or a non-finite value
     kBadRhs = 2u,     // a non-finite b_i
 };
-
-// Per-row values the host derives from the row weights: 1/w_i and the alias
-// bucket of row i (the header fields the device cannot form on its own).
-struct RowAux {
-    double inv_w;
-    uint32_t thresh;
-    int32_t alias;
-};
-static_assert(sizeof(RowAux) == 16, "RowAux");
 
 // Rows 0..m-1 of a CSR whose row_ptr the host has checked (row_ptr[0] = 0,
 // non-decreasing, row_ptr[m] = nnz): w_i = sum of v^2 over the row in CSR

@@ -1,14 +1,16 @@
 """The gfx950 code this library builds (CPU only: hipcc cross-compiles).
 
-Compiles kernels.hip and server.hip to device assembly with the package's own
-flags and checks what the hot path relies on:
+Compiles kernels.hip, server.hip and setup_dev.hip to device assembly with the
+package's own flags and checks what the hot path relies on:
 
 * every sweep kernel scatters with hardware float atomics
   (global/flat_atomic_add_f32 or _f64), never a compare-and-swap loop;
 * no packed-FP32 instruction appears anywhere (the build disables them);
 * the pipelined worker loop issues a lane's gathers for a ticket together:
   at least one unit's entries (4, or 8 for BF16) of agent-scope loads in a
-  row with no wait between them, never one load per wait.
+  row with no wait between them, never one load per wait;
+* the device-side setup forms the row weights with separate FP64 multiplies
+  and adds (no fused multiply-add), so they equal the host's sums.
 """
 import re
 import shutil
@@ -45,7 +47,7 @@ def _functions(asm):
 def kernels(tmp_path_factory):
     tmp = tmp_path_factory.mktemp("isa")
     funcs = {}
-    for src in ("kernels.hip", "server.hip"):
+    for src in ("kernels.hip", "server.hip", "setup_dev.hip"):
         funcs.update(_functions(_asm(src, tmp)))
     return funcs
 
@@ -101,3 +103,11 @@ def test_pipelined_gathers_issue_back_to_back(kernels):
         # show runs of one
         want = min(_lane_entries(name), _unit_entries(name))
         assert best >= want, (name, best, want)
+
+
+def test_device_setup_weights_are_unfused(kernels):
+    scans = {k: v for k, v in kernels.items() if "scan_rows_kernel" in k}
+    assert len(scans) == 3, sorted(kernels)
+    for name, body in scans.items():
+        assert "v_fma_f64" not in body and "v_fmac_f64" not in body, name
+        assert "v_mul_f64" in body and "v_add_f64" in body, name
