@@ -437,7 +437,7 @@ static asyrk_status create_from_device(asyrk_system **out, int64_t m, int64_t n,
         std::unique_ptr<uint32_t[]> thresh(new (std::nothrow) uint32_t[m]);
         std::unique_ptr<int32_t[]> alias(new (std::nothrow) int32_t[m]);
         if (!aux || !thresh || !alias) return ASYRK_ERR_OOM;
-        build_alias(res.w.data(), m, thresh.get(), alias.get());
+        build_alias(res.w.data(), m, res.fro2, thresh.get(), alias.get());
         row_aux(res.w.data(), m, thresh.get(), alias.get(), aux.get());
     }
     RowAux *d_aux = nullptr;

@@ -199,9 +199,7 @@ asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const
 // p_l <- (p_l + p_s) - 1.  Buckets left on either list keep their own row
 // (threshold stored as 2^32 - 1 with alias = itself, which selects the
 // bucket's row for every u2).
-void build_alias(const double *w, int64_t m, uint32_t *thresh, int32_t *alias) {
-    double total = 0.0;
-    for (int64_t i = 0; i < m; ++i) total = total + w[i];
+void build_alias(const double *w, int64_t m, double total, uint32_t *thresh, int32_t *alias) {
     std::unique_ptr<double[]> p(new double[m]);
     // Both work lists share one array: the small list grows up from the
     // front, the large list down from the back (each index is on at most one
@@ -256,9 +254,11 @@ void build_alias(const double *w, int64_t m, uint32_t *thresh, int32_t *alias) {
 
 void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
                  std::vector<int32_t> &alias) {
+    double total = 0.0;
+    for (double v : w) total = total + v;
     thresh.resize(w.size());
     alias.resize(w.size());
-    build_alias(w.data(), (int64_t)w.size(), thresh.data(), alias.data());
+    build_alias(w.data(), (int64_t)w.size(), total, thresh.data(), alias.data());
 }
 
 void row_aux(const double *w, int64_t m, const uint32_t *thresh, const int32_t *alias, RowAux *aux) {
@@ -432,7 +432,7 @@ asyrk_status pack_records(int64_t m, const int64_t *row_ptr, const int32_t *col,
     const int64_t mm = (int64_t)res.w.size();
     std::unique_ptr<uint32_t[]> thresh(new uint32_t[mm]);
     std::unique_ptr<int32_t[]> alias(new int32_t[mm]);
-    build_alias(res.w.data(), mm, thresh.get(), alias.get());
+    build_alias(res.w.data(), mm, res.fro2, thresh.get(), alias.get());
     int64_t total = 0;
     asyrk_status rc = plan_records(m, row_ptr, vk, res, &total);
     if (rc) return rc;

@@ -37,8 +37,9 @@ asyrk_status build_augmented(int64_t m, int64_t n, const int64_t *row_ptr, const
 asyrk_status validate_system(int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                              const void *vals, int vk, const double *b, SetupResult &out);
 // Alias table of the weights w[0..m-1] into thresh and alias (m entries each,
-// caller memory; see setup.cpp for the construction).
-void build_alias(const double *w, int64_t m, uint32_t *thresh, int32_t *alias);
+// caller memory; see setup.cpp for the construction).  total must be the sum
+// of w taken left to right (validate_system's fro2).
+void build_alias(const double *w, int64_t m, double total, uint32_t *thresh, int32_t *alias);
 void build_alias(const std::vector<double> &w, std::vector<uint32_t> &thresh,
                  std::vector<int32_t> &alias);
 
