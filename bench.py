@@ -390,6 +390,40 @@ def run_skewed(args):
             "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
 
 
+def serving_cpu_baseline(gen, specs, n_req, tol, k=16, max_sweeps=200):
+    """Sequential FP64 oracle on a stratified sample of the serving stream:
+    the k requests at the (q + 1/2)/k quantiles of m, each solved from x0 = 0
+    sweep by sweep until ||Ax - b|| / ||b|| <= tol.  Only the sweeps are
+    timed (the residual after each is the stopping test, untimed); the mean
+    time per solve over the strata gives solves/s on one core."""
+    import oracle
+    order = np.argsort(specs[:n_req, 0], kind="stable")
+    picks = [int(order[min(n_req - 1, int((q + 0.5) * n_req / k))]) for q in range(k)]
+    times, sweeps, reached = [], [], 0
+    for rid in picks:
+        s = gen(rid)
+        b2 = float(np.dot(s.b, s.b))
+        x = np.zeros(s.n)
+        t, done = 0.0, 0
+        for sw in range(max_sweeps):
+            t0 = time.perf_counter()
+            x = oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x, 1.0, s.m, 1 + rid, ticket0=sw * s.m,
+                              want_res=False)["x"]
+            t += time.perf_counter() - t0
+            done = sw + 1
+            if oracle.residual(s.row_ptr, s.col, s.val64, s.b, x) <= tol * tol * b2:
+                reached += 1
+                break
+        times.append(t)
+        sweeps.append(done)
+    mean_t = float(np.mean(times))
+    return {"value": 1.0 / mean_t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} requests at the quantiles of m ({int(specs[picks[0], 0])}..{int(specs[picks[-1], 0])} rows), "
+                      f"sequential FP64 RK to {tol:g} relative residual from x0=0, single thread, "
+                      f"{sum(times):.1f} s of sweeps, mean {float(np.mean(sweeps)):.1f} sweeps, "
+                      f"{reached}/{k} reached the tolerance within {max_sweeps} sweeps"}
+
+
 def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
     """Poisson stream of independent systems (m log-uniform in [1k, 200k],
     n = m/4, 8..64 entries per row, FP32 values, FP64 refinement to 1e-8
@@ -507,6 +541,11 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
             sysm.close()
         torch.cuda.synchronize()
         base = nb / (time.perf_counter() - t0)
+    cpu = None
+    if baseline and not args.no_cpu_baseline:
+        log("serving cpu baseline (oracle)")
+        cpu = serving_cpu_baseline(gen, specs, n_req, tol)
+        log(f"serving cpu baseline: {cpu}")
     return {"metric": "solves/s and p50/p99 solve latency (serving)", "value": sat["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
             "vs_baseline": None, "data": "synthetic", "dtype": "f64",
@@ -520,6 +559,7 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
             "speedup_vs_sequential_fp64": sat["solves_per_s"] / base if base else None,
+            "cpu_baseline": cpu,
             "server_stats": st}
 
 
