@@ -80,22 +80,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(s, target_s=15.0):
-    """Sequential FP64 oracle on a bounded sample of the same system."""
+def cpu_baseline(s, target_s=15.0, max_sweeps=12):
+    """Sequential FP64 oracle on a bounded sample of the same system (at least
+    one sweep, at most max_sweeps, about target_s seconds)."""
     import oracle
     x0 = np.zeros(s.n)
     probe = 2_000_000
     t0 = time.perf_counter()
     oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, probe, 7)
     rate0 = probe / (time.perf_counter() - t0)
-    steps = int(min(max(rate0 * target_s, s.m), 12 * s.m))
+    steps = int(min(max(rate0 * target_s, s.m), max_sweeps * s.m))
     t0 = time.perf_counter()
     # the error after every sweep is one O(n) pass, under 1% of a sweep
     out = oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, x0, GAMMA, steps, 7, curve_every=s.m,
                         x_ref=s.x_star, want_res=False)
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "row updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} row updates ({steps / s.m:.2f} sweeps) of the same 4Mx1M system "
+            "sample": f"{steps} row updates ({steps / s.m:.2f} sweeps) of the same {s.m}x{s.n} system "
                       f"from x0=0, sequential FP64, single thread, {dt:.1f} s",
             "err_curve": [float(v) for v in out["err"]]}
 
@@ -336,12 +337,21 @@ def run_precision(args):
     for name in out:
         out[name]["speedup_vs_fp64"] = base / out[name]["time_to_1e-10_s_p50"]
     best = min(out, key=lambda q: out[q]["time_to_1e-10_s_p50"])
+    cb = None
+    if not args.no_cpu_baseline:
+        # the oracle's rate on a bounded sample of the FP64 system; its time to
+        # 1e-10 estimated at the sweep count of the GPU's plain FP64 solve
+        log("cpu baseline (oracle)")
+        cb = cpu_baseline(s64, max_sweeps=2)
+        cb["rows_per_s"] = cb["value"]
+        cb["value"] = out["f64_values_f64_sweeps"]["sweeps"] * m / cb["rows_per_s"]
+        cb["unit"] = "s (estimated from the rate and the FP64 solve's sweep count)"
     return {"metric": "time to ||x-x*||/||x*|| <= 1e-10 (precision path)",
             "value": out[best]["time_to_1e-10_s_p50"], "unit": "s", "n_gpus": 1,
             "steps": args.steps, "warmup": 1, "higher_is_better": False, "vs_baseline": None,
             "data": "synthetic", "dtype": "mixed",
             "config": {"workload": "asyrk_8Mx2M_nnz16_to_1e-10", "m": m, "n": n, "nnz_per_row": k,
-                       "best": best}, "variants": out}
+                       "best": best}, "variants": out, "cpu_baseline": cb}
 
 
 def run_skewed(args):
@@ -387,7 +397,8 @@ def run_skewed(args):
                        "best_converging_in_flight": best},
             "lambda_max": lam, "tau_max_corollary1": tau_max, "default_in_flight": R0,
             "max_col_norm2": info["max_col_norm2"],
-            "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res}
+            "hot_column_row_fraction": float(cnt.max() / s.m), "by_in_flight": res,
+            "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(s, max_sweeps=2)}
 
 
 def serving_cpu_baseline(gen, specs, n_req, tol, k=16, max_sweeps=200):
