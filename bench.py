@@ -199,6 +199,11 @@ def run_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     # what the excess over the algorithmic bytes is: the 20 random
+                     # x gathers and 20 atomics per row, counted at the L2/fabric
+                     # boundary (x lives in the Infinity Cache), not re-reads
+                     "traffic_note": "x gathers: one line each from beyond the L2 (~136 B); "
+                                     "atomics: 32 B each; records + side: 208 B per row",
                      "kernel": kernel, "algorithmic_bytes_per_row": bytes_per_row,
                      "launch_ms_mean": per_launch_s * 1e3, "launches": launches},
     }
