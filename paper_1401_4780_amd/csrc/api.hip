@@ -131,14 +131,18 @@ constexpr int64_t kPipeMaxR = 8192;
 // than at the average's G = 8).  With so few workers that the covering
 // groups would not give every CU a wave (R * G < 2^14 lanes), G grows until
 // they do, idle lanes and all: spreading the workers over more CUs measured
-// 7-8% faster at R = 512-1024 on 20-entry rows.
-int auto_lanes(const asyrk_system *s, int64_t R) {
+// 7-8% faster at R = 512-1024 on 20-entry rows.  The single-coordinate
+// update (Algorithm 1) issues one atomic per row and is bound by its gathers,
+// which take twice the lanes in flight to saturate (R * G <= 2^17: 4.0e9
+// against 3.2e9 rows/s at R = 65536 on 20-entry rows).
+int auto_lanes(const asyrk_system *s, int64_t R, bool update_one) {
     const Geom g = geom_of(s->vk);
     const double units = (double)s->mu / g.U;
+    const int64_t cap = (int64_t)1 << (update_one ? 17 : 16);
     int cover = 1;
     while (cover < 64 && cover < units) cover *= 2;
     int G = 1;
-    while (G < cover && R * (2 * G) <= ((int64_t)1 << 16)) G *= 2;
+    while (G < cover && R * (2 * G) <= cap) G *= 2;
     while (G < 64 && R * G < ((int64_t)1 << 14)) G *= 2;
     return G;
 }
@@ -848,9 +852,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                 : p.in_flight          ? p.in_flight
                 : (tuned_kind && s->tuned_auto_R[xi]) ? s->tuned_R[xi]
                                                       : auto_in_flight(s);
-    // the autotuned pair holds at the R it was measured at
-    const int tuned = s->tuned_R[xi] == R ? s->tuned_G[xi] : 0;
-    const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R));
+    // the autotuned pair holds at the R and for the kind of solve it was measured on
+    const int tuned = tuned_kind && s->tuned_R[xi] == R ? s->tuned_G[xi] : 0;
+    const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R, p.update == ASYRK_UPDATE_ONE));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     if (p.pipeline == -1) {
         const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && p.order == 0 && !p.trace;

@@ -461,11 +461,26 @@ def test_autotune_picks_a_lane_width():
     assert R == R_max or (R >= 1024 and R < R_max and R & (R - 1) == 0)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6)
     assert st["in_flight"] == R and st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
-    # other kinds of solve were not timed at that R: they keep the default one
+    # other kinds of solve were not timed at that R: they keep the default one,
+    # and the lane rule (the tuned pair is not theirs either)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, order="slices")
     assert st["in_flight"] == R_max
     x, st = gpu_solve(sysm, s, True, gamma=0.5, sweeps=1, seed=1, update="one")
     assert st["in_flight"] == R_max
+    x, st = gpu_solve(sysm, s, True, gamma=0.5, sweeps=1, seed=1, update="one", in_flight=R)
+    fresh = make_system(s, device=True)
+    x, st0 = gpu_solve(fresh, s, True, gamma=0.5, sweeps=1, seed=1, update="one", in_flight=R)
+    assert st["lanes"] == st0["lanes"]
+    # the lane rule: 2^16 lanes in flight for the all-coordinate update, 2^17
+    # for Algorithm 1's gather-bound single-coordinate one (20-entry rows:
+    # 5 units, covered by 8 lanes)
+    x, st = gpu_solve(fresh, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=65536)
+    assert st["lanes"] == 1 and st["pipelined"] == 0
+    x, st = gpu_solve(fresh, s, True, gamma=0.05, sweeps=1, seed=1, in_flight=65536, update="one")
+    assert st["lanes"] == 2
+    x, st = gpu_solve(fresh, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=1024)
+    assert st["lanes"] == 16
+    fresh.close()
     sysm.close()
 
 
