@@ -467,6 +467,7 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
                    **({"max_workers": args.max_workers} if args.max_workers else {}),
                    **({"pipe_workers": args.pipe_workers} if args.pipe_workers >= 0 else {}),
                    **({"pipe_lanes": args.pipe_lanes} if args.pipe_lanes else {}),
+                   **({"order": args.order} if args.order >= 0 else {}),
                    fixed_rounds=int(args.fixed_rounds))
 
     def drive(first, count, arrivals):
@@ -571,6 +572,7 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
                        "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"],
                        "submit_threads": args.submit_threads, "fixed_rounds": srv.config["fixed_rounds"],
+                       "order": srv.config["order"],
                        "lanes_in_use": [st["lanes"], st["pipe_lanes"]]},
             "saturation": sat, "by_load": sweep,
             "sequential_fp64_solves_per_s": base,
@@ -587,6 +589,8 @@ def main():
     ap.add_argument("--in-flight", type=int, default=0, help="R (0: the library's choice)")
     ap.add_argument("--tune-lanes", action="store_true",
                     help="serving: the server picks lanes per row online (lanes = pipe_lanes = 0)")
+    ap.add_argument("--order", type=int, default=-1,
+                    help="serving: busy rounds' row order, 1 slices without replacement, 0 sampled (-1: default)")
     ap.add_argument("--fixed-rounds", action="store_true",
                     help="serving: every round runs the full inner sweeps (no sizing of later rounds)")
     ap.add_argument("--submit-threads", type=int, default=8,

@@ -85,7 +85,7 @@ class ServerConfig(C.Structure):
         ("budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("inner_sweeps", C.c_int32),
         ("max_workers", C.c_int64), ("max_rounds", C.c_int32), ("use_graph", C.c_int32),
         ("gamma", C.c_double), ("pinned_bytes", C.c_int64), ("lanes", C.c_int32), ("pipe_workers", C.c_int32),
-        ("pipe_lanes", C.c_int32), ("fixed_rounds", C.c_int32),
+        ("pipe_lanes", C.c_int32), ("fixed_rounds", C.c_int32), ("order", C.c_int32),
     ]
 
 

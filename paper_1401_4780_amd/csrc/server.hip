@@ -137,6 +137,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     srv_sweep_body<G, false>(th, sl);
 }
 
+// Plain loop without replacement (the slice scheme of the paper's
+// experiments): worker w of a system owns its rows [w L, min(m, (w + 1) L)),
+// L = ceil(m / R), and visits them in a fresh keyed permutation every sweep
+// of the round; a round's tickets cover whole sweeps.
+template <int G>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void srv_sweep_slices_kernel(
+    const TableHead *th, const SlotDesc *sl) {
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / G) + (lane / G);
+    if (worker >= th->total_workers) return;
+    const int s = find_slot(th->nact, worker, [&](int k) { return sl[k].w_off; });
+    const SlotDesc d = sl[s];
+    const int64_t w = worker - d.w_off;
+    const int64_t m = d.rows.m;
+    const int64_t L = (m + d.R - 1) / d.R;
+    const int64_t start = w * L;
+    const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
+    for (int64_t sw = d.t_begin / m; sw < d.t_end / m; ++sw) {
+        const U4 u = philox4x32_10((uint32_t)((uint64_t)sw & 0xffffffffu), (uint32_t)((uint64_t)sw >> 32),
+                                   (uint32_t)w, 0x5C4E3D2Bu, d.key0, d.key1);
+        for (int64_t k = 0; k < Lw; ++k) {
+            const uint32_t i = (uint32_t)(start + slice_perm((uint32_t)k, (uint32_t)Lw, u));
+            process_ticket<ASYRK_F32, ASYRK_F64, G, (G < 16 ? 16 / G : 1), false>(
+                d.rows, d.d, d.xshift, d.side, 0, 0u, 0u, 0u, 1, 0, d.gamma, gl, 0, i);
+        }
+    }
+}
+
 // Pipelined loop: its rounds hold at most a few thousand workers, so it may
 // use the registers of two tickets without an occupancy bound.
 template <int G>
@@ -397,6 +427,12 @@ hipError_t launch_zero_and_sweep(const asyrk_server *s, const RoundGroup &g, hip
             case 32: hipLaunchKernelGGL(srv_sweep_pipe_kernel<32>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             default: return hipErrorInvalidValue;
         }
+    } else if (s->cfg.order == 1) {
+        switch (G) {
+            case 4: hipLaunchKernelGGL(srv_sweep_slices_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 8: hipLaunchKernelGGL(srv_sweep_slices_kernel<8>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            default: return hipErrorInvalidValue;
+        }
     } else {
         switch (G) {
             case 4: hipLaunchKernelGGL(srv_sweep_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
@@ -483,6 +519,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->lanes = 4;
     c->pipe_workers = 8192;
     c->pipe_lanes = 16;
+    c->order = 1;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
@@ -498,7 +535,7 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 0 && cfg.lanes != 4 && cfg.lanes != 8) ||
         cfg.pipe_workers < 0 || (cfg.pipe_lanes != 0 && cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16 &&
                                   cfg.pipe_lanes != 32) ||
-        (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1))
+        (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1) || (cfg.order != 0 && cfg.order != 1))
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
