@@ -395,12 +395,11 @@ typedef struct asyrk_server_config {
                               sweeps its measured contraction per sweep predicts it still needs
                               to reach tol, plus one, at most inner_sweeps; 1: always
                               inner_sweeps */
-    int32_t order;         /* row order of the busy rounds (the plain loop): 1 (default)
-                              without replacement, the slice scheme of asyrk_solve_params.order
-                              = 1 per system (worker w of R_s owns rows [w L, (w+1) L),
-                              L = ceil(m / R_s), visited in a fresh keyed permutation each sweep:
-                              fewer sweeps to tol); 0: rows drawn with replacement as in the
-                              pipelined rounds, which always sample */
+    int32_t order;         /* row order of every round: 1 (default) without replacement, the
+                              slice scheme of asyrk_solve_params.order = 1 per system (worker w
+                              of R_s owns rows [w L, (w+1) L), L = ceil(m / R_s), visited in a
+                              fresh keyed permutation each sweep: fewer sweeps to tol), in busy
+                              and pipelined rounds alike; 0: rows drawn with replacement */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {

@@ -330,12 +330,15 @@ __device__ __forceinline__ uint64_t process_ticket(
 // order; the memory system keeps one wave's accesses to one address in order,
 // so the worker still sees its own update (the one-worker pipelined run
 // equals the sequential oracle to 1e-12).
-template <int VK, int XK, int G, int UPL = Upl<G>::value>
-__device__ __forceinline__ void run_tickets_pipelined(
+//
+// The row of a ticket comes from `pick(j, i)`, which returns the ticket's
+// random words and sets its bucket row i: the Philox draw for sampled rows
+// (SampledPick), or a row given outright with uniform = 1 (a slice walk).
+template <int VK, int XK, int G, int UPL, class Pick>
+__device__ __forceinline__ void run_rows_pipelined(
     const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
-    const double2 *side, int64_t j, int64_t j_end, int64_t step, uint32_t stream_id, uint32_t k0,
-    uint32_t k1, int uniform, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma,
-    int gl) {
+    const double2 *side, int64_t j, int64_t j_end, int64_t step, int uniform,
+    typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl, const Pick pick) {
     using T = VT<VK>;
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     using H = typename T::hdr_t;
@@ -405,8 +408,8 @@ __device__ __forceinline__ void run_tickets_pipelined(
     };
 
     // prologue: ticket j in full, ticket j + step's locator
-    U4 u = draw(j, stream_id, k0, k1);
-    uint32_t i = bucket_of(u.a, u.b, (uint32_t)rows.m);
+    uint32_t i;
+    U4 u = pick(j, i);
     const uint8_t *rec;
     int nnz;
     locate_nb(rows, i, rec, nnz);
@@ -424,8 +427,8 @@ __device__ __forceinline__ void run_tickets_pipelined(
         inv_w = (X)h.inv_w;
     }
     // (tickets drawn past the end have valid rows and are simply not used)
-    U4 u1 = draw(j + step, stream_id, k0, k1);
-    uint32_t i1 = bucket_of(u1.a, u1.b, (uint32_t)rows.m);
+    uint32_t i1;
+    U4 u1 = pick(j + step, i1);
     RowLoc l1 = locator_load(i1);
 
     for (;;) {
@@ -454,8 +457,8 @@ __device__ __forceinline__ void run_tickets_pipelined(
         fetch_units(rec1, (nnz1 + U - 1) / U, un1);
         double2 sd1{0.0, 0.0};
         if constexpr (SIDE) sd1 = gload<double2>(side + i1);
-        const U4 u2 = draw(jn + step, stream_id, k0, k1);
-        const uint32_t i2 = bucket_of(u2.a, u2.b, (uint32_t)rows.m);
+        uint32_t i2;
+        const U4 u2 = pick(jn + step, i2);
         const RowLoc l2 = locator_load(i2);
         // 3. gather-dot: the first chunk from registers (waiting for these
         // gathers only), then further chunks of long rows, re-read after it so
@@ -501,6 +504,26 @@ __device__ __forceinline__ void run_tickets_pipelined(
     }
 }
 
+// Sampled rows: ticket j's Philox draw and its bucket.
+struct SampledPick {
+    uint32_t m, stream_id, k0, k1;
+    __device__ __forceinline__ U4 operator()(int64_t j, uint32_t &i) const {
+        const U4 u = draw(j, stream_id, k0, k1);
+        i = bucket_of(u.a, u.b, m);
+        return u;
+    }
+};
+
+template <int VK, int XK, int G, int UPL = Upl<G>::value>
+__device__ __forceinline__ void run_tickets_pipelined(
+    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
+    const double2 *side, int64_t j, int64_t j_end, int64_t step, uint32_t stream_id, uint32_t k0,
+    uint32_t k1, int uniform, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma,
+    int gl) {
+    run_rows_pipelined<VK, XK, G, UPL>(rows, x, xsh, side, j, j_end, step, uniform, gamma, gl,
+                                       SampledPick{(uint32_t)rows.m, stream_id, k0, k1});
+}
+
 // Keyed bijection of [0, L) for the slice scheme: with b the smallest width
 // such that 2^b >= L, mask = 2^b - 1 and h = (b + 1) / 2, apply
 //   y <- ((y ^ (y >> h)) * (u0 | 1) + u1) & mask
@@ -519,5 +542,27 @@ __device__ __forceinline__ uint32_t slice_perm(uint32_t k, uint32_t L, const U4 
     } while (y >= L);
     return y;
 }
+
+// The slice walk of one worker as tickets 0, 1, ...: ticket t is position
+// k = t mod L of sweep sw0 + t / L in the worker's keyed permutation of its
+// rows [start, start + L) (L >= 1).
+struct SlicePick {
+    int64_t start, sw0;
+    uint32_t L, worker, k0, k1;
+    __device__ __forceinline__ U4 operator()(int64_t t, uint32_t &i) const {
+        uint64_t sw, k;
+        if ((uint64_t)t >> 32 == 0) {
+            sw = (uint32_t)t / L;
+            k = (uint32_t)t - (uint32_t)sw * L;
+        } else {
+            sw = (uint64_t)t / L;
+            k = (uint64_t)t - sw * L;
+        }
+        sw += (uint64_t)sw0;
+        const U4 u = philox4x32_10((uint32_t)(sw & 0xffffffffu), (uint32_t)(sw >> 32), worker, 0x5C4E3D2Bu, k0, k1);
+        i = (uint32_t)(start + slice_perm((uint32_t)k, L, u));
+        return U4{0u, 0u, 0u, 0u};
+    }
+};
 
 }  // namespace asyrk

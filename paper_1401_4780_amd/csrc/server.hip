@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void srv_zero_kernel(const TableHead *th, cons
 // stay in registers.  PIPE: the pipelined worker loop, for rounds with few
 // workers (latency-bound); the plain loop saturates the atomic unit better
 // when many are active.
-template <int G, bool PIPE>
+template <int G, bool PIPE, bool SLICES = false>
 __device__ __forceinline__ void srv_sweep_body(const TableHead *th, const SlotDesc *sl) {
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
@@ -120,7 +120,17 @@ __device__ __forceinline__ void srv_sweep_body(const TableHead *th, const SlotDe
     const int s = find_slot(th->nact, worker, [&](int k) { return sl[k].w_off; });
     const SlotDesc d = sl[s];  // a copy: the scatter cannot be taken to alias it
     const int64_t w = worker - d.w_off;
-    if constexpr (PIPE) {
+    if constexpr (PIPE && SLICES) {
+        // the slice walk (see srv_sweep_slices_kernel) as a ticket stream
+        const int64_t m = d.rows.m;
+        const int64_t L = (m + d.R - 1) / d.R;
+        const int64_t start = w * L;
+        const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
+        if (Lw == 0) return;
+        run_rows_pipelined<ASYRK_F32, ASYRK_F64, G, (G < 16 ? 16 / G : 1)>(
+            d.rows, d.d, d.xshift, d.side, 0, (d.t_end - d.t_begin) / m * Lw, 1, 1, d.gamma, gl,
+            SlicePick{start, d.t_begin / m, (uint32_t)Lw, (uint32_t)w, d.key0, d.key1});
+    } else if constexpr (PIPE) {
         run_tickets_pipelined<ASYRK_F32, ASYRK_F64, G, (G < 16 ? 16 / G : 1)>(d.rows, d.d, d.xshift, d.side, d.t_begin + w, d.t_end, d.R,
                                                                0u, d.key0, d.key1, 0, d.gamma, gl);
     } else {
@@ -169,9 +179,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
 
 // Pipelined loop: its rounds hold at most a few thousand workers, so it may
 // use the registers of two tickets without an occupancy bound.
-template <int G>
+template <int G, bool SLICES>
 __global__ __launch_bounds__(256) void srv_sweep_pipe_kernel(const TableHead *th, const SlotDesc *sl) {
-    srv_sweep_body<G, true>(th, sl);
+    srv_sweep_body<G, true, SLICES>(th, sl);
 }
 
 __global__ __launch_bounds__(256) void srv_axpy_kernel(const TableHead *th, const SlotDesc *sl) {
@@ -419,12 +429,20 @@ hipError_t launch_zero_and_sweep(const asyrk_server *s, const RoundGroup &g, hip
     const int64_t workers = pipe ? std::min<int64_t>(s->cfg.max_workers, s->cfg.pipe_workers) : s->cfg.max_workers;
     const int block = pipe ? 64 : 256;  // light rounds: one wave per block, spread over the CUs
     const dim3 grid((unsigned)((workers * G + block - 1) / block));
-    if (pipe) {
+    if (pipe && s->cfg.order == 1) {
         switch (G) {
-            case 4: hipLaunchKernelGGL(srv_sweep_pipe_kernel<4>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
-            case 8: hipLaunchKernelGGL(srv_sweep_pipe_kernel<8>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
-            case 16: hipLaunchKernelGGL(srv_sweep_pipe_kernel<16>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
-            case 32: hipLaunchKernelGGL(srv_sweep_pipe_kernel<32>, grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<4, true>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<8, true>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<16, true>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 32: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<32, true>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (pipe) {
+        switch (G) {
+            case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<4, false>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<8, false>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<16, false>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
+            case 32: hipLaunchKernelGGL(HIP_KERNEL_NAME(srv_sweep_pipe_kernel<32, false>), grid, dim3(block), 0, st, g.d_head, g.d_slots); break;
             default: return hipErrorInvalidValue;
         }
     } else if (s->cfg.order == 1) {
