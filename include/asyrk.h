@@ -131,7 +131,8 @@ typedef struct asyrk_solve_params {
                                 same arithmetic and reads of x, two dependent memory
                                 round trips per ticket; faster when few workers are in
                                 flight, slower when the atomic unit is saturated); needs
-                                ASYNC, UPDATE_ALL, order 0, no trace.  0 = plain.
+                                ASYNC, UPDATE_ALL, no trace (with order 1 each worker's
+                                slice walk is its ticket stream).  0 = plain.
                                 -1 (set by asyrk_solve_params_init) = the autotuned
                                 choice when the autotuner ran at this R and G, else
                                 pipelined for R <= 8192 where allowed */

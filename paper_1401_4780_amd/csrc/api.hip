@@ -831,7 +831,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         return ASYRK_ERR_INVALID_ARG;
     if (p.order != 0 && p.order != 1) return ASYRK_ERR_INVALID_ARG;
     if (p.pipeline < -1 || p.pipeline > 1 || p.reserved != 0) return ASYRK_ERR_INVALID_ARG;
-    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL || p.order != 0 || p.trace))
+    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL || p.trace))
         return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
@@ -857,7 +857,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R, p.update == ASYRK_UPDATE_ONE));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     if (p.pipeline == -1) {
-        const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && p.order == 0 && !p.trace;
+        const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && !p.trace;
         const bool tuned_here = tuned && G == tuned;
         p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
     }

@@ -94,11 +94,44 @@ __global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
     }
 }
 
+// The same slice walks, each fed to the software-pipelined worker loop as a
+// stream of tickets (asynchronous, all-coordinate sweeps without a trace).
+template <int VK, int XK, int G>
+__global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs a) {
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t worker = wave * (64 / G) + (lane / G);
+    if (worker >= a.R) return;
+    const int64_t m = a.rows.m;
+    const int64_t L = (m + a.R - 1) / a.R;
+    const int64_t start = worker * L;
+    const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
+    if (Lw == 0) return;
+    run_rows_pipelined<VK, XK, G, Upl<G>::value>(
+        a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, 0, (a.t_end - a.t_begin) / m * Lw, 1, 1,
+        (X)a.gamma, gl, SlicePick{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1});
+}
+
 template <int VK, int XK>
 static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
     const int64_t threads = a.R * G;
-    const int block = threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256;
+    const int block = a.pipe ? 64 : (threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256);
     const int64_t grid = (threads + block - 1) / block;
+    if (a.pipe) {
+        switch (G) {
+            case 1: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
+            case 4: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
+            case 16: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
+            case 32: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
+            case 64: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (G) {
         case 1: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
         case 2: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;

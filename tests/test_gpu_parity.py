@@ -510,6 +510,33 @@ def test_pipelined_single_worker_matches_oracle(lanes, dtype):
     sysm.close()
 
 
+@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16")])
+def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype):
+    """One asynchronous worker walking its slice (all rows) through the
+    pipelined loop is the oracle's one-worker slice scheme: 1e-12, ragged rows
+    with three multi-chunk ones, several sweeps, and a resume at a sweep
+    boundary that continues the same walk."""
+    rng = np.random.default_rng(6)
+    lens = rng.integers(1, 38, 900)
+    lens[[7, 200, 899]] = 300
+    s = synth.ragged_rows(900, 450, lens, seed=6, dtype=dtype)
+    _say(f"pipelined single-worker slices lanes={lanes} values={dtype}")
+    ref = oracle_run(s, 0.8, 5, 9, slices=True, workers=1)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=0.8, sweeps=5, seed=9, in_flight=1, lanes=lanes,
+                      order="slices", pipeline=True, history=8)
+    assert st["status"] == "OK" and st["pipelined"] == 1
+    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
+    torch = _torch()
+    x3 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    st = sysm.solve(x3, 0.8, 2, 9, in_flight=1, lanes=lanes, order="slices", pipeline=True)
+    sysm.solve(x3, 0.8, 3, 9, in_flight=1, lanes=lanes, order="slices", pipeline=True,
+               ticket0=st["next_ticket"])
+    assert np.linalg.norm(x3.cpu().numpy() - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    sysm.close()
+
+
 PIPE_CASES = {
     "f32_ragged": (lambda: synth.serving_system(31, 30_000, 7_500), "f32"),
     "bf16_fixed": (lambda: synth.uniform_rows(30_000, 7_500, 16, seed=8, dtype="bf16"), "f32"),
@@ -540,12 +567,17 @@ def test_pipelined_option_checks():
     s = synth.uniform_rows(500, 100, 5, seed=3, dtype="f32", require_full_columns=False)
     _say("pipelined option checks")
     sysm = make_system(s, device=False)
-    for kw in ({"mode": "replay"}, {"update": "one"}, {"order": "slices"}, {"trace": True}):
+    for kw in ({"mode": "replay"}, {"update": "one"}, {"trace": True}):
         with pytest.raises(P.AsyrkError) as ei:
             sysm.solve(np.zeros(s.n), 1.0, 1, 0, pipeline=True, **kw)
         assert ei.value.name == "UNSUPPORTED", kw
         st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, **kw)  # automatic choice: plain loop
         assert st["pipelined"] == 0, kw
+    # slice walks run in either loop; few workers take the pipelined one
+    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, order="slices", in_flight=64)
+    assert st["pipelined"] == 1
+    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, order="slices", in_flight=64, pipeline=False)
+    assert st["pipelined"] == 0
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64)
     assert st["pipelined"] == 1  # the rule for few workers
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64, pipeline=False)
