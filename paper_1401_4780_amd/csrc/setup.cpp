@@ -207,8 +207,10 @@ void build_alias(const double *w, int64_t m, double total, uint32_t *thresh, int
     std::unique_ptr<int32_t[]> lists(new int32_t[m]);
     // p_i, the default entries and the lists, over row ranges in parallel:
     // each range counts its small rows first, so that it knows where its
-    // share of either list starts, then fills it in index order.
-    const unsigned parts = threads_for(m);
+    // share of either list starts, then fills it in index order.  A few
+    // nanoseconds per row: threads pay for their start only from about 2^19
+    // rows on.
+    const unsigned parts = threads_for(m / 64);
     const int64_t chunk = (m + parts - 1) / parts;
     std::vector<int64_t> n_small(parts, 0);
     parallel_rows(m, parts, [&](int64_t lo, int64_t hi) {
