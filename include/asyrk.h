@@ -247,7 +247,9 @@ asyrk_status asyrk_create_augmented(asyrk_system **out, int64_t m, int64_t n, co
 /* Release every device and host resource of the system (NULL is accepted). */
 asyrk_status asyrk_destroy(asyrk_system *s);
 
-/* Replace b (double[m], finite) keeping A. */
+/* Replace b (double[m], finite; in the memory kind the system was created
+ * with, read during the call only) keeping A.  Device b is checked on the
+ * device.  INVALID_ARG for a non-finite entry, with the system's b unchanged. */
 asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b);
 
 /* Sizes and derived quantities of the system. */

@@ -553,13 +553,24 @@ asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *inf
 
 asyrk_status asyrk_set_rhs(asyrk_system *s, const double *b) {
     if (!s || !b) return ASYRK_ERR_INVALID_ARG;
-    std::vector<double> buf;
-    const double *hb = nullptr;
-    asyrk_status rc = to_host(s, s->mem, b, (size_t)s->m, buf, hb);
-    if (rc) return rc;
-    for (int64_t i = 0; i < s->m; ++i)
-        if (!std::isfinite(hb[i])) return ASYRK_ERR_INVALID_ARG;
-    HIP_OK(hipMemcpyAsync(s->d_b64, hb, (size_t)s->m * sizeof(double), hipMemcpyHostToDevice, s->st));
+    if (s->mem == ASYRK_MEM_DEVICE) {
+        // checked where it lies; only the verdict comes to the host
+        DevScratch tmp;
+        uint32_t *d_flag = nullptr;
+        HIP_OK(tmp.alloc((void **)&d_flag, sizeof(uint32_t)));
+        HIP_OK(hipMemsetAsync(d_flag, 0, sizeof(uint32_t), s->st));
+        HIP_OK(launch_check_finite_dev(b, s->m, d_flag, s->st));
+        HIP_OK(hipMemcpyAsync(s->h_pin, d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s->st));
+        HIP_OK(hipStreamSynchronize(s->st));
+        uint32_t flag = 0;
+        std::memcpy(&flag, s->h_pin, sizeof flag);
+        if (flag) return ASYRK_ERR_INVALID_ARG;
+        HIP_OK(hipMemcpyAsync(s->d_b64, b, (size_t)s->m * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    } else {
+        for (int64_t i = 0; i < s->m; ++i)
+            if (!std::isfinite(b[i])) return ASYRK_ERR_INVALID_ARG;
+        HIP_OK(hipMemcpyAsync(s->d_b64, b, (size_t)s->m * sizeof(double), hipMemcpyHostToDevice, s->st));
+    }
     HIP_OK(launch_set_rec_b(s->vk, s->rows, s->d_b64, s->st));
     if (s->d_side) HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
     HIP_OK(hipStreamSynchronize(s->st));

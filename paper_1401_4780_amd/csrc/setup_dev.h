@@ -28,6 +28,8 @@ enum : uint32_t {
 hipError_t launch_scan_rows_dev(int vk, int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const void *vals, const double *b, double *w, uint32_t *col_cnt, double *col_sq,
                                 uint32_t *flags, hipStream_t st);
+// kBadRhs or-ed into *flags if any of v[0..n-1] is not finite.
+hipError_t launch_check_finite_dev(const double *v, int64_t n, uint32_t *flags, hipStream_t st);
 // out[0] = max_j col_cnt[j], out[1] = bits of max_j col_sq[j]; out zero on entry.
 hipError_t launch_col_max_dev(const uint32_t *col_cnt, const double *col_sq, int64_t n, unsigned long long *out,
                               hipStream_t st);

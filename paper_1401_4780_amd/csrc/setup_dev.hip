@@ -120,7 +120,20 @@ __global__ __launch_bounds__(256) void write_records_kernel(int64_t m, const int
         for (uint8_t *p = u; p < r + stride; p += 16) *reinterpret_cast<uint4 *>(p) = uint4{0u, 0u, 0u, 0u};
 }
 
+__global__ __launch_bounds__(256) void check_finite_kernel(const double *v, int64_t n, uint32_t *flags) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !__builtin_isfinite(v[i]);
+    if (bad) atomicOr(flags, kBadRhs);
+}
+
 }  // namespace
+
+hipError_t launch_check_finite_dev(const double *v, int64_t n, uint32_t *flags, hipStream_t st) {
+    const int64_t blocks = grid_for(n) < 1024 ? grid_for(n) : 1024;
+    hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, st, v, n, flags);
+    return hipGetLastError();
+}
 
 hipError_t launch_scan_rows_dev(int vk, int64_t m, int64_t n, const int64_t *row_ptr, const int32_t *col,
                                 const void *vals, const double *b, double *w, uint32_t *col_cnt, double *col_sq,

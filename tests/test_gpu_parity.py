@@ -395,6 +395,20 @@ def test_set_rhs():
     st = sysm.solve(x, 1.0, 60, 1, tol=1e-12, x_ref=x2)
     assert st["status"] == "OK"
     sysm.close()
+    # device b: checked on the device; a non-finite entry is refused and
+    # leaves the system's b as it was
+    sysm = make_system(s, device=True)
+    sysm.set_rhs(_dev(b2))
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=60, seed=1)
+    assert np.linalg.norm(x - x2) <= 1e-10 * np.linalg.norm(x2)
+    bad = b2.copy()
+    bad[777] = np.inf
+    with pytest.raises(P.AsyrkError) as ei:
+        sysm.set_rhs(_dev(bad))
+    assert ei.value.name == "INVALID_ARG"
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=60, seed=1)
+    assert np.linalg.norm(x - x2) <= 1e-10 * np.linalg.norm(x2)
+    sysm.close()
 
 
 # ------------------------------------------------------------------ slice scheme, autotuner
