@@ -152,6 +152,9 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_server_poll(None, 1, None, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_take_completed(None, None, 0, None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_run(None, None)] == "INVALID_ARG"
+    size = C.c_int64(-1)
+    assert P.STATUS[L.asyrk_records_get(None, None, 0, C.byref(size))] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_set_rhs(None, x.ctypes.data)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_destroy(None)] == "OK"
 
 
