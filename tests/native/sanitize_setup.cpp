@@ -128,6 +128,41 @@ int main() {
                   ASYRK_ERR_INVALID_ARG);
         }
     }
+    // the alias table's classification pass runs over row ranges in parallel
+    // from about 2^19 rows on: the table must equal the sequential
+    // construction's (written out here from its definition), entry for entry
+    {
+        const int64_t m = 600000;
+        std::vector<double> w(m);
+        std::lognormal_distribution<double> ln(0.0, 1.5);
+        for (auto &x : w) x = ln(g);
+        std::vector<uint32_t> t;
+        std::vector<int32_t> al;
+        build_alias(w, t, al);
+        double total = 0.0;
+        for (double x : w) total = total + x;
+        std::vector<double> p(m);
+        std::vector<int32_t> small, large;
+        for (int64_t i = 0; i < m; ++i) {
+            p[i] = (w[i] * (double)m) / total;
+            (p[i] < 1.0 ? small : large).push_back((int32_t)i);
+        }
+        std::vector<uint32_t> t2(m, 0xffffffffu);
+        std::vector<int32_t> a2(m);
+        for (int64_t i = 0; i < m; ++i) a2[i] = (int32_t)i;
+        while (!small.empty() && !large.empty()) {
+            const int32_t sm = small.back();
+            small.pop_back();
+            const int32_t l = large.back();
+            large.pop_back();
+            t2[sm] = (uint32_t)(uint64_t)(p[sm] * 4294967296.0);
+            a2[sm] = l;
+            p[l] = (p[l] + p[sm]) - 1.0;
+            (p[l] < 1.0 ? small : large).push_back(l);
+        }
+        CHECK(t == t2);
+        CHECK(al == a2);
+    }
     // invalid inputs
     Sys s = make(g, 50, 40, 2, 6);
     SetupResult r;
