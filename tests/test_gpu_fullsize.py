@@ -22,6 +22,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 import paper_1401_4780_amd as P
@@ -116,3 +117,38 @@ def test_fullsize_slices_and_algorithm1(big):
     assert st["status"] == "OK", st
     assert np.linalg.norm(x.cpu().numpy() - s.x_star) <= 1.05e-6 * np.linalg.norm(s.x_star)
     _say(f"full-size Algorithm 1: {st['sweeps_done']} sweeps, lanes {st['lanes']}, {st['rows_per_s']:.3e} rows/s")
+
+
+# ------------------------------------------------------------------ precision workload at its size
+
+def test_fullsize_precision_paths_reach_1e10():
+    """8M x 2M, 16 entries per row (the precision workload): BF16 values with
+    the FP64 iterate, and FP32 values with FP32 sweeps and FP64 refinement,
+    both reach ||x - x*|| / ||x*|| <= 1e-10 against the exact solution of the
+    stored matrix; the library's residual equals the oracle's within the
+    forward error of the two summation orders."""
+    import torch
+    _say("full-size precision: generate")
+    s64 = synth.uniform_rows(8_000_000, 2_000_000, 16, seed=3, dtype="f64")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    for dt, kw in (("bf16", dict(iter_dtype="f64")), ("f32", dict(refine=True))):
+        s = synth.as_dtype(s64, dt)
+        _say(f"full-size precision: {dt} {kw}")
+        sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n, dtype=dt)
+        x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+        st = sysm.solve(x, 1.0, 400, 1, tol=1e-10, x_ref=d(s.x_star), **kw)
+        assert st["status"] == "OK", st
+        xh = x.cpu().numpy()
+        assert np.linalg.norm(xh - s.x_star) <= 1.05e-10 * np.linalg.norm(s.x_star)
+        # near the solution b - A x cancels: the two sums (lane-parallel
+        # FMAs on the device, sequential on the host) may differ by their
+        # forward error, |dr_i| <= 2 k u (|A| |x|)_i per row, so ||r||^2 by
+        # at most 2 ||r|| ||dr|| + ||dr||^2
+        n2_o = oracle.residual(s.row_ptr, s.col, s.val64, s.b, xh)
+        absAx = sp.csr_matrix((np.abs(s.val64), s.col, s.row_ptr), shape=(s.m, s.n)) @ np.abs(xh)
+        dr = 2 * 16 * np.finfo(np.float64).eps * np.linalg.norm(absAx)
+        assert abs(sysm.residual(x) - n2_o) <= 2 * np.sqrt(n2_o) * dr + dr * dr
+        _say(f"full-size precision {dt}: {st['sweeps_done']} sweeps")
+        sysm.close()
+        del x
+        torch.cuda.empty_cache()
