@@ -152,3 +152,31 @@ def test_fullsize_precision_paths_reach_1e10():
         sysm.close()
         del x
         torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ skewed workload at its size
+
+def test_fullsize_skewed_threshold():
+    """2M x 500k, lognormal rows, Zipf(1.1) columns (the skewed workload):
+    Corollary 1 allows only a few workers (the hot column's norm dominates
+    lambda_max); the default R stays inside and converges, while R = 16384,
+    far outside, diverges, which the solve reports as DIVERGED: the paper's
+    threshold effect at full size."""
+    import torch
+    _say("full-size skewed: generate")
+    s = synth.skewed_rows(2_000_000, 500_000, seed=2, dtype="f32")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    sysm = P.System(d(s.row_ptr), d(s.col), d(s.val), d(s.b), n=s.n)
+    info = sysm.info()
+    R0 = info["default_in_flight"]
+    assert 1 <= R0 <= 16, info
+    x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    st = sysm.solve(x, 1.0, 5, 5, x_ref=d(s.x_star), history=8)
+    assert st["status"] == "OK" and st["in_flight"] == R0
+    h = st["history"]
+    assert h[5] < 0.5 * h[0], h
+    x.zero_()
+    st = sysm.solve(x, 1.0, 5, 5, x_ref=d(s.x_star), in_flight=16384, history=8)
+    assert st["status"] == "DIVERGED", st
+    _say(f"full-size skewed: R0={R0} err after 5 sweeps {h[5]:.3f}; R=16384 diverged after {st['sweeps_done']}")
+    sysm.close()
