@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ASYRK_ABI_VERSION 1
+#define ASYRK_ABI_VERSION 2
 
 typedef struct asyrk_system asyrk_system; /* opaque; owns all device-side data */
 
@@ -107,7 +107,11 @@ typedef struct asyrk_solve_params {
                                 solve stops when its relative residual is <= 1e-6 or stops
                                 halving per sweep (at most 40), later ones run as many sweeps */
     uint32_t stream_id;      /* RNG stream (third counter word) */
-    int32_t trace;           /* 1: time each worker's read-to-write window (tau_obs) */
+    int32_t trace;           /* 1: measure the staleness of eq. (3) in every sweep kernel and
+                                worker loop (see asyrk_solve_stats.tau_obs_mean): a completion
+                                counter that each wave advances once per step, read by every
+                                wave on one step in 16 just before its gathers and right
+                                after its scatter */
     int64_t ticket0;         /* first ticket (resume: pass stats.next_ticket) */
     volatile const int32_t *cancel; /* nullable HOST pointer, polled at every check */
     double *history;         /* nullable HOST array: monitored error at the start and after
@@ -131,12 +135,14 @@ typedef struct asyrk_solve_params {
                                 same arithmetic and reads of x, two dependent memory
                                 round trips per ticket; faster when few workers are in
                                 flight, slower when the atomic unit is saturated); needs
-                                ASYNC, UPDATE_ALL, no trace (with order 1 each worker's
-                                slice walk is its ticket stream).  0 = plain.
+                                ASYNC and UPDATE_ALL (with order 1 each worker's slice
+                                walk is its ticket stream).  0 = plain.
                                 -1 (set by asyrk_solve_params_init) = the autotuned
                                 choice when the autotuner ran at this R and G, else
                                 pipelined for R <= 8192 where allowed */
-    int32_t reserved;        /* must be 0 */
+    int32_t skip_resid;      /* 0 (default): fill asyrk_solve_stats.final_resid, which costs one
+                                FP64 residual pass unless the monitor already measured the
+                                residual of the returned x; 1: leave it NaN */
 } asyrk_solve_params;
 
 /* Slice permutation (order = 1), for sweep s (= ticket / m) and worker w:
@@ -163,10 +169,23 @@ typedef struct asyrk_solve_stats {
     double rows_per_s;         /* row_updates / sweep_seconds */
     double final_err;          /* last monitored error (NaN if never checked) */
     double tau_design;         /* R - 1 */
-    double tau_obs_mean;       /* trace: mean read-to-write window x global row rate */
-    double tau_obs_max;        /* trace: max read-to-write window x global row rate */
-    double window_ns_mean;     /* trace: mean read-to-write window in ns */
-    double window_ns_max;      /* trace: max read-to-write window in ns */
+    double tau_obs_mean;       /* trace: eq. (3)'s delay j - k(j) measured on sampled tickets: the
+                                  row updates other workers completed between the ticket's read
+                                  of x and its scatter (completion counter, advanced once per
+                                  wave and step after the scatter is issued); mean over samples */
+    double tau_obs_max;        /* trace: the largest sampled delay */
+    double window_ns_mean;     /* trace: mean time from the sampled read to the scatter, ns */
+    double window_ns_max;      /* trace: its maximum, ns */
+    int64_t tau_samples;       /* trace: number of sampled (wave, step) pairs */
+    double lambda_max_est;     /* lambda_max(A^T A) behind tau_max_corollary: the power-iteration
+                                  value once asyrk_lambda_max has run on this system, else
+                                  max(Gaussian-ensemble estimate, largest column norm^2) */
+    double tau_max_corollary;  /* Corollary 1: the largest tau with
+                                  2 e lambda_max_est (tau + 1) / ||A||_F^2 <= 1, or -1 if none */
+    double final_resid;        /* ||b - A x|| / ||b|| of the returned x in FP64 (the quantity of the
+                                  paper's figures, Section "Experiments"); NaN with skip_resid */
+    int32_t lambda_source;     /* 1: lambda_max_est is a power-iteration value; 0: the estimate */
+    int32_t reserved2;
 } asyrk_solve_stats;
 
 typedef struct asyrk_system_info {
@@ -236,13 +255,23 @@ asyrk_status asyrk_create(asyrk_system **out, int64_t m, int64_t n, const int64_
  * (size n + m; zeta, phi > 0; the paper's best choice is phi = 1 and
  * zeta = sigma_min(A) / sqrt(2)).  Arguments as in asyrk_create for A and b;
  * the created system's unknown is z = (x, y) and its x block equals
- * zeta * x_LS, so the least-squares solution is z[0:n] / zeta.  Entries
+ * zeta * x_LS; asyrk_augmented_solution returns x_LS = z[0:n] / zeta.  Entries
  * phi * a_ij and -zeta are rounded to vals_dtype.  Errors as asyrk_create;
  * ZERO_ROW also for an empty column of A.
  */
 asyrk_status asyrk_create_augmented(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
                                     const int32_t *col_idx, const void *vals, int32_t vals_dtype,
                                     const double *b, double zeta, double phi, int32_t mem, void *stream);
+
+/*
+ * The least-squares solution of a system made by asyrk_create_augmented, from
+ * the augmented unknown z = (x, y) (double[n + m], e.g. asyrk_solve's result):
+ * x_out[k] = z[k] / zeta for k < n (Section "Extension to Inconsistent
+ * Systems": the x block of the augmented solution is zeta x_LS).  z and x_out
+ * (double[n], n of the original A) are in the system's memory kind and may
+ * alias.  Errors: INVALID_ARG (s not augmented, NULL pointers), DEVICE.
+ */
+asyrk_status asyrk_augmented_solution(asyrk_system *s, const double *z, double *x_out);
 
 /* Release every device and host resource of the system (NULL is accepted). */
 asyrk_status asyrk_destroy(asyrk_system *s);
@@ -287,7 +316,9 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
 
 /*
  * Residual in FP64 over the stored values promoted exactly:
- *   r = b - A x (x double[n]); r_out nullable double[m]; *norm2_out = ||r||^2.
+ *   r = b - A x (x double[n]); r_out nullable double[m]; *norm2_out = ||r||^2,
+ * the squared residual norm the paper plots against epochs (Section
+ * "Experiments").  x and r_out are in the system's memory kind.
  * Errors: INVALID_ARG, DEVICE.
  */
 asyrk_status asyrk_residual(asyrk_system *s, const double *x, double *r_out, double *norm2_out);
@@ -306,7 +337,8 @@ asyrk_status asyrk_sample_rows(asyrk_system *s, uint64_t seed, uint32_t stream_i
  * from a Philox-seeded start; *lambda_out gets the Rayleigh quotient after
  * iters steps (iters >= 1).  tau_max_out (nullable): the largest tau with
  * 2 e lambda_max (tau + 1) / ||A||_F^2 <= 1 (Corollary 1; ||A||_F^2 = m for
- * normalized rows), or -1 when none.
+ * normalized rows), or -1 when none.  The system keeps the value for the
+ * lambda_max_est and tau_max_corollary of later solves.
  */
 asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
                               double *tau_max_out);
@@ -444,7 +476,8 @@ asyrk_status asyrk_server_destroy(asyrk_server *s);
 /* Queue one request: HOST arrays (CSR as in asyrk_create, FP32 values, FP64
  * b), tol > 0 on ||b - A x||/||b||, Philox seed.  The arrays are copied
  * (packed on the calling thread); *request_id receives its id.
- * Errors: INVALID_ARG, ZERO_ROW, OOM (larger than the whole budget). */
+ * Errors: INVALID_ARG, ZERO_ROW, OOM (larger than the whole budget), or the
+ * server's sticky device failure. */
 asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const int64_t *row_ptr,
                                  const int32_t *col_idx, const float *vals, const double *b, double tol,
                                  uint64_t seed, int64_t *request_id);
@@ -452,7 +485,10 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
 /* Serve one round group: collect its previous round and retire finished
  * requests, add uploaded requests, admit what fits, launch its next round
  * (returns without waiting for it).  n_active / n_queued (nullable) receive
- * the counts afterwards.  Errors: DEVICE. */
+ * the counts afterwards.  Errors: DEVICE (or OOM) from a HIP call; such a
+ * failure is sticky: this and every later progress and submit call, and poll
+ * of every request not finished before it, return it (finished results stay
+ * readable; destroy the server). */
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued);
 
 /* The round loop on the calling thread: progress() until *stop becomes
@@ -465,7 +501,8 @@ asyrk_status asyrk_server_run(asyrk_server *s, const volatile int32_t *stop);
 
 /* Result of a finished request: x_out (nullable, HOST double[n]) and stats
  * (nullable).  Returns the request's final status, ASYRK_PENDING while it is
- * queued or active, INVALID_ARG for an unknown or already-polled id. */
+ * queued or active, INVALID_ARG for an unknown or already-polled id, and the
+ * server's sticky device failure for a request it left unfinished. */
 asyrk_status asyrk_server_poll(asyrk_server *s, int64_t request_id, double *x_out,
                                asyrk_request_stats *st);
 

@@ -53,7 +53,7 @@ class SolveParams(C.Structure):
         ("check_every", C.c_int32), ("refine", C.c_int32), ("inner_sweeps", C.c_int64),
         ("stream_id", C.c_uint32), ("trace", C.c_int32), ("ticket0", C.c_int64),
         ("cancel", C.c_void_p), ("history", C.c_void_p), ("history_cap", C.c_int64),
-        ("iter_dtype", C.c_int32), ("order", C.c_int32), ("pipeline", C.c_int32), ("reserved", C.c_int32),
+        ("iter_dtype", C.c_int32), ("order", C.c_int32), ("pipeline", C.c_int32), ("skip_resid", C.c_int32),
     ]
 
 
@@ -65,7 +65,9 @@ class SolveStats(C.Structure):
         ("seconds", C.c_double), ("sweep_seconds", C.c_double),
         ("rows_per_s", C.c_double), ("final_err", C.c_double), ("tau_design", C.c_double),
         ("tau_obs_mean", C.c_double), ("tau_obs_max", C.c_double), ("window_ns_mean", C.c_double),
-        ("window_ns_max", C.c_double),
+        ("window_ns_max", C.c_double), ("tau_samples", C.c_int64), ("lambda_max_est", C.c_double),
+        ("tau_max_corollary", C.c_double), ("final_resid", C.c_double), ("lambda_source", C.c_int32),
+        ("reserved2", C.c_int32),
     ]
 
 
@@ -140,6 +142,7 @@ def lib():
     L.asyrk_solve_params_init.restype = None
     L.asyrk_create.argtypes = [P, i64, i64, P, P, P, i32, P, i32, P]
     L.asyrk_create_augmented.argtypes = [P, i64, i64, P, P, P, i32, P, dbl, dbl, i32, P]
+    L.asyrk_augmented_solution.argtypes = [P, P, P]
     L.asyrk_destroy.argtypes = [P]
     L.asyrk_set_rhs.argtypes = [P, P]
     L.asyrk_system_info_get.argtypes = [P, P]
@@ -163,7 +166,7 @@ def lib():
     L.asyrk_server_take_completed.argtypes = [P, P, i64, P]
     L.asyrk_now.argtypes = []
     L.asyrk_now.restype = dbl
-    for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
+    for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_augmented_solution", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_records_get",
                  "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
@@ -249,8 +252,8 @@ class System:
 
     def __init__(self, row_ptr, col, val, b, *, n=None, dtype=None, stream=None, augmented=None):
         """augmented=(zeta, phi): build the paper's consistent augmented system
-        for least squares of an inconsistent A x = b (size n + m); the
-        least-squares x is then z[:n] / zeta (see least_squares_x)."""
+        for least squares of an inconsistent A x = b (size n + m); solve it for
+        z and read the least-squares x with least_squares_x(z)."""
         L = lib()
         self.device = _is_torch(row_ptr) and row_ptr.is_cuda
         _expect(row_ptr, self.device, "int64", "row_ptr")
@@ -282,13 +285,27 @@ class System:
                                           self.vals_dtype, _ptr(b), float(zeta), float(phi), mem, stream)
             _check(rc, "asyrk_create_augmented")
             self.a_shape = (self.m, self.n)
-            self.zeta = float(zeta)
             self.m = self.n = self.m + self.n
         self._h = h
 
-    def least_squares_x(self, z):
-        """x_LS = z[:n] / zeta for a system built with augmented=(zeta, phi)."""
-        return z[: self.a_shape[1]] / self.zeta
+    def least_squares_x(self, z, out=None):
+        """The least-squares solution of the original A x = b from the augmented
+        unknown z (asyrk_augmented_solution); a system built with augmented=..."""
+        if not hasattr(self, "a_shape"):
+            raise TypeError("least_squares_x: not an augmented system")
+        _expect(z, self.device, "float64", "z")
+        _expect_len(z, self.n, "z")
+        n = self.a_shape[1]
+        if out is None:
+            if self.device:
+                import torch
+                out = torch.empty(n, dtype=torch.float64, device=z.device)
+            else:
+                out = np.empty(n, dtype=np.float64)
+        _expect(out, self.device, "float64", "out")
+        _expect_len(out, n, "out")
+        _check(lib().asyrk_augmented_solution(self._h, _ptr(z), _ptr(out)), "asyrk_augmented_solution")
+        return out
 
     # -- lifetime
     def close(self):
@@ -383,7 +400,7 @@ class System:
     def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
               update="all", lanes=0, in_flight=0, tol=0.0, x_ref=None, check_every=1,
               refine=False, inner_sweeps=0, stream_id=0, trace=False, ticket0=0, cancel=None,
-              history=0, iter_dtype=None, order="replacement", pipeline=None) -> dict:
+              history=0, iter_dtype=None, order="replacement", pipeline=None, final_resid=True) -> dict:
         """Run from x (float64, overwritten with the result).  Returns the stats
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
         "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
@@ -410,6 +427,7 @@ class System:
         p.iter_dtype = {None: -1, "f32": F32, "f64": F64}[iter_dtype]
         p.order = {"replacement": 0, "slices": 1}[order]
         p.pipeline = -1 if pipeline is None else int(bool(pipeline))
+        p.skip_resid = 0 if final_resid else 1
         if cancel is not None:
             if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):
                 raise TypeError("cancel: expected a numpy int32 array")
@@ -428,8 +446,9 @@ class System:
         out["status"] = STATUS[rc]
         if hist is not None:
             out["history"] = hist[: st.history_len].copy()
-        if not math.isfinite(out["final_err"]):
-            out["final_err"] = float("nan")
+        for k in ("final_err", "final_resid"):
+            if not math.isfinite(out[k]):
+                out[k] = float("nan")
         return out
 
 

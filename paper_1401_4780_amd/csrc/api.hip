@@ -9,7 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "internal.h"
+#include "device.h"
 #include "setup.h"
 #include "setup_dev.h"
 
@@ -35,8 +35,12 @@ struct asyrk_system {
     double *d_part = nullptr;     // reduction partials
     double *d_scalar = nullptr;   // 4 device scalars
     double *h_pin = nullptr;      // 4 pinned host scalars
-    uint64_t *d_trace = nullptr;
-    int64_t trace_cap = 0;
+    uint64_t *d_trace = nullptr;  // staleness samples, kTraceWords per wave
+    int64_t trace_cap = 0;        // waves d_trace holds
+    uint64_t *d_tau = nullptr;    // the completion counter's shards (monotone, never reset)
+    double lambda_pi = 0.0;       // lambda_max by power iteration, once asyrk_lambda_max ran (else 0)
+    int64_t aug_n = 0;            // augmented system: columns of the original A (else 0)
+    double aug_zeta = 0.0;        // augmented system: its zeta
     int64_t device_bytes = 0;
     bool rec_b_dirty = false;
     int tuned_G[2] = {0, 0};      // autotuned lanes per row for F64 / F32 iterates (0 = none)
@@ -83,6 +87,7 @@ void free_system(asyrk_system *s) {
     (void)hipFree(s->d_part);
     (void)hipFree(s->d_scalar);
     (void)hipFree(s->d_trace);
+    (void)hipFree(s->d_tau);
     if (s->h_pin) (void)hipHostFree(s->h_pin);
     if (s->e0) (void)hipEventDestroy(s->e0);
     if (s->e1) (void)hipEventDestroy(s->e1);
@@ -202,9 +207,12 @@ double now_s() {
 
 }  // namespace
 
+// Staleness samples of the sweeps of one call, summed over launches.
+struct TraceSums {
+    double tau_max = 0.0, tau_sum = 0.0, count = 0.0, win_max = 0.0, win_sum = 0.0;
+};
 static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
-                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
-                               double *win_max_ticks, double *win_sum_ticks, double *win_cnt);
+                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s, TraceSums *tr);
 static asyrk_status create_from_device(asyrk_system **out, int64_t m, int64_t n, const int64_t *row_ptr,
                                        const int32_t *col, const void *vals, int32_t vals_dtype, const double *b,
                                        void *stream);
@@ -521,8 +529,26 @@ asyrk_status asyrk_create_augmented(asyrk_system **out, int64_t m, int64_t n, co
     AugCSR aug;
     rc = build_augmented(m, n, rp, cl, vl, vals_dtype, bb, zeta, phi, aug);
     if (rc) return rc;
-    return create_from_host(out, n + m, n + m, aug.row_ptr.data(), aug.col.data(), aug.vals.data(), vals_dtype,
-                            aug.b.data(), mem, stream);
+    rc = create_from_host(out, n + m, n + m, aug.row_ptr.data(), aug.col.data(), aug.vals.data(), vals_dtype,
+                          aug.b.data(), mem, stream);
+    if (rc) return rc;
+    (*out)->aug_n = n;
+    (*out)->aug_zeta = zeta;
+    return ASYRK_OK;
+}
+
+asyrk_status asyrk_augmented_solution(asyrk_system *s, const double *z, double *x_out) {
+    if (!s || !z || !x_out || s->aug_n <= 0) return ASYRK_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)s->aug_n * sizeof(double);
+    if (s->mem == ASYRK_MEM_DEVICE) {
+        HIP_OK(launch_divide(z, s->aug_zeta, x_out, s->aug_n, s->st));
+    } else {
+        HIP_OK(hipMemcpyAsync(s->d_x64, z, bytes, hipMemcpyHostToDevice, s->st));
+        HIP_OK(launch_divide(s->d_x64, s->aug_zeta, s->d_x64, s->aug_n, s->st));
+        HIP_OK(hipMemcpyAsync(x_out, s->d_x64, bytes, hipMemcpyDeviceToHost, s->st));
+    }
+    HIP_OK(hipStreamSynchronize(s->st));
+    return ASYRK_OK;
 }
 
 asyrk_status asyrk_system_info_get(const asyrk_system *s, asyrk_system_info *info) {
@@ -661,6 +687,7 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
     if (e != hipSuccess) return dev_fail(e);
     if (rc) return rc;
     *lambda_out = lam;
+    if (lam > 0.0 && std::isfinite(lam)) s->lambda_pi = lam;
     if (tau_max_out) {
         const double t = std::floor(s->fro2 / (2.0 * M_E * lam)) - 1.0;
         *tau_max_out = t >= 0 ? t : -1.0;
@@ -683,8 +710,9 @@ static asyrk_status tune_at(asyrk_system *s, int xk, int64_t R, double gamma, in
         for (int k = 0; k < 7; ++k) {
             const int G = cands[k];
             HIP_OK(launch_zero(s->d_x, s->n * s->xstride, s->st));
-            double gpu_s = 0.0, a = 0, b = 0, c = 0;
-            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &a, &b, &c);
+            double gpu_s = 0.0;
+            TraceSums unused;
+            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, 0x5eedull, 0, tickets, &gpu_s, &unused);
             if (rc) return rc;
             rate[pipe][k] = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
             top[pipe] = std::max(top[pipe], rate[pipe][k]);
@@ -779,8 +807,7 @@ asyrk_status asyrk_probe_scatter(int64_t n, int64_t count, int32_t dtype, int32_
 // ------------------------------------------------------------------- solve
 
 static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int xk, int G, int64_t R, double gamma,
-                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s,
-                               double *win_max_ticks, double *win_sum_ticks, double *win_cnt) {
+                               uint64_t seed, int64_t t_begin, int64_t t_end, double *gpu_s, TraceSums *tr) {
     SweepArgs a{};
     a.rows = s->rows;
     a.x = s->d_x;
@@ -797,8 +824,11 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     a.replay = p.mode == ASYRK_REPLAY;
     a.gamma = gamma;
     a.trace = p.trace ? s->d_trace : nullptr;
+    a.tau_ctr = p.trace ? s->d_tau : nullptr;
     a.slices = p.order;
     a.pipe = p.pipeline;
+    const int64_t waves = (R * G + 63) / 64;
+    if (p.trace) HIP_OK(launch_zero(s->d_trace, waves * kTraceWords * 8, s->st));
     HIP_OK(hipEventRecord(s->e0, s->st));
     if (p.order == 1)
         HIP_OK(launch_sweep_slices(s->vk, xk, G, a, s->st));
@@ -809,13 +839,16 @@ static asyrk_status run_sweeps(asyrk_system *s, const asyrk_solve_params &p, int
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, s->e0, s->e1));
     *gpu_s += ms * 1e-3;
-    if (p.trace && p.order == 0) {
-        std::vector<uint64_t> tr((size_t)R * 3);
-        HIP_OK(hipMemcpy(tr.data(), s->d_trace, tr.size() * 8, hipMemcpyDeviceToHost));
-        for (int64_t w = 0; w < R; ++w) {
-            *win_max_ticks = std::max(*win_max_ticks, (double)tr[3 * w]);
-            *win_sum_ticks += (double)tr[3 * w + 1];
-            *win_cnt += (double)tr[3 * w + 2];
+    if (p.trace) {
+        std::vector<uint64_t> w((size_t)waves * kTraceWords);
+        HIP_OK(hipMemcpy(w.data(), s->d_trace, w.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < waves; ++k) {
+            const uint64_t *o = w.data() + k * kTraceWords;
+            tr->tau_max = std::max(tr->tau_max, (double)o[0]);
+            tr->tau_sum += (double)o[1];
+            tr->count += (double)o[2];
+            tr->win_max = std::max(tr->win_max, (double)o[3]);
+            tr->win_sum += (double)o[4];
         }
     }
     return ASYRK_OK;
@@ -841,9 +874,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
         return ASYRK_ERR_INVALID_ARG;
     if (p.order != 0 && p.order != 1) return ASYRK_ERR_INVALID_ARG;
-    if (p.pipeline < -1 || p.pipeline > 1 || p.reserved != 0) return ASYRK_ERR_INVALID_ARG;
-    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL || p.trace))
-        return ASYRK_ERR_UNSUPPORTED;
+    if (p.pipeline < -1 || p.pipeline > 1 || (p.skip_resid != 0 && p.skip_resid != 1)) return ASYRK_ERR_INVALID_ARG;
+    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL)) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
     if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
@@ -868,7 +900,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     const int G = p.lanes ? p.lanes : (tuned ? tuned : auto_lanes(s, R, p.update == ASYRK_UPDATE_ONE));
     if (R > ((int64_t)1 << 26)) return ASYRK_ERR_INVALID_ARG;
     if (p.pipeline == -1) {
-        const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL && !p.trace;
+        const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL;
         const bool tuned_here = tuned && G == tuned;
         p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
     }
@@ -908,12 +940,17 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         HIP_OK(launch_build_side(s->vk, s->rows, s->d_b64, s->d_side, s->st));
     }
     if (p.trace) {
-        if (s->trace_cap < R) {
+        const int64_t waves = (R * G + 63) / 64;
+        if (s->trace_cap < waves) {
             (void)hipFree(s->d_trace);
             s->d_trace = nullptr;
             s->trace_cap = 0;
-            HIP_OK(hipMalloc((void **)&s->d_trace, (size_t)R * 3 * 8));
-            s->trace_cap = R;
+            HIP_OK(hipMalloc((void **)&s->d_trace, (size_t)waves * kTraceWords * 8));
+            s->trace_cap = waves;
+        }
+        if (!s->d_tau) {
+            HIP_OK(hipMalloc((void **)&s->d_tau, (size_t)kTauShards * kTauShardStride * 8));
+            HIP_OK(launch_zero(s->d_tau, (int64_t)kTauShards * kTauShardStride * 8, s->st));
         }
     }
     const bool monitor = p.tol > 0.0 || p.history_cap > 0 || p.cancel != nullptr;
@@ -923,7 +960,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     };
     const double t_setup = now_s();
 
-    double gpu_s = 0.0, wmax = 0.0, wsum = 0.0, wcnt = 0.0;
+    double gpu_s = 0.0;
+    TraceSums tr;
     asyrk_status result = ASYRK_OK;
     int64_t ticket = p.ticket0;
     int64_t done = 0;
@@ -939,8 +977,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         }
         while (done < sweeps) {
             const int64_t c = std::min<int64_t>(p.check_every, sweeps - done);
-            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &wmax, &wsum,
-                                         &wcnt);
+            asyrk_status rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + c * s->m, &gpu_s, &tr);
             if (rc) return rc;
             ticket += c * s->m;
             done += c;
@@ -989,14 +1026,13 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
             HIP_OK(launch_zero(s->d_x, s->n * s->xstride, s->st));
             const int64_t budget = std::min<int64_t>(inner, sweeps - done);
             if (!adaptive) {
-                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + budget * s->m, &gpu_s, &wmax, &wsum,
-                                &wcnt);
+                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + budget * s->m, &gpu_s, &tr);
                 if (rc) return rc;
                 ticket += budget * s->m;
                 done += budget;
             } else if (learned > 0) {
                 const int64_t k = std::min(learned, budget);
-                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + k * s->m, &gpu_s, &wmax, &wsum, &wcnt);
+                rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + k * s->m, &gpu_s, &tr);
                 if (rc) return rc;
                 ticket += k * s->m;
                 done += k;
@@ -1007,7 +1043,7 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
                 rc = fetch_scalar(s, kResidualBlocks, &r0);
                 if (rc) return rc;
                 for (int64_t k = 0; k < budget; ++k) {
-                    rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + s->m, &gpu_s, &wmax, &wsum, &wcnt);
+                    rc = run_sweeps(s, p, xk, G, R, gamma, seed, ticket, ticket + s->m, &gpu_s, &tr);
                     if (rc) return rc;
                     ticket += s->m;
                     done += 1;
@@ -1043,6 +1079,27 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         s->rec_b_dirty = false;
         if (result == ASYRK_OK && p.tol > 0.0 && !ok) result = ASYRK_ERR_NOT_CONVERGED;
     }
+    // ||b - A x|| / ||b|| of the returned iterate: the monitor's last value when
+    // it measured exactly that, else one FP64 residual pass
+    S.final_resid = NAN;
+    if (!p.skip_resid) {
+        const bool have = !mon.use_ref && (p.refine || done > 0 || monitor);
+        if (have) {
+            S.final_resid = S.final_err;
+        } else {
+            if (mon.use_ref) {
+                HIP_OK(launch_sumsq_diff(s->d_b64, 0, 0, nullptr, s->m, s->d_part, kResidualBlocks, s->st));
+                asyrk_status rc = fetch_scalar(s, kResidualBlocks, &mon.b_norm2);
+                if (rc) return rc;
+            }
+            double v = 0.0;
+            HIP_OK(launch_residual(s->vk, s->rows, s->d_b64, s->d_x64, 0, 0, nullptr, 0, s->d_part, kResidualBlocks,
+                                   s->st));
+            asyrk_status rc = fetch_scalar(s, kResidualBlocks, &v);
+            if (rc) return rc;
+            S.final_resid = mon.b_norm2 > 0 ? std::sqrt(v / mon.b_norm2) : std::sqrt(v);
+        }
+    }
     HIP_OK(hipMemcpyAsync(x, s->d_x64, (size_t)s->n * 8, d2h, s->st));
     HIP_OK(hipStreamSynchronize(s->st));
 
@@ -1053,17 +1110,23 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     (void)wall0;
     S.sweep_seconds = gpu_s;
     S.rows_per_s = gpu_s > 0 ? (double)S.row_updates / gpu_s : 0.0;
-    if (p.trace && wcnt > 0) {
+    if (p.trace && tr.count > 0) {
         int clock_khz = 0;
         int dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
         const double ns_per_tick = clock_khz > 0 ? 1e6 / clock_khz : 10.0;
-        S.window_ns_mean = wsum / wcnt * ns_per_tick;
-        S.window_ns_max = wmax * ns_per_tick;
-        S.tau_obs_mean = S.window_ns_mean * 1e-9 * S.rows_per_s;
-        S.tau_obs_max = S.window_ns_max * 1e-9 * S.rows_per_s;
+        S.tau_samples = (int64_t)tr.count;
+        S.tau_obs_mean = tr.tau_sum / tr.count;
+        S.tau_obs_max = tr.tau_max;
+        S.window_ns_mean = tr.win_sum / tr.count * ns_per_tick;
+        S.window_ns_max = tr.win_max * ns_per_tick;
     }
+    // Corollary 1's bound on tau for this system
+    S.lambda_source = s->lambda_pi > 0.0 ? 1 : 0;
+    S.lambda_max_est = S.lambda_source ? s->lambda_pi : std::max(lambda_mp(s), s->max_col_norm2);
+    const double tmax = std::floor(s->fro2 / (2.0 * M_E * S.lambda_max_est)) - 1.0;
+    S.tau_max_corollary = tmax >= 0.0 ? tmax : -1.0;
     if (st) *st = S;
     return result;
 }

@@ -156,6 +156,94 @@ __device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
         v = gload<typename T::val_t>(u + T::COLB + T::VB * e);
 }
 
+// ---------------------------------------------------------------- staleness
+//
+// The delay of eq. (3), measured: for a sampled ticket, the number of row
+// updates other waves completed between its read of x and its scatter
+// (j - k(j) in the paper's notation).  A completion counter is split over
+// kTauShards words, each on a line of its own.  Every worker counts its rows;
+// every kTauFlush steps a wave adds the rows its workers finished since the
+// last add to its shard (one atomic per wave per kTauFlush steps, after the
+// scatter), and a worker that runs out of tickets adds what it has left.
+// Every kTauPeriod-th step a wave reads the counter (the sum of the shards)
+// just before its gathers and again just before it issues its scatter, so a
+// lone worker measures exactly 0.  The reads are agent-scope atomic loads and
+// the adds agent-scope atomics on the same words, so a wave's later read sees
+// its own earlier adds.  Rows of other waves finished in the window but not
+// yet added are missed and rows finished earlier but added in the window are
+// counted: each sample is exact up to that backlog (at most kTauFlush steps
+// of each wave), and unbiased on average.  The workers of one wave step
+// together, so each also runs concurrently with up to 64/G - 1 updates of its
+// own wave that the counter does not include.
+constexpr int kTauShards = 16;
+constexpr int kTauShardStride = 32;  // u64 words between shards (256 B)
+constexpr int kTauPeriod = 64;       // steps between samples of one wave
+constexpr int kTauFlush = 4;         // steps between a wave's adds
+constexpr int kTraceWords = 8;       // per wave: {tau max, tau sum, samples, window max, window sum, 0, 0, 0}
+
+struct TauProbe {
+    const uint64_t *ctr;  // counter shards
+    bool sample;          // read the counter around this ticket
+    uint64_t c0, c1;      // counter before the gathers, before the scatter
+    uint64_t t0, t1;      // wall clock at those points
+};
+
+// per-wave accumulators (identical in every lane: the counter reads of one
+// instruction return one value to all lanes)
+struct TauAcc {
+    uint64_t tmax = 0, tsum = 0, tcnt = 0, wmax = 0, wsum = 0;
+};
+
+// The counter: every lane loads every shard (one address per instruction).
+__device__ __forceinline__ uint64_t tau_read(const uint64_t *ctr) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTauShards; ++k) s += load_agent(ctr + k * kTauShardStride);
+    return s;
+}
+
+__device__ __forceinline__ void tau_accumulate(TauAcc &acc, uint64_t c0, uint64_t c1, uint64_t t0, uint64_t t1) {
+    const uint64_t d = c1 - c0;  // each shard is read later at c1 than at c0: c1 >= c0
+    const uint64_t w = t1 - t0;
+    acc.tmax = d > acc.tmax ? d : acc.tmax;
+    acc.tsum += d;
+    acc.tcnt += 1;
+    acc.wmax = w > acc.wmax ? w : acc.wmax;
+    acc.wsum += w;
+}
+
+// A wave's add: the rows `mine` (< 8) its active group leaders finished since
+// their last add, summed bit by bit over ballots, added by the lowest active
+// lane to the wave's shard; every leader's count is then cleared.
+__device__ __forceinline__ void tau_flush_wave(uint64_t *ctr, int64_t wave, int gl, uint32_t &mine) {
+    const bool lead = gl == 0;
+    uint64_t total = 0;
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit)
+        total += (uint64_t)__popcll(__ballot(lead && ((mine >> bit) & 1u))) << bit;
+    const unsigned long long active = __ballot(1);
+    if ((int)__lane_id() == __ffsll(active) - 1 && total > 0)
+        atomic_add(ctr + (wave & (kTauShards - 1)) * kTauShardStride, total);
+    mine = 0;
+}
+
+// A leader's own remainder when it leaves the loop.
+__device__ __forceinline__ void tau_flush_leader(uint64_t *ctr, int64_t wave, int gl, uint32_t &mine) {
+    if (gl == 0 && mine > 0) atomic_add(ctr + (wave & (kTauShards - 1)) * kTauShardStride, (uint64_t)mine);
+    mine = 0;
+}
+
+__device__ __forceinline__ void tau_store(const TauAcc &acc, uint64_t *out, int64_t wave, int lane) {
+    if (lane == 0) {
+        uint64_t *o = out + wave * kTraceWords;
+        o[0] = acc.tmax;
+        o[1] = acc.tsum;
+        o[2] = acc.tcnt;
+        o[3] = acc.wmax;
+        o[4] = acc.wsum;
+    }
+}
+
 template <int G, class X>
 __device__ __forceinline__ X group_sum(X v) {
 #pragma unroll
@@ -172,16 +260,16 @@ template <int G> struct Upl { static constexpr int value = G >= 8 ? 1 : 8 / G; }
 // One ticket of one worker (a group of G lanes): draw the row, fetch its
 // record, gather-dot, step, atomic scatter.  XK: iterate dtype.  FP32 records
 // with an FP64 iterate read b_i and 1/w_i in FP64 from the side array (the
-// record header holds them in FP32).  Returns the read-to-write window in
-// clock ticks when `trace` is set.
-// Row i of a sweep given directly (no sampling): used by the slice scheme.
-// `alias_ok` = false keeps row i whatever its header says.
+// record header holds them in FP32).  With SAMPLED = false the row is
+// `given_row` (the slice scheme).  tp (nullable): when tp->sample is set, the
+// completion counter and the clock are read just before the gathers and
+// just before the scatter.
 template <int VK, int XK, int G, int UPL = Upl<G>::value, bool SAMPLED = true>
-__device__ __forceinline__ uint64_t process_ticket(
+__device__ __forceinline__ void process_ticket(
     const Rows &rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
     const double2 *side, int64_t j, uint32_t stream_id, uint32_t k0, uint32_t k1, int uniform,
     int update_one, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl,
-    int trace, uint32_t given_row = 0) {
+    TauProbe *tp, uint32_t given_row = 0) {
     using T = VT<VK>;
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     using H = typename T::hdr_t;
@@ -219,8 +307,10 @@ __device__ __forceinline__ uint64_t process_ticket(
         }
     }
 
-    uint64_t t0 = 0;
-    if (trace) t0 = wall_clock64();
+    if (tp && tp->sample) {
+        tp->c0 = tau_read(tp->ctr);
+        tp->t0 = wall_clock64();
+    }
 
     // a3: gather-dot over supp(a_i)
     X acc = (X)0;
@@ -269,6 +359,10 @@ __device__ __forceinline__ uint64_t process_ticket(
         inv_w = (X)h.inv_w;
     }
     const X r = acc - bi;
+    if (tp && tp->sample) {
+        tp->c1 = tau_read(tp->ctr);
+        tp->t1 = wall_clock64();
+    }
 
     // a5: lock-free scatter
     if (!update_one) {
@@ -306,7 +400,6 @@ __device__ __forceinline__ uint64_t process_ticket(
         const X s1 = gamma * (X)nnz * r * inv_w;
         atomic_add(xat(x, c, xsh), -s1 * (X)v);
     }
-    return trace ? wall_clock64() - t0 : 0;
 }
 
 // The tickets j0, j0 + step, ... < j_end of one worker with the steps of
@@ -334,11 +427,22 @@ __device__ __forceinline__ uint64_t process_ticket(
 // The row of a ticket comes from `pick(j, i)`, which returns the ticket's
 // random words and sets its bucket row i: the Philox draw for sampled rows
 // (SampledPick), or a row given outright with uniform = 1 (a slice walk).
-template <int VK, int XK, int G, int UPL, class Pick>
+//
+// TRACE: every kTauPeriod-th step the completion counter is read before the
+// gathers and again just before the scatter is issued (see TauProbe).  Both
+// reads sit in branches on the same wave-uniform step number, and their values
+// are taken where the loop waits anyway: the first with the gathers, the
+// second with the wait for the next ticket's record header (step 5), which
+// covers every load issued before the atomics.  Nothing is carried across
+// iterations unwaited (a loaded value live across the loop's back edge is
+// copied there, and the copy waits for everything issued before it, the
+// atomics included).
+template <int VK, int XK, int G, int UPL, bool TRACE = false, class Pick>
 __device__ __forceinline__ void run_rows_pipelined(
     const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
     const double2 *side, int64_t j, int64_t j_end, int64_t step, int uniform,
-    typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl, const Pick pick) {
+    typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl, const Pick pick,
+    uint64_t *tau_ctr = nullptr, int64_t wave = 0, TauAcc *tacc = nullptr) {
     using T = VT<VK>;
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     using H = typename T::hdr_t;
@@ -431,10 +535,22 @@ __device__ __forceinline__ void run_rows_pipelined(
     U4 u1 = pick(j + step, i1);
     RowLoc l1 = locator_load(i1);
 
+    // staleness samples (TRACE)
+    int64_t nstep = 0;
+    uint32_t mine = 0;  // this worker's rows not yet added to the counter
+
     for (;;) {
         const int64_t jn = j + step;
         const bool more = jn < j_end;
         const int nunits = (nnz + U - 1) / U;
+        const bool samp = TRACE && (nstep % kTauPeriod == 0);
+        uint64_t c0 = 0, c1 = 0, t0 = 0, t1 = 0;
+        if constexpr (TRACE) {
+            if (samp) {
+                c0 = tau_read(tau_ctr);
+                t0 = wall_clock64();
+            }
+        }
         // 1. this ticket's gathers
         X xv[UPL][U];
         gather_issue(un, 0, nnz, xv);
@@ -472,6 +588,12 @@ __device__ __forceinline__ void run_rows_pipelined(
             acc = gather_dot(t, base, nnz, tv, acc);
         }
         acc = group_sum<G>(acc);
+        if constexpr (TRACE) {
+            if (samp) {
+                c1 = tau_read(tau_ctr);
+                t1 = wall_clock64();
+            }
+        }
         const X s = gamma * (acc - bi) * inv_w;
         // 4. lock-free scatter
         chunk_scatter(un, 0, nnz, s);
@@ -480,10 +602,25 @@ __device__ __forceinline__ void run_rows_pipelined(
             fetch_chunk(rec, base, nunits, t);
             chunk_scatter(t, base, nnz, s);
         }
-        if (!more) break;
+        if constexpr (TRACE) {
+            ++mine;
+            if (nstep % kTauFlush == kTauFlush - 1) tau_flush_wave(tau_ctr, wave, gl, mine);
+            ++nstep;
+        }
+        if (!more) {
+            if constexpr (TRACE) {
+                if (samp) tau_accumulate(*tacc, c0, c1, t0, t1);
+                tau_flush_leader(tau_ctr, wave, gl, mine);
+            }
+            break;
+        }
         // 5. rotate: the next ticket becomes current
         if (resolve(u1, i1, rec1, nnz1, h1, un1)) {
             if constexpr (SIDE) sd1 = gload<double2>(side + i1);
+        }
+        if constexpr (TRACE) {
+            // the header wait above covered the counter loads issued before the atomics
+            if (samp) tau_accumulate(*tacc, c0, c1, t0, t1);
         }
         if constexpr (SIDE) {
             bi = sd1.x;
@@ -514,14 +651,15 @@ struct SampledPick {
     }
 };
 
-template <int VK, int XK, int G, int UPL = Upl<G>::value>
+template <int VK, int XK, int G, int UPL = Upl<G>::value, bool TRACE = false>
 __device__ __forceinline__ void run_tickets_pipelined(
     const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
     const double2 *side, int64_t j, int64_t j_end, int64_t step, uint32_t stream_id, uint32_t k0,
     uint32_t k1, int uniform, typename std::conditional<XK == ASYRK_F64, double, float>::type gamma,
-    int gl) {
-    run_rows_pipelined<VK, XK, G, UPL>(rows, x, xsh, side, j, j_end, step, uniform, gamma, gl,
-                                       SampledPick{(uint32_t)rows.m, stream_id, k0, k1});
+    int gl, uint64_t *tau_ctr = nullptr, int64_t wave = 0, TauAcc *tacc = nullptr) {
+    run_rows_pipelined<VK, XK, G, UPL, TRACE>(rows, x, xsh, side, j, j_end, step, uniform, gamma, gl,
+                                              SampledPick{(uint32_t)rows.m, stream_id, k0, k1}, tau_ctr,
+                                              wave, tacc);
 }
 
 // Keyed bijection of [0, L) for the slice scheme: with b the smallest width

@@ -52,9 +52,10 @@ struct SweepArgs {
     int32_t update_one;    // 1: Algorithm 1 single-coordinate step
     int32_t replay;        // 1: wait for the scatter before the next read
     double gamma;
-    uint64_t *trace;       // nullable: per worker {max window, sum window, count} in clock ticks
+    uint64_t *trace;       // nullable: staleness samples, kTraceWords words per wave (device.h)
+    uint64_t *tau_ctr;     // the completion counter's shards when trace is set
     int32_t slices;        // 1: without-replacement slice scheme (t_begin, t_end are sweep multiples)
-    int32_t pipe;          // 1: software-pipelined worker loop (asynchronous, all-coordinate, no trace)
+    int32_t pipe;          // 1: software-pipelined worker loop (asynchronous, all-coordinate)
 };
 
 // ---------------------------------------------------------------------------
@@ -117,6 +118,7 @@ hipError_t launch_zero(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_set_rec_b(int vk, const Rows &rows, const double *b64, hipStream_t st);
 hipError_t launch_scatter_rows(int vk, const Rows &rows, const double *y, double *z, hipStream_t st);
 hipError_t launch_scale(double *v, int64_t n, const double *norm2, hipStream_t st);
+hipError_t launch_divide(const double *z, double d, double *out, int64_t n, hipStream_t st);  // out = z / d
 hipError_t launch_random_fill(double *v, int64_t n, uint32_t k0, uint32_t k1, hipStream_t st);
 hipError_t launch_sample_rows(int vk, const Rows &rows, int64_t ticket0, int64_t count, uint32_t k0, uint32_t k1,
                               uint32_t stream_id, int uniform, int32_t *rows_out, int32_t *coords_out,

@@ -29,29 +29,31 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
 
     X *x = reinterpret_cast<X *>(a.x);
     const X gamma = (X)a.gamma;
-    uint64_t tr_max = 0, tr_sum = 0, tr_cnt = 0;
-    for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R) {
-        const uint64_t w = process_ticket<VK, XK, G>(a.rows, x, a.xshift, a.side, j, a.stream_id, a.key0, a.key1,
-                                                     a.uniform, a.update_one, gamma, gl,
-                                                     a.trace != nullptr);
+    TauAcc acc;
+    TauProbe tp{a.tau_ctr, false, 0, 0, 0, 0};
+    int64_t it = 0;
+    uint32_t mine = 0;
+    for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R, ++it) {
+        tp.sample = a.trace != nullptr && it % kTauPeriod == 0;
+        process_ticket<VK, XK, G>(a.rows, x, a.xshift, a.side, j, a.stream_id, a.key0, a.key1, a.uniform,
+                                  a.update_one, gamma, gl, a.trace ? &tp : nullptr);
         if (a.trace) {
-            tr_max = w > tr_max ? w : tr_max;
-            tr_sum += w;
-            tr_cnt += 1;
+            if (tp.sample) tau_accumulate(acc, tp.c0, tp.c1, tp.t0, tp.t1);
+            ++mine;
+            if (it % kTauFlush == kTauFlush - 1) tau_flush_wave(a.tau_ctr, wave, gl, mine);
         }
         if (a.replay) __threadfence();
     }
-    if (a.trace && gl == 0) {
-        a.trace[3 * worker + 0] = tr_max;
-        a.trace[3 * worker + 1] = tr_sum;
-        a.trace[3 * worker + 2] = tr_cnt;
+    if (a.trace) {
+        tau_flush_leader(a.tau_ctr, wave, gl, mine);
+        tau_store(acc, a.trace, wave, lane);
     }
 }
 
 // The same worker loop with the steps of consecutive tickets overlapped
-// (run_tickets_pipelined): for asynchronous, all-coordinate sweeps without
-// tracing.
-template <int VK, int XK, int G>
+// (run_tickets_pipelined): for asynchronous, all-coordinate sweeps.  TRACE:
+// the instance that samples the staleness.
+template <int VK, int XK, int G, bool TRACE>
 __global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -59,8 +61,11 @@ __global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t worker = wave * (64 / G) + (lane / G);
     if (worker >= a.R) return;
-    run_tickets_pipelined<VK, XK, G>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, a.t_begin + worker, a.t_end,
-                                     a.R, a.stream_id, a.key0, a.key1, a.uniform, (X)a.gamma, gl);
+    TauAcc acc;
+    run_tickets_pipelined<VK, XK, G, Upl<G>::value, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side,
+                                                           a.t_begin + worker, a.t_end, a.R, a.stream_id, a.key0,
+                                                           a.key1, a.uniform, (X)a.gamma, gl, a.tau_ctr, wave, &acc);
+    if constexpr (TRACE) tau_store(acc, a.trace, wave, lane);
 }
 
 // Without-replacement slice scheme (the paper's experiments): worker w owns
@@ -79,24 +84,37 @@ __global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
     const int64_t L = (m + a.R - 1) / a.R;
     const int64_t start = worker * L;
     const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
-    if (Lw == 0) return;
     X *x = reinterpret_cast<X *>(a.x);
     const X gamma = (X)a.gamma;
-    for (int64_t sw = a.t_begin / m; sw < a.t_end / m; ++sw) {
+    TauAcc acc;
+    TauProbe tp{a.tau_ctr, false, 0, 0, 0, 0};
+    int64_t it = 0;
+    uint32_t mine = 0;
+    for (int64_t sw = a.t_begin / m; sw < a.t_end / m && Lw > 0; ++sw) {
         const U4 u = philox4x32_10((uint32_t)((uint64_t)sw & 0xffffffffu), (uint32_t)((uint64_t)sw >> 32),
                                    (uint32_t)worker, 0x5C4E3D2Bu, a.key0, a.key1);
-        for (int64_t k = 0; k < Lw; ++k) {
+        for (int64_t k = 0; k < Lw; ++k, ++it) {
             const uint32_t i = (uint32_t)(start + slice_perm((uint32_t)k, (uint32_t)Lw, u));
+            tp.sample = a.trace != nullptr && it % kTauPeriod == 0;
             process_ticket<VK, XK, G, Upl<G>::value, false>(a.rows, x, a.xshift, a.side, 0, 0u, 0u, 0u, 1, 0, gamma,
-                                                             gl, 0, i);
+                                                             gl, a.trace ? &tp : nullptr, i);
+            if (a.trace) {
+                if (tp.sample) tau_accumulate(acc, tp.c0, tp.c1, tp.t0, tp.t1);
+                ++mine;
+                if (it % kTauFlush == kTauFlush - 1) tau_flush_wave(a.tau_ctr, wave, gl, mine);
+            }
             if (a.replay) __threadfence();
         }
+    }
+    if (a.trace) {
+        tau_flush_leader(a.tau_ctr, wave, gl, mine);
+        tau_store(acc, a.trace, wave, lane);
     }
 }
 
 // The same slice walks, each fed to the software-pipelined worker loop as a
-// stream of tickets (asynchronous, all-coordinate sweeps without a trace).
-template <int VK, int XK, int G>
+// stream of tickets (asynchronous, all-coordinate sweeps).
+template <int VK, int XK, int G, bool TRACE>
 __global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs a) {
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -108,41 +126,57 @@ __global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs 
     const int64_t L = (m + a.R - 1) / a.R;
     const int64_t start = worker * L;
     const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
-    if (Lw == 0) return;
-    run_rows_pipelined<VK, XK, G, Upl<G>::value>(
-        a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, 0, (a.t_end - a.t_begin) / m * Lw, 1, 1,
-        (X)a.gamma, gl, SlicePick{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1});
+    TauAcc acc;
+    if (Lw > 0)
+        run_rows_pipelined<VK, XK, G, Upl<G>::value, TRACE>(
+            a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, 0, (a.t_end - a.t_begin) / m * Lw, 1, 1,
+            (X)a.gamma, gl, SlicePick{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1},
+            a.tau_ctr, wave, &acc);
+    if constexpr (TRACE) tau_store(acc, a.trace, wave, lane);
+}
+
+// Calls f(std::integral_constant<int, G>) for a lane-group width G in
+// {1, 2, 4, ..., 64}, then returns the launch status.
+template <class F>
+static hipError_t dispatch_lanes(int G, F &&f) {
+    switch (G) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 16: f(std::integral_constant<int, 16>{}); break;
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// The pipelined loop serves the latency-bound regime (few workers): one
+// wave per block spreads those workers over as many CUs as there are waves
+// instead of packing four waves onto each CU's memory pipeline.
+static void sweep_geometry(const SweepArgs &a, int G, int64_t *grid, int *block) {
+    const int64_t threads = a.R * G;
+    *block = a.pipe ? 64 : (threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256);
+    *grid = (threads + *block - 1) / *block;
 }
 
 template <int VK, int XK>
 static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
-    const int64_t threads = a.R * G;
-    const int block = a.pipe ? 64 : (threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256);
-    const int64_t grid = (threads + block - 1) / block;
-    if (a.pipe) {
-        switch (G) {
-            case 1: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
-            case 4: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
-            case 8: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
-            case 16: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
-            case 32: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
-            case 64: hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (G) {
-        case 1: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
-        case 32: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
-        case 64: hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    int64_t grid;
+    int block;
+    sweep_geometry(a, G, &grid, &block);
+    if (a.pipe && a.trace)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, true>), dim3(grid), dim3(block), 0, st, a);
+        });
+    if (a.pipe)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, false>), dim3(grid), dim3(block), 0, st, a);
+        });
+    return dispatch_lanes(G, [&](auto g) {
+        hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, decltype(g)::value>), dim3(grid), dim3(block), 0, st, a);
+    });
 }
 
 hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStream_t st) {
@@ -163,36 +197,20 @@ hipError_t launch_sweep_slices(int vk, int xk, int G, const SweepArgs &a, hipStr
 
 template <int VK, int XK>
 static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
-    const int64_t threads = a.R * G;
-    // The pipelined loop serves the latency-bound regime (few workers): one
-    // wave per block spreads those workers over as many CUs as there are
-    // waves instead of packing four waves onto each CU's memory pipeline.
-    const int block = a.pipe ? 64 : (threads < 256 ? (int)(((threads + 63) / 64) * 64) : 256);
-    const int64_t grid = (threads + block - 1) / block;
-    if (a.pipe) {
-        switch (G) {
-            case 1: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
-            case 4: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
-            case 8: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
-            case 16: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
-            case 32: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
-            case 64: hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (G) {
-        case 1: hipLaunchKernelGGL((sweep_kernel<VK, XK, 1>), dim3(grid), dim3(block), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((sweep_kernel<VK, XK, 2>), dim3(grid), dim3(block), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((sweep_kernel<VK, XK, 4>), dim3(grid), dim3(block), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((sweep_kernel<VK, XK, 8>), dim3(grid), dim3(block), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((sweep_kernel<VK, XK, 16>), dim3(grid), dim3(block), 0, st, a); break;
-        case 32: hipLaunchKernelGGL((sweep_kernel<VK, XK, 32>), dim3(grid), dim3(block), 0, st, a); break;
-        case 64: hipLaunchKernelGGL((sweep_kernel<VK, XK, 64>), dim3(grid), dim3(block), 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    int64_t grid;
+    int block;
+    sweep_geometry(a, G, &grid, &block);
+    if (a.pipe && a.trace)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, true>), dim3(grid), dim3(block), 0, st, a);
+        });
+    if (a.pipe)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, false>), dim3(grid), dim3(block), 0, st, a);
+        });
+    return dispatch_lanes(G, [&](auto g) {
+        hipLaunchKernelGGL((sweep_kernel<VK, XK, decltype(g)::value>), dim3(grid), dim3(block), 0, st, a);
+    });
 }
 
 hipError_t launch_sweep(int vk, int xk, int G, const SweepArgs &a, hipStream_t st) {
@@ -486,6 +504,16 @@ __global__ __launch_bounds__(256) void scale_kernel(double *v, int64_t n, const 
 
 hipError_t launch_scale(double *v, int64_t n, const double *norm2, hipStream_t st) {
     hipLaunchKernelGGL(scale_kernel, dim3(vec_grid(n)), dim3(256), 0, st, v, n, norm2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void divide_kernel(const double *z, double d, double *out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += stride) out[c] = z[c] / d;
+}
+
+hipError_t launch_divide(const double *z, double d, double *out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(divide_kernel, dim3(vec_grid(n)), dim3(256), 0, st, z, d, out, n);
     return hipGetLastError();
 }
 

@@ -382,6 +382,9 @@ struct asyrk_server {
     std::atomic<int64_t> n_active{0};  // admitted and not finished, for other threads
     int64_t workers_in_use = 0;        // R over admitted requests not yet finished
     asyrk_server_stats stats{};
+    // the first device failure of a round: sticky, every later progress,
+    // submit and poll of an unfinished request returns it
+    std::atomic<int> fault{ASYRK_OK};
 };
 
 namespace {
@@ -615,6 +618,7 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
                                  const int32_t *col_idx, const float *vals, const double *b, double tol,
                                  uint64_t seed, int64_t *request_id) {
     if (!s || !request_id || !(tol > 0.0) || !std::isfinite(tol)) return ASYRK_ERR_INVALID_ARG;
+    if (s->fault.load() != ASYRK_OK) return (asyrk_status)s->fault.load();
     auto r = std::unique_ptr<Request>(new (std::nothrow) Request());
     if (!r) return ASYRK_ERR_OOM;
     asyrk_status rc = validate_system(m, n, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack);
@@ -738,8 +742,10 @@ asyrk_status collect_round(asyrk_server *s, RoundGroup &g) {
     }
     (void)ms;
     // ---- bookkeeping and retirement: every finished x is copied out, then one wait
+    // (every device call comes before any request leaves g.active, so a
+    // failure leaves the group as it was)
     uint8_t *base = s->arena.base;
-    std::vector<std::unique_ptr<Request>> keep, out;
+    std::vector<char> retire((size_t)nact, 0);
     for (int k = 0; k < nact; ++k) {
         std::unique_ptr<Request> &r = g.active[k];
         const int ns = r->next_sweeps;
@@ -755,7 +761,7 @@ asyrk_status collect_round(asyrk_server *s, RoundGroup &g) {
             r->status = conv ? ASYRK_OK : (bad ? ASYRK_ERR_DIVERGED : ASYRK_ERR_NOT_CONVERGED);
             r->x.resize(r->n);
             SRV_OK(hipMemcpyAsync(r->x.data(), base + r->off_x, r->n * 8, hipMemcpyDeviceToHost, g.st));
-            out.push_back(std::move(r));
+            retire[k] = 1;
         } else {
             // Size the next round from this one: RK contracts the residual by
             // a roughly constant factor per sweep, so the sweeps still needed
@@ -769,12 +775,15 @@ asyrk_status collect_round(asyrk_server *s, RoundGroup &g) {
                     nxt = (int)std::min<double>(cfg.inner_sweeps, std::max(1.0, std::ceil(need) + 1.0));
             }
             r->next_sweeps = nxt;
-            keep.push_back(std::move(r));
         }
     }
+    bool any_out = false;
+    for (int k = 0; k < nact; ++k) any_out |= retire[k] != 0;
+    if (any_out) SRV_OK(hipStreamSynchronize(g.st));
+    std::vector<std::unique_ptr<Request>> keep, out;
+    for (int k = 0; k < nact; ++k) (retire[k] ? out : keep).push_back(std::move(g.active[k]));
     g.active.swap(keep);
     if (!out.empty()) {
-        SRV_OK(hipStreamSynchronize(g.st));
         const double t = now_s();
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &r : out) {
@@ -794,8 +803,18 @@ asyrk_status collect_round(asyrk_server *s, RoundGroup &g) {
 
 extern "C" {
 
+static asyrk_status server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued);
+
 asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
     if (!s) return ASYRK_ERR_INVALID_ARG;
+    const int f = s->fault.load();
+    if (f != ASYRK_OK) return (asyrk_status)f;
+    const asyrk_status rc = server_progress(s, n_active, n_queued);
+    if (rc != ASYRK_OK) s->fault.store(rc);
+    return rc;
+}
+
+static asyrk_status server_progress(asyrk_server *s, int32_t *n_active, int32_t *n_queued) {
     const asyrk_server_config &cfg = s->cfg;
     // The two groups take turns: collect this group's previous round while
     // the other group's round computes, admit into this group, launch its
@@ -1036,7 +1055,11 @@ asyrk_status asyrk_server_poll(asyrk_server *s, int64_t request_id, double *x_ou
     {
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->done.find(request_id);
-        if (it == s->done.end()) return s->live.count(request_id) ? ASYRK_PENDING : ASYRK_ERR_INVALID_ARG;
+        if (it == s->done.end()) {
+            if (!s->live.count(request_id)) return ASYRK_ERR_INVALID_ARG;
+            const int f = s->fault.load();
+            return f != ASYRK_OK ? (asyrk_status)f : ASYRK_PENDING;
+        }
         r = std::move(it->second);
         s->done.erase(it);
         s->live.erase(request_id);

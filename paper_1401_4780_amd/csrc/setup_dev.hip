@@ -1,5 +1,5 @@
 // Device-side setup for systems handed over in device memory: validation,
-// row weights and column statistics (Section 2's sampling needs
+// row weights and column statistics (the row sampling of Section 1 needs
 // w_i = ||a_i||^2 for every row, Corollary 1's bound the largest column norm),
 // then the row records, written from the caller's CSR arrays without a round
 // trip through host memory.  One thread per row in both passes.

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_function():
     assert "asyrk_create" in names and "asyrk_solve" in names and "asyrk_residual" in names
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
-    assert L.asyrk_abi_version() == 1
+    assert L.asyrk_abi_version() == 2
 
 
 def _c_layout(struct, fields):
@@ -64,6 +64,7 @@ def test_status_strings_and_defaults():
     L.asyrk_solve_params_init(C.byref(p))
     assert (p.mode, p.sampling, p.update, p.check_every, p.in_flight, p.lanes) == (0, 0, 0, 1, 0, 0)
     assert p.iter_dtype == -1  # -1 = default; 0 is ASYRK_F64
+    assert p.skip_resid == 0 and p.pipeline == -1
 
 
 def _create(rp, col, val, b, n, dtype=P.F32, mem=P.MEM_HOST):
@@ -145,6 +146,7 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_create_augmented(None, 1, 1, None, None, None, 0, None, 1.0, 1.0, 0,
                                              None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_lambda_max(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_augmented_solution(None, x.ctypes.data, x.ctypes.data)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_destroy(None)] == "OK"
     assert P.STATUS[L.asyrk_probe_copy(0, 1, C.byref(v))] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_server_create(None, None)] == "INVALID_ARG"

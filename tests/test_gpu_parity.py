@@ -300,13 +300,89 @@ def test_refinement_reaches_1e10(dtype, inner):
     sysm.close()
 
 
-def test_trace_reports_staleness():
-    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
-    _say("trace tau_obs")
+# Staleness (eq. (3)): tau_obs is the number of row updates other workers
+# completed between a sampled ticket's read of x and its scatter, counted by
+# a completion counter every wave advances after each step.
+
+@pytest.mark.parametrize("pipeline,order", [(False, "replacement"), (True, "replacement"),
+                                            (False, "slices"), (True, "slices")])
+def test_trace_lone_worker_sees_no_other_update(pipeline, order):
+    """One worker: nobody else completes an update while its ticket is in
+    flight, so every sampled delay is exactly 0 (in every worker loop)."""
+    s = synth.uniform_rows(20_000, 5_000, 20, seed=1, dtype="f32")
+    _say(f"trace R=1 pipeline={pipeline} order={order}")
     sysm = make_system(s, device=True)
-    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=3, seed=1, in_flight=4096, trace=True)
-    assert st["window_ns_mean"] > 0 and st["window_ns_max"] >= st["window_ns_mean"]
-    assert 0 < st["tau_obs_mean"] < 1e7 and st["tau_design"] == 4095
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=1, trace=True,
+                      pipeline=pipeline, order=order)
+    assert st["pipelined"] == int(pipeline)
+    # one sample every 16 tickets of the one worker
+    assert st["tau_samples"] == -(-s.m // 16)
+    assert st["tau_obs_max"] == 0 and st["tau_obs_mean"] == 0, st
+    assert st["window_ns_mean"] > 0
+    sysm.close()
+
+
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_trace_staleness_grows_with_workers(pipeline):
+    """More workers in flight, more updates land inside one ticket's window:
+    the measured delay grows with R and stays of the order of R - 1 (each
+    other worker finishes about one row per ticket time)."""
+    s = synth.uniform_rows(200_000, 50_000, 20, seed=1, dtype="f32")
+    sysm = make_system(s, device=True)
+    means = []
+    for R in (16, 256, 4096):
+        _say(f"trace R={R} pipeline={pipeline}")
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=2, seed=R, in_flight=R, trace=True,
+                          pipeline=pipeline)
+        assert st["pipelined"] == int(pipeline)
+        assert st["tau_samples"] > 0 and st["tau_obs_max"] >= st["tau_obs_mean"] > 0, st
+        # bounds that hold for any schedule the hardware picks: a window sees
+        # at least a few other rows and far fewer than all rows of the sweep
+        assert 0.05 * (R - 1) <= st["tau_obs_mean"] <= 8 * R, (R, st["tau_obs_mean"])
+        means.append(st["tau_obs_mean"])
+    assert means[0] < means[1] < means[2], means
+    sysm.close()
+
+
+def test_traced_pipelined_solve_converges():
+    """The traced pipelined loop computes the same method: it reaches 1e-6."""
+    s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
+    _say("traced pipelined solve to 1e-6")
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=60, seed=4, tol=1e-6, in_flight=2048, trace=True,
+                      pipeline=True)
+    assert st["status"] == "OK" and st["pipelined"] == 1, st
+    assert np.linalg.norm(x - s.x_star) <= 1e-6 * np.linalg.norm(s.x_star)
+    assert st["tau_design"] == 2047 and st["tau_samples"] > 0
+    sysm.close()
+
+
+def test_stats_report_corollary_bound_and_final_residual():
+    """The solve reports Corollary 1's bound (estimate, then the power
+    iteration's value once it ran) and the FP64 residual of the returned x,
+    equal to the oracle's residual of that x."""
+    s = synth.uniform_rows(3000, 600, 7, seed=8, dtype="f64")
+    _say("stats: corollary bound, final residual")
+    sysm = make_system(s, device=True)
+    fro2 = float(np.sum(s.val64 ** 2))
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=3, seed=2, in_flight=8)
+    info = sysm.info()
+    assert st["lambda_source"] == 0
+    assert st["lambda_max_est"] == max(info["lambda_mp"], info["max_col_norm2"])
+    assert st["tau_max_corollary"] == math.floor(fro2 / (2 * math.e * st["lambda_max_est"])) - 1
+    n2, _ = oracle.residual(s.row_ptr, s.col, s.val64, s.b, x, want_r=True)
+    rel = math.sqrt(n2 / float(np.dot(s.b, s.b)))
+    assert abs(st["final_resid"] - rel) <= 1e-12 * rel, (st["final_resid"], rel)
+    lam, tau = sysm.lambda_max(iters=200, seed=1)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=3, in_flight=8, final_resid=False)
+    assert st["lambda_source"] == 1 and st["lambda_max_est"] == lam and st["tau_max_corollary"] == tau
+    assert math.isnan(st["final_resid"])
+    # residual monitor: the final residual is the monitor's last value
+    xd = _dev(np.zeros(s.n))
+    st = sysm.solve(xd, 1.0, 4, 5, tol=1e-30)
+    n2, _ = oracle.residual(s.row_ptr, s.col, s.val64, s.b, xd.cpu().numpy(), want_r=True)
+    rel = math.sqrt(n2 / float(np.dot(s.b, s.b)))
+    assert st["final_resid"] == st["final_err"] and abs(st["final_resid"] - rel) <= 1e-12 * rel
     sysm.close()
 
 
@@ -581,12 +657,15 @@ def test_pipelined_option_checks():
     s = synth.uniform_rows(500, 100, 5, seed=3, dtype="f32", require_full_columns=False)
     _say("pipelined option checks")
     sysm = make_system(s, device=False)
-    for kw in ({"mode": "replay"}, {"update": "one"}, {"trace": True}):
+    for kw in ({"mode": "replay"}, {"update": "one"}):
         with pytest.raises(P.AsyrkError) as ei:
             sysm.solve(np.zeros(s.n), 1.0, 1, 0, pipeline=True, **kw)
         assert ei.value.name == "UNSUPPORTED", kw
         st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, **kw)  # automatic choice: plain loop
         assert st["pipelined"] == 0, kw
+    # tracing keeps the loop the solve would run without it
+    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64, trace=True)
+    assert st["pipelined"] == 1 and st["tau_samples"] > 0
     # slice walks run in either loop; few workers take the pipelined one
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, order="slices", in_flight=64)
     assert st["pipelined"] == 1
@@ -635,6 +714,25 @@ def test_async_augmented_reaches_least_squares():
     st = sysm.solve(z, 1.0, 3000, 3, tol=1e-13, check_every=10)
     x = sysm.least_squares_x(z).cpu().numpy()
     assert np.linalg.norm(x - x_ls) <= 1e-8 * np.linalg.norm(x_ls), (st["status"], st["sweeps_done"])
+    # the library's x_LS is z[:n] / zeta of the same z, to the last bit
+    np.testing.assert_array_equal(x, z[: s.n].cpu().numpy() / zeta)
+    sysm.close()
+
+
+def test_augmented_solution_host_memory_and_checks():
+    s, b = _inconsistent(300, 80, 6, 23)
+    zeta = 0.37
+    _say("augmented solution, host arrays")
+    sysm = P.System(s.row_ptr, s.col, s.val, b, n=s.n, augmented=(zeta, 1.0))
+    z = np.random.default_rng(1).standard_normal(s.n + s.m)
+    np.testing.assert_array_equal(sysm.least_squares_x(z), z[: s.n] / zeta)
+    plain = P.System(s.row_ptr, s.col, s.val, s.b, n=s.n)
+    with pytest.raises(TypeError):
+        plain.least_squares_x(np.zeros(s.n))
+    out = np.empty(s.n)
+    rc = P.lib().asyrk_augmented_solution(plain._h, np.zeros(s.n).ctypes.data, out.ctypes.data)
+    assert P.STATUS[rc] == "INVALID_ARG"
+    plain.close()
     sysm.close()
 
 
