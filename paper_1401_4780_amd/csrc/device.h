@@ -165,9 +165,10 @@ __device__ __forceinline__ void load_entry(const uint8_t *rec, int pos, int &c,
 // every kTauFlush steps a wave adds the rows its workers finished since the
 // last add to its shard (one atomic per wave per kTauFlush steps, after the
 // scatter), and a worker that runs out of tickets adds what it has left.
-// Every kTauPeriod-th step a wave reads the counter (the sum of the shards)
-// just before its gathers and again just before it issues its scatter, so a
-// lone worker measures exactly 0.  The reads are agent-scope atomic loads and
+// On steps kTauFlush, kTauFlush + kTauPeriod, ... of a launch (the first
+// after every wave has added once) a wave reads the counter (the sum of the
+// shards) just before its gathers and again just before it issues its
+// scatter, so a lone worker measures exactly 0.  The reads are agent-scope atomic loads and
 // the adds agent-scope atomics on the same words, so a wave's later read sees
 // its own earlier adds.  Rows of other waves finished in the window but not
 // yet added are missed and rows finished earlier but added in the window are
@@ -199,6 +200,19 @@ __device__ __forceinline__ uint64_t tau_read(const uint64_t *ctr) {
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kTauShards; ++k) s += load_agent(ctr + k * kTauShardStride);
+    return s;
+}
+
+// The same read in two halves: the loads, and later their sum (so that the
+// wave need not wait for them where they are issued).
+__device__ __forceinline__ void tau_issue(const uint64_t *ctr, uint64_t (&v)[kTauShards]) {
+#pragma unroll
+    for (int k = 0; k < kTauShards; ++k) v[k] = load_agent(ctr + k * kTauShardStride);
+}
+__device__ __forceinline__ uint64_t tau_sum(const uint64_t (&v)[kTauShards]) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTauShards; ++k) s += v[k];
     return s;
 }
 
@@ -428,8 +442,8 @@ __device__ __forceinline__ void process_ticket(
 // random words and sets its bucket row i: the Philox draw for sampled rows
 // (SampledPick), or a row given outright with uniform = 1 (a slice walk).
 //
-// TRACE: every kTauPeriod-th step the completion counter is read before the
-// gathers and again just before the scatter is issued (see TauProbe).  Both
+// TRACE: on the sampled steps (see TauProbe) the completion counter is read
+// as the gathers leave and again just before the scatter is issued.  Both
 // reads sit in branches on the same wave-uniform step number, and their values
 // are taken where the loop waits anyway: the first with the gathers, the
 // second with the wait for the next ticket's record header (step 5), which
@@ -538,22 +552,25 @@ __device__ __forceinline__ void run_rows_pipelined(
     // staleness samples (TRACE)
     int64_t nstep = 0;
     uint32_t mine = 0;  // this worker's rows not yet added to the counter
+    uint64_t c0v[kTauShards], c1v[kTauShards];
 
     for (;;) {
         const int64_t jn = j + step;
         const bool more = jn < j_end;
         const int nunits = (nnz + U - 1) / U;
-        const bool samp = TRACE && (nstep % kTauPeriod == 0);
-        uint64_t c0 = 0, c1 = 0, t0 = 0, t1 = 0;
-        if constexpr (TRACE) {
-            if (samp) {
-                c0 = tau_read(tau_ctr);
-                t0 = wall_clock64();
-            }
-        }
+        const bool samp = TRACE && (nstep % kTauPeriod == kTauFlush);
+        uint64_t t0 = 0, t1 = 0;
         // 1. this ticket's gathers
         X xv[UPL][U];
         gather_issue(un, 0, nnz, xv);
+        if constexpr (TRACE) {
+            // (right behind the gathers: a branch before them would make the
+            // wait for this ticket's units at their issue a wait for everything)
+            if (samp) {
+                tau_issue(tau_ctr, c0v);
+                t0 = wall_clock64();
+            }
+        }
         // 2. the next ticket's record, then the locator of the one after
         const uint8_t *rec1;
         int nnz1;
@@ -590,7 +607,7 @@ __device__ __forceinline__ void run_rows_pipelined(
         acc = group_sum<G>(acc);
         if constexpr (TRACE) {
             if (samp) {
-                c1 = tau_read(tau_ctr);
+                tau_issue(tau_ctr, c1v);
                 t1 = wall_clock64();
             }
         }
@@ -609,7 +626,7 @@ __device__ __forceinline__ void run_rows_pipelined(
         }
         if (!more) {
             if constexpr (TRACE) {
-                if (samp) tau_accumulate(*tacc, c0, c1, t0, t1);
+                if (samp) tau_accumulate(*tacc, tau_sum(c0v), tau_sum(c1v), t0, t1);
                 tau_flush_leader(tau_ctr, wave, gl, mine);
             }
             break;
@@ -620,7 +637,7 @@ __device__ __forceinline__ void run_rows_pipelined(
         }
         if constexpr (TRACE) {
             // the header wait above covered the counter loads issued before the atomics
-            if (samp) tau_accumulate(*tacc, c0, c1, t0, t1);
+            if (samp) tau_accumulate(*tacc, tau_sum(c0v), tau_sum(c1v), t0, t1);
         }
         if constexpr (SIDE) {
             bi = sd1.x;

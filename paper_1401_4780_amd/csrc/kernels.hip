@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
     int64_t it = 0;
     uint32_t mine = 0;
     for (int64_t j = a.t_begin + worker; j < a.t_end; j += a.R, ++it) {
-        tp.sample = a.trace != nullptr && it % kTauPeriod == 0;
+        tp.sample = a.trace != nullptr && it % kTauPeriod == kTauFlush;
         process_ticket<VK, XK, G>(a.rows, x, a.xshift, a.side, j, a.stream_id, a.key0, a.key1, a.uniform,
                                   a.update_one, gamma, gl, a.trace ? &tp : nullptr);
         if (a.trace) {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
                                    (uint32_t)worker, 0x5C4E3D2Bu, a.key0, a.key1);
         for (int64_t k = 0; k < Lw; ++k, ++it) {
             const uint32_t i = (uint32_t)(start + slice_perm((uint32_t)k, (uint32_t)Lw, u));
-            tp.sample = a.trace != nullptr && it % kTauPeriod == 0;
+            tp.sample = a.trace != nullptr && it % kTauPeriod == kTauFlush;
             process_ticket<VK, XK, G, Upl<G>::value, false>(a.rows, x, a.xshift, a.side, 0, 0u, 0u, 0u, 1, 0, gamma,
                                                              gl, a.trace ? &tp : nullptr, i);
             if (a.trace) {
