@@ -60,7 +60,9 @@ typedef enum asyrk_status {
     ASYRK_ERR_DIVERGED = 6,      /* the monitored error became non-finite or grew 1e6-fold */
     ASYRK_ERR_CANCELLED = 7,     /* the cancel flag was set; x holds the last checked iterate */
     ASYRK_ERR_UNSUPPORTED = 8,   /* a valid combination this build does not implement */
-    ASYRK_PENDING = 9            /* asyrk_server_poll: the request has not finished yet */
+    ASYRK_PENDING = 9,           /* asyrk_server_poll: the request has not finished yet */
+    ASYRK_ERR_SCRATCH = 10       /* the problem does not fit the fixed scratch of an
+                                    allocation-free entry point (nothing was changed) */
 } asyrk_status;
 
 typedef enum asyrk_dtype { ASYRK_F64 = 0, ASYRK_F32 = 1, ASYRK_BF16 = 2 } asyrk_dtype;
@@ -342,6 +344,24 @@ asyrk_status asyrk_sample_rows(asyrk_system *s, uint64_t seed, uint32_t stream_i
  */
 asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
                               double *tau_max_out);
+
+/*
+ * asyrk_lambda_max without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid it): the same power iteration and the same outputs, with its
+ * vectors v, z (n doubles each), y (m doubles) and reduction partials in one
+ * fixed 64 MiB device array that the library holds on every device it runs
+ * on until the process ends.  Calls no hipMalloc, hipFree or allocating
+ * library routine; the result reaches the host through the system's pinned
+ * scalar.  Requires 2 n + m + 2049 <= 8,388,608 (doubles) and the system's
+ * device current.  Every call on one device shares that array: calls that
+ * overlap on one GPU (several host threads, or streams running concurrently)
+ * race and must be serialized by the caller.
+ * Errors: INVALID_ARG (NULL, iters < 1, another device current), SCRATCH (too
+ * large; asyrk_last_error_message says so), DEVICE.
+ */
+asyrk_status asyrk_lambda_max_noalloc(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
+                                      double *tau_max_out);
 
 /*
  * Autotuner: times one sweep (at least 2^21 tickets) from x = 0 for each

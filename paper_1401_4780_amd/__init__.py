@@ -31,7 +31,7 @@ ASYNC, REPLAY = 0, 1
 SAMPLE_NORM2, SAMPLE_UNIFORM = 0, 1
 UPDATE_ALL, UPDATE_ONE = 0, 1
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "ZERO_ROW", 3: "OOM", 4: "DEVICE", 5: "NOT_CONVERGED",
-          6: "DIVERGED", 7: "CANCELLED", 8: "UNSUPPORTED", 9: "PENDING"}
+          6: "DIVERGED", 7: "CANCELLED", 8: "UNSUPPORTED", 9: "PENDING", 10: "SCRATCH"}
 _SOFT = {5, 6, 7}  # statuses after which x and the stats are still valid
 
 
@@ -151,6 +151,7 @@ def lib():
     L.asyrk_residual.argtypes = [P, P, P, P]
     L.asyrk_sample_rows.argtypes = [P, u64, u32, i32, i64, i64, P, P]
     L.asyrk_lambda_max.argtypes = [P, i32, u64, P, P]
+    L.asyrk_lambda_max_noalloc.argtypes = [P, i32, u64, P, P]
     L.asyrk_autotune.argtypes = [P, dbl, i32, i64, P, P, P]
     L.asyrk_probe_copy.argtypes = [i64, i32, P]
     L.asyrk_probe_scatter.argtypes = [i64, i64, i32, i32, i32, P]
@@ -168,7 +169,7 @@ def lib():
     L.asyrk_now.restype = dbl
     for name in ("asyrk_create", "asyrk_create_augmented", "asyrk_augmented_solution", "asyrk_destroy", "asyrk_set_rhs", "asyrk_system_info_get",
                  "asyrk_records_get",
-                 "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max",
+                 "asyrk_solve", "asyrk_residual", "asyrk_sample_rows", "asyrk_lambda_max", "asyrk_lambda_max_noalloc",
                  "asyrk_probe_copy", "asyrk_probe_scatter", "asyrk_autotune", "asyrk_server_create",
                  "asyrk_server_destroy", "asyrk_server_submit", "asyrk_server_progress",
                  "asyrk_server_poll", "asyrk_server_stats_get", "asyrk_server_take_completed",
@@ -375,11 +376,13 @@ class System:
                "asyrk_sample_rows")
         return rows_out
 
-    def lambda_max(self, iters=60, seed=0):
-        """(lambda_max(A^T A) by power iteration, Corollary 1's largest tau or -1)."""
+    def lambda_max(self, iters=60, seed=0, noalloc=False):
+        """(lambda_max(A^T A) by power iteration, Corollary 1's largest tau or -1).
+        noalloc=True: the allocation-free entry point (fixed scratch)."""
         lam, tau = C.c_double(), C.c_double()
-        _check(lib().asyrk_lambda_max(self._h, iters, seed, C.byref(lam), C.byref(tau)),
-               "asyrk_lambda_max")
+        fn = lib().asyrk_lambda_max_noalloc if noalloc else lib().asyrk_lambda_max
+        _check(fn(self._h, iters, seed, C.byref(lam), C.byref(tau)),
+               "asyrk_lambda_max_noalloc" if noalloc else "asyrk_lambda_max")
         return lam.value, tau.value
 
     def autotune(self, gamma=1.0, iter_dtype=None, in_flight=0):

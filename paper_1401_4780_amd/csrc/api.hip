@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -48,6 +49,7 @@ struct asyrk_system {
     int64_t tuned_R[2] = {0, 0};  // the R those were tuned at
     bool tuned_auto_R[2] = {false, false};  // R chosen by the autotuner: solves with in_flight = 0 use it
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    int dev = 0;                  // the device current at creation (its stream's device)
 };
 
 namespace {
@@ -238,6 +240,7 @@ const char *asyrk_status_string(asyrk_status s) {
         case ASYRK_ERR_CANCELLED: return "cancelled";
         case ASYRK_ERR_UNSUPPORTED: return "unsupported combination";
         case ASYRK_PENDING: return "request pending";
+        case ASYRK_ERR_SCRATCH: return "problem larger than the fixed scratch of an allocation-free entry point";
     }
     return "unknown status";
 }
@@ -304,6 +307,7 @@ static asyrk_status alloc_system(asyrk_system *&out, int64_t m, int64_t n, int32
     s->vk = vals_dtype;
     s->mem = mem;
     s->st = (hipStream_t)stream;
+    (void)hipGetDevice(&s->dev);
     s->mu = res.mu;
     s->nu = res.nu;
     s->fixed_nnz = res.fixed_nnz;
@@ -686,6 +690,88 @@ asyrk_status asyrk_lambda_max(asyrk_system *s, int32_t iters, uint64_t seed, dou
     (void)hipFree(y);
     if (e != hipSuccess) return dev_fail(e);
     if (rc) return rc;
+    *lambda_out = lam;
+    if (lam > 0.0 && std::isfinite(lam)) s->lambda_pi = lam;
+    if (tau_max_out) {
+        const double t = std::floor(s->fro2 / (2.0 * M_E * lam)) - 1.0;
+        *tau_max_out = t >= 0 ? t : -1.0;
+    }
+    return ASYRK_OK;
+}
+
+// ------------------------------------------------------- allocation-free lambda_max
+//
+// Scratch of asyrk_lambda_max_noalloc: the power iteration's vectors v, z (n
+// doubles each) and y (m doubles), the reduction partials and one device
+// scalar.  A file-scope device array, so that the entry point allocates
+// nothing; every device the library runs on holds one copy for the life of
+// the process.  In host code `scratch` names a host-side stand-in: its device
+// address on each device comes from hipGetSymbolAddress (scratch_on).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};  // per device, looked up once with that device current
+
+// The device address of `scratch` on the current device (looked up once).
+hipError_t scratch_on(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<uint8_t *>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+asyrk_status asyrk_lambda_max_noalloc(asyrk_system *s, int32_t iters, uint64_t seed, double *lambda_out,
+                                      double *tau_max_out) {
+    if (!s || !lambda_out || iters < 1) return ASYRK_ERR_INVALID_ARG;
+    const size_t need = (2 * (size_t)s->n + (size_t)s->m + (size_t)kResidualBlocks + 1) * sizeof(double);
+    if (need > kNoAllocScratchBytes) {
+        g_last = "asyrk_lambda_max_noalloc: 2 n + m + 2049 doubles exceed the 64 MiB scratch";
+        return ASYRK_ERR_SCRATCH;
+    }
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != s->dev) {
+        g_last = "asyrk_lambda_max_noalloc: the system's device is not the current device";
+        return ASYRK_ERR_INVALID_ARG;
+    }
+    uint8_t *base = nullptr;
+    HIP_OK(scratch_on(dev, &base));
+    double *v = reinterpret_cast<double *>(base);
+    double *z = v + s->n;
+    double *y = z + s->n;
+    double *part = y + s->m;
+    double *scal = part + kResidualBlocks;
+    const hipStream_t st = s->st;
+    // the same steps as asyrk_lambda_max, on scratch instead of fresh buffers
+    HIP_OK(launch_random_fill(v, s->n, (uint32_t)seed, (uint32_t)(seed >> 32), st));
+    HIP_OK(launch_sumsq_diff(v, 0, 0, nullptr, s->n, part, kResidualBlocks, st));
+    HIP_OK(launch_finish_sum(part, kResidualBlocks, scal, st));
+    HIP_OK(launch_scale(v, s->n, scal, st));
+    for (int it = 0; it < iters; ++it) {
+        HIP_OK(launch_residual(s->vk, s->rows, nullptr, v, 0, 0, y, 0, part, kResidualBlocks, st));
+        HIP_OK(launch_zero(z, s->n * 8, st));
+        HIP_OK(launch_scatter_rows(s->vk, s->rows, y, z, st));
+        HIP_OK(launch_sumsq_diff(z, 0, 0, nullptr, s->n, part, kResidualBlocks, st));
+        HIP_OK(launch_finish_sum(part, kResidualBlocks, scal, st));
+        HIP_OK(launch_scale(z, s->n, scal, st));
+        std::swap(v, z);
+    }
+    HIP_OK(launch_residual(s->vk, s->rows, nullptr, v, 0, 0, nullptr, 0, part, kResidualBlocks, st));
+    HIP_OK(launch_finish_sum(part, kResidualBlocks, scal, st));
+    HIP_OK(hipMemcpyAsync(s->h_pin, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const double lam = s->h_pin[0];
     *lambda_out = lam;
     if (lam > 0.0 && std::isfinite(lam)) s->lambda_pi = lam;
     if (tau_max_out) {

@@ -58,7 +58,7 @@ def test_struct_layouts_match_binding(cname, pycls):
 
 def test_status_strings_and_defaults():
     L = P.lib()
-    for code in range(10):
+    for code in range(11):
         assert L.asyrk_status_string(code)
     p = P.SolveParams()
     L.asyrk_solve_params_init(C.byref(p))
@@ -146,6 +146,7 @@ def test_null_handles_rejected():
     assert P.STATUS[L.asyrk_create_augmented(None, 1, 1, None, None, None, 0, None, 1.0, 1.0, 0,
                                              None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_lambda_max(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
+    assert P.STATUS[L.asyrk_lambda_max_noalloc(None, 5, 0, C.byref(v), None)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_augmented_solution(None, x.ctypes.data, x.ctypes.data)] == "INVALID_ARG"
     assert P.STATUS[L.asyrk_destroy(None)] == "OK"
     assert P.STATUS[L.asyrk_probe_copy(0, 1, C.byref(v))] == "INVALID_ARG"
