@@ -455,6 +455,12 @@ typedef struct asyrk_server_config {
                               of R_s owns rows [w L, (w+1) L), L = ceil(m / R_s), visited in a
                               fresh keyed permutation each sweep: fewer sweeps to tol), in busy
                               and pipelined rounds alike; 0: rows drawn with replacement */
+    int32_t pinned_wait_ms; /* a submit whose packed request does not fit the pinned staging waits
+                              up to this long for uploads to release some (default 1000; 0 =
+                              never): admissions stay DMA transfers under overload instead of
+                              pageable copies that hold the round loop's thread.  A caller that
+                              also drives progress() itself from the submitting thread should
+                              set 0 or keep the pinned staging large enough */
 } asyrk_server_config;
 
 typedef struct asyrk_request_stats {
@@ -480,6 +486,7 @@ typedef struct asyrk_server_stats {
     int32_t lanes_tuning;      /* bit 0 / bit 1: the last plain / pipelined round timed every
                                   candidate width (its load bucket was still being tuned) */
     int32_t buckets_untuned;   /* load buckets (4 per loop) not tuned yet; 0 with fixed widths */
+    int64_t pageable_uploads;  /* requests staged in pageable memory (no room in the pinned staging) */
 } asyrk_server_stats;
 
 /* Defaults for asyrk_server_config. */

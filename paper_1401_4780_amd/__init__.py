@@ -88,6 +88,7 @@ class ServerConfig(C.Structure):
         ("max_workers", C.c_int64), ("max_rounds", C.c_int32), ("use_graph", C.c_int32),
         ("gamma", C.c_double), ("pinned_bytes", C.c_int64), ("lanes", C.c_int32), ("pipe_workers", C.c_int32),
         ("pipe_lanes", C.c_int32), ("fixed_rounds", C.c_int32), ("order", C.c_int32),
+        ("pinned_wait_ms", C.c_int32),
     ]
 
 
@@ -107,7 +108,7 @@ class ServerStats(C.Structure):
         ("row_updates", C.c_int64), ("arena_used", C.c_int64), ("gpu_seconds", C.c_double),
         ("round_workers", C.c_int64), ("round_systems", C.c_int64), ("pipelined_rounds", C.c_int64),
         ("lanes", C.c_int32), ("pipe_lanes", C.c_int32), ("lanes_tuning", C.c_int32),
-        ("buckets_untuned", C.c_int32),
+        ("buckets_untuned", C.c_int32), ("pageable_uploads", C.c_int64),
     ]
 
 

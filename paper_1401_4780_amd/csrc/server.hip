@@ -373,6 +373,7 @@ struct asyrk_server {
 
     std::mutex mu;
     std::condition_variable cv_submit;  // signalled by submit for an idle run loop
+    std::condition_variable cv_pinned;  // signalled when pinned staging is released (or on a fault)
     std::deque<std::unique_ptr<Request>> queue;
     std::unordered_map<int64_t, std::unique_ptr<Request>> done;
     std::unordered_set<int64_t> live;  // submitted and not yet polled
@@ -541,6 +542,7 @@ void asyrk_server_config_init(asyrk_server_config *c) {
     c->pipe_workers = 8192;
     c->pipe_lanes = 16;
     c->order = 1;
+    c->pinned_wait_ms = 1000;
 }
 
 asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *cfg_in) {
@@ -556,7 +558,8 @@ asyrk_status asyrk_server_create(asyrk_server **out, const asyrk_server_config *
         !(cfg.gamma > 0.0 && cfg.gamma < 2.0) || (cfg.lanes != 0 && cfg.lanes != 4 && cfg.lanes != 8) ||
         cfg.pipe_workers < 0 || (cfg.pipe_lanes != 0 && cfg.pipe_lanes != 4 && cfg.pipe_lanes != 8 && cfg.pipe_lanes != 16 &&
                                   cfg.pipe_lanes != 32) ||
-        (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1) || (cfg.order != 0 && cfg.order != 1))
+        (cfg.fixed_rounds != 0 && cfg.fixed_rounds != 1) || (cfg.order != 0 && cfg.order != 1) ||
+        cfg.pinned_wait_ms < 0)
         return ASYRK_ERR_INVALID_ARG;
     asyrk_server *s = new (std::nothrow) asyrk_server();
     if (!s) return ASYRK_ERR_OOM;
@@ -650,10 +653,22 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
     const int64_t lloc = Arena::round_up((int64_t)r->pack.loc.size() * 8);
     const int64_t lb = Arena::round_up(m * 8);
     const int64_t lside = Arena::round_up(m * 16);
+    // Pinned staging full: wait (up to pinned_wait_ms) for uploads to release
+    // some, so that admissions stay DMA transfers; a pageable request's upload
+    // would hold the round loop's thread for its whole copy exactly when the
+    // queue is longest.
     int64_t off = -1;
     if (s->pinned.base) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        off = s->pinned.alloc(lrec + lloc + lb + lside);
+        const int64_t need = lrec + lloc + lb + lside;
+        std::unique_lock<std::mutex> lk(s->mu);
+        off = s->pinned.alloc(need);
+        if (off < 0 && need <= s->pinned.size && s->cfg.pinned_wait_ms > 0) {
+            const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(s->cfg.pinned_wait_ms);
+            while (off < 0 && s->fault.load() == ASYRK_OK &&
+                   s->cv_pinned.wait_until(lk, until) != std::cv_status::timeout)
+                off = s->pinned.alloc(need);
+            if (off < 0) off = s->pinned.alloc(need);
+        }
     }
     uint8_t *p_rec, *p_b, *p_side;
     if (off >= 0) {
@@ -675,6 +690,8 @@ asyrk_status asyrk_server_submit(asyrk_server *s, int64_t m, int64_t n, const in
         p_rec = r->pack.rec.data();
         p_b = reinterpret_cast<uint8_t *>(r->b64.data());
         p_side = reinterpret_cast<uint8_t *>(r->side.data());
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.pageable_uploads++;
     }
     write_records(m, row_ptr, col_idx, vals, ASYRK_F32, b, r->pack, thresh.data(), alias.data(), p_rec);
     std::memcpy(p_b, b, (size_t)m * 8);
@@ -810,7 +827,10 @@ asyrk_status asyrk_server_progress(asyrk_server *s, int32_t *n_active, int32_t *
     const int f = s->fault.load();
     if (f != ASYRK_OK) return (asyrk_status)f;
     const asyrk_status rc = server_progress(s, n_active, n_queued);
-    if (rc != ASYRK_OK) s->fault.store(rc);
+    if (rc != ASYRK_OK) {
+        s->fault.store(rc);
+        s->cv_pinned.notify_all();  // submits waiting for staging give up
+    }
     return rc;
 }
 
@@ -830,15 +850,18 @@ static asyrk_status server_progress(asyrk_server *s, int32_t *n_active, int32_t 
     // would otherwise have nothing to do, wait for the oldest batch
     using Upload = asyrk_server::Upload;
     auto finish_upload = [&](Upload &u) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &r : u.reqs) {
-            if (r->pin_off >= 0) {
-                s->pinned.release(r->pin_off, r->pin_bytes);
-                r->pin_off = -1;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &r : u.reqs) {
+                if (r->pin_off >= 0) {
+                    s->pinned.release(r->pin_off, r->pin_bytes);
+                    r->pin_off = -1;
+                }
+                s->ready.push_back(std::move(r));
             }
-            s->ready.push_back(std::move(r));
+            s->ev_pool.push_back(u.ev);
         }
-        s->ev_pool.push_back(u.ev);
+        s->cv_pinned.notify_all();
     };
     while (!s->uploading.empty()) {
         Upload &u = s->uploading.front();

@@ -167,8 +167,9 @@ def test_server_config_validation():
     L.asyrk_server_config_init(C.byref(c))
     assert c.budget_bytes == 64 << 30 and c.use_graph == 1 and c.max_workers == 65536
     assert c.inner_sweeps == 8 and c.pinned_bytes == 4 << 30 and c.lanes == 4 and c.pipe_workers == 8192 and c.pipe_lanes == 16 and c.fixed_rounds == 0 and c.order == 1
+    assert c.pinned_wait_ms == 1000
     for field, bad in (("gamma", 2.0), ("max_slots", 0), ("inner_sweeps", 0), ("budget_bytes", 10),
-                       ("pinned_bytes", -1), ("lanes", 16), ("lanes", 2), ("pipe_workers", -1), ("pipe_lanes", 2), ("pipe_lanes", 64), ("fixed_rounds", 2), ("order", 2), ("order", -1)):
+                       ("pinned_bytes", -1), ("lanes", 16), ("lanes", 2), ("pipe_workers", -1), ("pipe_lanes", 2), ("pipe_lanes", 64), ("fixed_rounds", 2), ("order", 2), ("order", -1), ("pinned_wait_ms", -1)):
         d = P.ServerConfig()
         L.asyrk_server_config_init(C.byref(d))
         setattr(d, field, bad)

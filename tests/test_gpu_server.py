@@ -62,16 +62,60 @@ def _check(s, res):
 
 @pytest.mark.parametrize("use_graph,pinned", [(True, 1 << 30), (False, 0), (True, 8 << 20)])
 def test_server_solves_a_mixed_stream(use_graph, pinned):
-    """pinned = 8 MiB holds only the small requests: both upload paths in one run."""
+    """pinned = 8 MiB holds only the small requests: both upload paths in one
+    run (every request is submitted before the first round, from the thread
+    that drives the rounds, so submits do not wait for staging)."""
     _say(f"server mixed stream graph={use_graph} pinned={pinned}")
     sizes = [1000, 1500, 4000, 12000, 30000, 2000, 800, 60000, 5000, 1000]
     systems = _systems(range(100, 110), sizes)
-    with P.Server(budget_bytes=1 << 30, use_graph=use_graph, pinned_bytes=pinned) as srv:
+    with P.Server(budget_bytes=1 << 30, use_graph=use_graph, pinned_bytes=pinned, pinned_wait_ms=0) as srv:
         res = _run_all(srv, systems)
         for s, r in zip(systems, res):
             _check(s, r)
         st = srv.stats()
         assert st["completed"] == len(systems) and st["active"] == 0 and st["arena_used"] == 0
+        if pinned == 8 << 20:
+            assert 0 < st["pageable_uploads"] < len(systems)
+        else:
+            assert st["pageable_uploads"] == (len(systems) if pinned == 0 else 0)
+
+
+def test_submit_waits_for_pinned_staging_while_the_loop_runs():
+    """A pinned staging of 12 MiB holds one of these requests (6-9 MiB packed)
+    at a time: with the round loop running, submits wait for uploads to
+    release staging instead of packing into pageable memory, and every
+    request is still solved; with pinned_wait_ms = 0 some go pageable."""
+    import threading
+    _say("server submit waits for pinned staging")
+    systems = _systems(range(720, 732), [16000 + 1000 * k for k in range(12)])
+    for wait_ms, expect_pageable in ((10000, False), (0, True)):
+        ids = [None] * len(systems)
+        with P.Server(budget_bytes=1 << 30, pinned_bytes=12 << 20, pinned_wait_ms=wait_ms) as srv:
+            srv.start()
+
+            def worker(lo):
+                for k in range(lo, len(systems), 2):
+                    s = systems[k]
+                    ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=TOL, seed=k)
+            threads = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            out = {}
+            import time
+            t_end = time.monotonic() + 60.0
+            while len(out) < len(systems) and time.monotonic() < t_end:
+                for rid in srv.take_completed():
+                    k = ids.index(rid)
+                    out[k] = srv.poll(rid, n=systems[k].n)
+                time.sleep(0.001)
+            srv.stop()
+            assert len(out) == len(systems)
+            for k, s in enumerate(systems):
+                _check(s, out[k])
+            st = srv.stats()
+            assert (st["pageable_uploads"] > 0) == expect_pageable, (wait_ms, st["pageable_uploads"])
 
 
 def test_busy_rounds_without_replacement_take_fewer_sweeps():
