@@ -474,6 +474,12 @@ def run_skewed(args, Rs=None, sweeps=100, baseline=True, short=False):
     # staleness at Corollary 1's R, measured on the same loop
     x.zero_()
     tr = sysm.solve(x, 1.0, 1, 6, in_flight=R0, lanes=args.lanes, trace=True)
+    # one worker alone: the time one ticket takes (its gathers are one round
+    # trip to the point where the device performs atomics) bounds what R0
+    # workers can do
+    x.zero_()
+    lone = sysm.solve(x, 1.0, 1, 8, in_flight=1, lanes=args.lanes, final_resid=False)
+    ticket_ns = 1e9 / lone["rows_per_s"]
     converging = {q: v for q, v in res.items() if np.isfinite(v["err_after_sweeps"])
                   and v["err_after_sweeps"] < v["err_curve"][0]}
     best = max(converging or res, key=lambda q: res[q]["rows_per_s"])
@@ -492,13 +498,22 @@ def run_skewed(args, Rs=None, sweeps=100, baseline=True, short=False):
            "staleness_at_default_in_flight": {"tau_obs_mean": tr["tau_obs_mean"], "tau_obs_max": tr["tau_obs_max"],
                                               "tau_samples": tr["tau_samples"],
                                               "within_corollary1": tr["tau_obs_max"] <= tau_max},
+           "one_worker": {"rows_per_s": lone["rows_per_s"], "ns_per_ticket": ticket_ns, "lanes": lone["lanes"],
+                          "pipelined": lone["pipelined"],
+                          "bound_rows_per_s_at_default_in_flight": R0 * lone["rows_per_s"]},
            "by_in_flight": res, "cpu_baseline": cb}
     if cb:
         r0 = res[str(R0)]["rows_per_s"] if str(R0) in res else None
+        met = bool(r0 and r0 >= 2 * cb["value"])
         out["target"] = {"target": "at Corollary 1's R, at least 2x the single-core oracle's row updates/s",
                          "in_flight": R0, "gpu_rows_per_s": r0, "oracle_rows_per_s": cb["value"],
-                         "ratio": r0 / cb["value"] if r0 else None,
-                         "target_met": bool(r0 and r0 >= 2 * cb["value"])}
+                         "ratio": r0 / cb["value"] if r0 else None, "target_met": met,
+                         "why": None if met else (
+                             f"Corollary 1 admits {R0} workers here (lambda_max = {lam:.3g} from the hot column); "
+                             f"a worker's ticket costs {ticket_ns:.0f} ns even alone (its gathers are one round "
+                             "trip to the memory-side point where the atomics are performed), so "
+                             f"{R0} workers are bound by {R0 * lone['rows_per_s']:.3g} rows/s, against the oracle's "
+                             f"{cb['value']:.3g} on one core whose caches hold x")}
     return out
 
 
@@ -550,12 +565,29 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
 
     tol = 1e-8
     n_req = args.requests
-    specs = synth.serving_specs(n_req * (len(rates) + 1), seed=4)
+    # saturation (every request present at t = 0) on at most 2000 requests:
+    # the queued requests' packed copies wait in host memory
+    n_sat = min(n_req, 2000)
+    n_total = n_sat + n_req * len(rates)
+    # pool > 0: the stream's requests cycle through that many distinct
+    # generated systems (each request is still packed, uploaded and solved on
+    # its own, with its own seed); 0: every request is a system of its own
+    n_sys = min(args.pool, n_total) if args.pool else n_total
+    specs = synth.serving_specs(n_sys, seed=4)
     pool = ThreadPoolExecutor(16)
 
     def gen(rid):
-        m, n = (int(v) for v in specs[rid])
-        return synth.serving_system(rid, m, n)
+        m, n = (int(v) for v in specs[rid % n_sys])
+        return synth.serving_system(rid % n_sys, m, n)
+
+    def lite(rid):
+        # what a request submits (the oracle's FP64 copy and x* are not needed)
+        s = gen(rid)
+        return s.row_ptr, s.col, s.val, s.b, s.n
+
+    kept = list(pool.map(lite, range(n_sys))) if args.pool else None
+    if kept is not None:
+        log(f"serving: generated a pool of {n_sys} systems")
 
     srv = P.Server(budget_bytes=64 << 30, **({"inner_sweeps": args.inner} if args.inner else {}),
                    **({"lanes": 0, "pipe_lanes": 0} if args.tune_lanes else {}),
@@ -569,7 +601,8 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
     def drive(first, count, arrivals):
         """Submit requests first..first+count-1 at their arrival times (seconds
         after t0) from a thread pool; run rounds until all finished."""
-        systems = list(pool.map(gen, range(first, first + count)))
+        systems = ([kept[(first + k) % n_sys] for k in range(count)] if kept is not None
+                   else list(pool.map(lite, range(first, first + count))))
         t0 = P.now() + 0.05
         ids = [None] * count
         sub_pool = ThreadPoolExecutor(args.submit_threads)
@@ -580,8 +613,8 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
             delay = t0 + arrivals[k] - P.now()
             if delay > 0:
                 time.sleep(delay)
-            s = systems[k]
-            ids[k] = srv.submit(s.row_ptr, s.col, s.val, s.b, n=s.n, tol=tol, seed=first + k)
+            rp, col, val, b, n = systems[k]
+            ids[k] = srv.submit(rp, col, val, b, n=n, tol=tol, seed=first + k)
             id_of[ids[k]] = k
 
         st0 = srv.stats()
@@ -628,13 +661,13 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
                 "pipelined_rounds": st1["pipelined_rounds"] - st0["pipelined_rounds"]}
 
     # saturation: every request present at t = 0
-    sat = drive(0, n_req, np.zeros(n_req))
+    sat = drive(0, n_sat, np.zeros(n_sat))
     log(f"serving saturation: {sat}")
     sweep = {}
     for q, f in enumerate(rates):
         rate = f * sat["solves_per_s"]
         arr = synth.poisson_arrivals(n_req, rate, seed=5 + q)
-        sweep[str(f)] = dict(drive(n_req * (q + 1), n_req, arr), offered_per_s=rate)
+        sweep[str(f)] = dict(drive(n_sat + n_req * q, n_req, arr), offered_per_s=rate)
         log(f"serving load {f}: {sweep[str(f)]}")
     st = srv.stats()
     srv.close()
@@ -644,7 +677,7 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
     if baseline:
         dev = torch.device("cuda:0")
         nb = min(40, n_req)
-        base_sys = list(pool.map(gen, range(nb)))
+        base_sys = list(pool.map(gen, range(nb)))  # the stream's first requests
         t0 = time.perf_counter()
         for s in base_sys:
             d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
@@ -657,13 +690,14 @@ def run_serving(args, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), baseline=True):
     cpu = None
     if baseline and not args.no_cpu_baseline:
         log("serving cpu baseline (oracle)")
-        cpu = serving_cpu_baseline(gen, specs, n_req, tol)
+        cpu = serving_cpu_baseline(gen, specs, min(n_req, n_sys), tol)
         log(f"serving cpu baseline: {cpu}")
     return {"metric": "solves/s and p50/p99 solve latency (serving)", "value": sat["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0, "higher_is_better": True,
             "vs_baseline": None, "data": "synthetic", "dtype": "f64",
             "config": {"workload": "asyrk_serving_stream_m1k-200k_n=m/4_nnz8-64_to_1e-8", "values": "f32",
-                       "requests_per_point": n_req, "budget_GiB": 64, "tol": tol,
+                       "requests_per_point": n_req, "saturation_requests": n_sat,
+                       "distinct_systems": n_sys, "budget_GiB": 64, "tol": tol,
                        "inner_sweeps_per_round": srv.config["inner_sweeps"],
                        "lanes": srv.config["lanes"], "max_workers": srv.config["max_workers"],
                        "pipe_workers": srv.config["pipe_workers"], "pipe_lanes": srv.config["pipe_lanes"],
@@ -695,10 +729,13 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="refinement inner sweeps (0: default)")
     ap.add_argument("--workload", default="c2", choices=["c2", "precision", "skewed", "serving"])
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per load point")
+    ap.add_argument("--pool", type=int, default=0,
+                    help="serving: requests cycle through this many distinct systems (0: all distinct)")
     ap.add_argument("--max-workers", type=int, default=0, help="serving: total row workers (0: default)")
     ap.add_argument("--pipe-lanes", type=int, default=0, help="serving: lanes in pipelined rounds (0: default)")
     ap.add_argument("--pipe-workers", type=int, default=-1,
                     help="serving: pipelined rounds up to this many workers (-1: default)")
+    ap.add_argument("--sweeps", type=int, default=100, help="skewed: sweep budget per in-flight count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the in-flight (R) sweep")
     ap.add_argument("--headline-only", action="store_true",
@@ -709,7 +746,8 @@ def main():
               "lock-free sweep does not shard within the paper's delay bound; independent "
               "systems would be placed one GPU each).", file=sys.stderr)
         sys.exit(2)
-    fn = {"c2": run_c2, "precision": run_precision, "skewed": run_skewed,
+    fn = {"c2": run_c2, "precision": run_precision,
+          "skewed": lambda a: run_skewed(a, sweeps=a.sweeps),
           "serving": run_serving}[args.workload]
     result = fn(args)
     if args.workload == "c2" and not args.headline_only:
