@@ -47,6 +47,9 @@ SIDE_EXTRA_BYTES = 8
 R_SWEEP = (1024, 2048, 4096, 8192, 16384, 32768, 65536)
 
 
+# worker loops of the sweep (solve stats "pipelined", autotuner keys)
+LOOP_NAMES = {0: "", 1: " pipelined", 2: " batched"}
+
 def kernel_source_hash() -> str:
     """Hash of the code (comments and blank lines removed) of the sweep kernels,
     their launch geometry, the iterate stride and the record layout."""
@@ -149,7 +152,7 @@ def run_c2(args):
         # the library's choice of R (in_flight = 0) is left to the autotuner too
         best, pipe, rates = sysm.autotune(GAMMA, in_flight=args.in_flight or "auto")
         tuned = {"best_lanes": best, "pipelined": pipe, "in_flight": sysm.info()["tuned_in_flight"] or args.in_flight,
-                 "rows_per_s": {f"G={g}{' pipelined' if p else ''}": r for (g, p), r in rates.items()}}
+                 "rows_per_s": {f"G={g}{LOOP_NAMES[p]}": r for (g, p), r in rates.items()}}
         log(f"autotune: R={tuned['in_flight']} G={best} pipelined={pipe} {tuned['rows_per_s']}")
 
     b_norm = float(np.linalg.norm(s.b))

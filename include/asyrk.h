@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ASYRK_ABI_VERSION 2
+#define ASYRK_ABI_VERSION 3
 
 typedef struct asyrk_system asyrk_system; /* opaque; owns all device-side data */
 
@@ -136,12 +136,18 @@ typedef struct asyrk_solve_params {
                                 ticket's row while the current one gathers and scatters:
                                 same arithmetic and reads of x, two dependent memory
                                 round trips per ticket; faster when few workers are in
-                                flight, slower when the atomic unit is saturated); needs
+                                flight, slower when the atomic unit is saturated);
+                                2 = batched (each worker fetches the rows of its next
+                                8, 4 or 2 tickets together, for G >= 8, G = 4 and
+                                G <= 2, and runs them back to back: same arithmetic and
+                                reads of x, one record round trip per batch; the
+                                fastest loop with few workers in flight).  1 and 2 need
                                 ASYNC and UPDATE_ALL (with order 1 each worker's slice
                                 walk is its ticket stream).  0 = plain.
                                 -1 (set by asyrk_solve_params_init) = the autotuned
                                 choice when the autotuner ran at this R and G, else
-                                pipelined for R <= 8192 where allowed */
+                                batched for R <= 1024 and pipelined for R <= 8192
+                                where allowed */
     int32_t skip_resid;      /* 0 (default): fill asyrk_solve_stats.final_resid, which costs one
                                 FP64 residual pass unless the monitor already measured the
                                 residual of the returned x; 1: leave it NaN */
@@ -164,7 +170,7 @@ typedef struct asyrk_solve_stats {
     int64_t in_flight;         /* R used */
     int32_t lanes;             /* G used */
     int32_t outer_iters;       /* refinement outer iterations (0 without refinement) */
-    int32_t pipelined;         /* 1 if the pipelined worker loop ran */
+    int32_t pipelined;         /* worker loop that ran: 0 plain, 1 pipelined, 2 batched */
     int32_t reserved;
     double seconds;            /* wall time of the call after setup */
     double sweep_seconds;      /* GPU time of the sweep kernels (HIP events) */
@@ -366,7 +372,7 @@ asyrk_status asyrk_lambda_max_noalloc(asyrk_system *s, int32_t iters, uint64_t s
 /*
  * Autotuner: times one sweep (at least 2^21 tickets) from x = 0 for each
  * lane-group width G in {1, 2, 4, 8, 16, 32, 64} and each worker loop (plain,
- * pipelined) on this system, at in_flight workers (0 = the default R) and the
+ * pipelined, batched) on this system, at in_flight workers (0 = the default R) and the
  * given iterate dtype (-1 = default), and keeps the fastest pair for later
  * solves with lanes = 0 and pipeline = -1 at that R.  in_flight = -1 chooses R
  * as well: each power of two from 1024 below the default R, and the default R,
@@ -374,10 +380,11 @@ asyrk_status asyrk_lambda_max_noalloc(asyrk_system *s, int32_t iters, uint64_t s
  * kept (the same throughput with less staleness); later asynchronous,
  * all-coordinate solves with replacement and in_flight = 0 then use it
  * (asyrk_system_info.tuned_in_flight); other kinds keep the default R.  Near-ties go by a fixed
- * rule: the pipelined loop only when its best rate beats the plain loop's by
- * more than 3%, then the smallest G within 3% of that loop's best.  best_lanes and
- * best_pipeline (nullable) receive it; rows_per_s (nullable, double[14]) the
- * rate of each candidate: [0..6] plain, [7..13] pipelined, G ascending.  The
+ * rule: a loop replaces the one chosen so far (plain, then pipelined, then
+ * batched) only when its best rate is more than 3% higher, then the smallest G
+ * within 3% of that loop's best.  best_lanes and best_pipeline (nullable)
+ * receive it; rows_per_s (nullable, double[21]) the rate of each candidate:
+ * [0..6] plain, [7..13] pipelined, [14..20] batched, G ascending.  The
  * system's b and matrix are unchanged.  Errors: INVALID_ARG, UNSUPPORTED,
  * DEVICE.
  */

@@ -390,15 +390,16 @@ class System:
         """Time one sweep per lane-group width and worker loop; the fastest pair
         becomes the default at this R (in_flight = 0: the default R; "auto":
         the autotuner picks R too, see info()["tuned_in_flight"]).  Returns
-        (best G, pipelined?, {(G, pipelined): rows/s}) at that R."""
+        (best G, loop, {(G, loop): rows/s}) at that R, loop 0 plain,
+        1 pipelined, 2 batched."""
         if in_flight == "auto":
             in_flight = -1
         best, pipe = C.c_int32(), C.c_int32()
-        rates = (C.c_double * 14)()
+        rates = (C.c_double * 21)()
         _check(lib().asyrk_autotune(self._h, float(gamma), {None: -1, "f32": F32, "f64": F64}[iter_dtype],
                                     int(in_flight), C.byref(best), C.byref(pipe), rates), "asyrk_autotune")
-        keys = [(g, p) for p in (False, True) for g in (1, 2, 4, 8, 16, 32, 64)]
-        return best.value, bool(pipe.value), dict(zip(keys, list(rates)))
+        keys = [(g, p) for p in (0, 1, 2) for g in (1, 2, 4, 8, 16, 32, 64)]
+        return best.value, pipe.value, dict(zip(keys, list(rates)))
 
     # -- the method
     def solve(self, x, gamma=1.0, sweeps=1, seed=0, *, mode="async", sampling="norm2",
@@ -430,7 +431,7 @@ class System:
         p.ticket0 = ticket0
         p.iter_dtype = {None: -1, "f32": F32, "f64": F64}[iter_dtype]
         p.order = {"replacement": 0, "slices": 1}[order]
-        p.pipeline = -1 if pipeline is None else int(bool(pipeline))
+        p.pipeline = -1 if pipeline is None else int(pipeline)  # False/True/0/1/2; others are rejected
         p.skip_resid = 0 if final_resid else 1
         if cancel is not None:
             if not (isinstance(cancel, np.ndarray) and cancel.dtype == np.int32):

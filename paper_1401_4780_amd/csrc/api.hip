@@ -45,7 +45,7 @@ struct asyrk_system {
     int64_t device_bytes = 0;
     bool rec_b_dirty = false;
     int tuned_G[2] = {0, 0};      // autotuned lanes per row for F64 / F32 iterates (0 = none)
-    int tuned_pipe[2] = {0, 0};   // autotuned worker loop (1 = pipelined) for F64 / F32 iterates
+    int tuned_pipe[2] = {0, 0};   // autotuned worker loop (0 plain, 1 pipelined, 2 batched) for F64 / F32 iterates
     int64_t tuned_R[2] = {0, 0};  // the R those were tuned at
     bool tuned_auto_R[2] = {false, false};  // R chosen by the autotuner: solves with in_flight = 0 use it
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -124,9 +124,13 @@ asyrk_status fetch_scalar(asyrk_system *s, int nparts, double *host_out) {
     return ASYRK_OK;
 }
 
-// Without autotuning, the pipelined worker loop is used up to this many
-// workers: below it the sweep is bound by each worker's memory latency, above
-// it by the atomic unit, where the plain loop measured faster.
+// Worker loops: 0 plain, 1 pipelined, 2 batched.
+constexpr int kLoops = 3;
+// Without autotuning, the batched worker loop is used up to kBatchMaxR
+// workers and the pipelined one up to kPipeMaxR: below these the sweep is
+// bound by each worker's memory latency (which the batched loop shortens
+// most), above them by the atomic unit, where the plain loop measured faster.
+constexpr int64_t kBatchMaxR = 1024;
 constexpr int64_t kPipeMaxR = 8192;
 
 // Lanes per row without autotuning: the sweep saturates once about 2^16
@@ -782,16 +786,16 @@ asyrk_status asyrk_lambda_max_noalloc(asyrk_system *s, int32_t iters, uint64_t s
 }
 
 // Time every lane-group width and worker loop at R workers; returns the
-// chosen pair and its rate (the near-tie rule below) and the rates of all 14.
+// chosen pair and its rate (the near-tie rule below) and the rates of all 21.
 static asyrk_status tune_at(asyrk_system *s, int xk, int64_t R, double gamma, int *G_out, int *pipe_out,
-                            double *rate_out, double *rates14) {
+                            double *rate_out, double *rates21) {
     asyrk_solve_params p;
     asyrk_solve_params_init(&p);
     // at least one sweep and at least 2M tickets per candidate
     const int64_t tickets = std::max<int64_t>(s->m, (int64_t)2 << 20);
     const int cands[7] = {1, 2, 4, 8, 16, 32, 64};
-    double rate[2][7] = {}, top[2] = {0.0, 0.0};
-    for (int pipe = 0; pipe < 2; ++pipe) {
+    double rate[kLoops][7] = {}, top[kLoops] = {};
+    for (int pipe = 0; pipe < kLoops; ++pipe) {
         p.pipeline = pipe;
         for (int k = 0; k < 7; ++k) {
             const int G = cands[k];
@@ -802,14 +806,17 @@ static asyrk_status tune_at(asyrk_system *s, int xk, int64_t R, double gamma, in
             if (rc) return rc;
             rate[pipe][k] = gpu_s > 0 ? (double)tickets / gpu_s : 0.0;
             top[pipe] = std::max(top[pipe], rate[pipe][k]);
-            if (rates14) rates14[7 * pipe + k] = rate[pipe][k];
+            if (rates21) rates21[7 * pipe + k] = rate[pipe][k];
         }
     }
     // Candidates a few percent apart differ by timing noise (a saturated
-    // atomic unit), so ties are broken by a fixed rule: the pipelined loop only
-    // when it beats the plain one by more than 3%, then the narrowest lane
-    // group within 3% of that loop's fastest.
-    const int best_pipe = top[1] > 1.03 * top[0] ? 1 : 0;
+    // atomic unit), so ties are broken by a fixed rule: a loop replaces the
+    // one chosen so far (plain, then pipelined, then batched) only when it is
+    // more than 3% faster, then the narrowest lane group within 3% of that
+    // loop's fastest.
+    int best_pipe = 0;
+    for (int pipe = 1; pipe < kLoops; ++pipe)
+        if (top[pipe] > 1.03 * top[best_pipe]) best_pipe = pipe;
     int k_best = 6;
     for (int k = 0; k < 7; ++k)
         if (rate[best_pipe][k] >= 0.97 * top[best_pipe]) {
@@ -960,8 +967,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
         p.inner_sweeps < 0 || p.history_cap < 0 || (p.history_cap > 0 && !p.history))
         return ASYRK_ERR_INVALID_ARG;
     if (p.order != 0 && p.order != 1) return ASYRK_ERR_INVALID_ARG;
-    if (p.pipeline < -1 || p.pipeline > 1 || (p.skip_resid != 0 && p.skip_resid != 1)) return ASYRK_ERR_INVALID_ARG;
-    if (p.pipeline == 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL)) return ASYRK_ERR_UNSUPPORTED;
+    if (p.pipeline < -1 || p.pipeline > 2 || (p.skip_resid != 0 && p.skip_resid != 1)) return ASYRK_ERR_INVALID_ARG;
+    if (p.pipeline >= 1 && (p.mode != ASYRK_ASYNC || p.update != ASYRK_UPDATE_ALL)) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.update != ASYRK_UPDATE_ALL) return ASYRK_ERR_UNSUPPORTED;
     if (p.order == 1 && p.ticket0 % s->m != 0) return ASYRK_ERR_INVALID_ARG;
     if (p.iter_dtype != -1 && p.iter_dtype != ASYRK_F32 && p.iter_dtype != ASYRK_F64) return ASYRK_ERR_INVALID_ARG;
@@ -988,7 +995,8 @@ asyrk_status asyrk_solve(asyrk_system *s, double *x, double gamma, int64_t sweep
     if (p.pipeline == -1) {
         const bool allowed = p.mode == ASYRK_ASYNC && p.update == ASYRK_UPDATE_ALL;
         const bool tuned_here = tuned && G == tuned;
-        p.pipeline = !allowed ? 0 : (tuned_here ? s->tuned_pipe[xi] : (R <= kPipeMaxR ? 1 : 0));
+        p.pipeline = !allowed ? 0
+                     : (tuned_here ? s->tuned_pipe[xi] : (R <= kBatchMaxR ? 2 : (R <= kPipeMaxR ? 1 : 0)));
     }
     const bool f32 = xk == ASYRK_F32;
     const int xsh = xshift_of(s, f32, p);

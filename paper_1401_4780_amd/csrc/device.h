@@ -258,11 +258,101 @@ __device__ __forceinline__ void tau_store(const TauAcc &acc, uint64_t *out, int6
     }
 }
 
+// One DPP lane move of a 32- or 64-bit value (a 64-bit value moves as its
+// two halves).  ROWS = 0xF: a pattern that gives every lane a source in its
+// own row (quad permutations, mirrors), so every lane is written.  Otherwise
+// the lanes of the rows outside the mask read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move32(int v) {
+    if constexpr (ROWS == 0xF) return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+    else return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, dpp_move32<CTRL, ROWS>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp_move32<CTRL, ROWS>((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)dpp_move32<CTRL, ROWS>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <class X>
+__device__ __forceinline__ X read_lane(X v, int lane) {
+    if constexpr (sizeof(X) == 8) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return __builtin_bit_cast(X, ((uint64_t)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(X, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    }
+}
+
+// Sum over each aligned group of G lanes, returned to every lane of the group.
+// Within a 16-lane row the moves are register-to-register DPP (quad
+// permutations, then the half-row and row mirrors: after each step the value
+// is uniform over the lanes summed so far, so a mirror adds the other half's
+// sum).  Across rows, row_bcast15 adds row 0 into row 1 and row 2 into row 3,
+// row_bcast31 adds rows 0 + 1 into rows 2 and 3, and the group's total is read
+// from its last lane.  No LDS traffic, so no wait on the LDS counter; every
+// lane of a group ends with the same bits.  The lanes of a group must be
+// active together (a group is one worker).
 template <int G, class X>
 __device__ __forceinline__ X group_sum(X v) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if constexpr (G >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    if constexpr (G >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (G >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+    if constexpr (G >= 16) v += dpp_move<0x140>(v); // row_mirror
+    if constexpr (G == 32) {
+        v += dpp_move<0x142, 0xA>(v);                // row_bcast15 into rows 1, 3
+        const X lo = read_lane(v, 31), hi = read_lane(v, 63);
+        v = (__lane_id() < 32) ? lo : hi;
+    } else if constexpr (G == 64) {
+        v += dpp_move<0x142, 0xA>(v);                // row_bcast15 into rows 1, 3
+        v += dpp_move<0x143, 0xC>(v);                // row_bcast31 into rows 2, 3
+        v = read_lane(v, 63);
+    }
     return v;
+}
+
+// What lane b of this lane's group holds (G >= 16, b a constant): lane b of
+// every group is read into a scalar register and this group's is selected.
+template <int G>
+__device__ __forceinline__ uint32_t group_lane(uint32_t v, int b) {
+    static_assert(G >= 16 && G <= 64, "group_lane: groups of 16 to 64 lanes");
+    uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)v, b);
+    if constexpr (G < 64) {
+        const int grp = (int)__lane_id() / G;
+#pragma unroll
+        for (int g = 1; g < 64 / G; ++g) {
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)v, g * G + b);
+            r = grp == g ? o : r;
+        }
+    }
+    return r;
+}
+
+// A copy of v that the compiler treats as varying across lanes.  A value
+// loaded through a uniform address is uniform, and the compiler moves it to
+// scalar registers as soon as the load returns, which makes the wave wait for
+// that load where it is issued; row indices pass through here after the draw
+// so that the records loaded through them stay in vector registers and are
+// waited for where they are used.
+__device__ __forceinline__ uint32_t as_varying(uint32_t v) {
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// A value that is the same in every active lane, moved to a scalar register
+// (so that arithmetic on it runs on the scalar unit).
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Units per lane kept in registers: a row of up to G * UPL units is read
@@ -462,6 +552,12 @@ __device__ __forceinline__ void run_rows_pipelined(
     using H = typename T::hdr_t;
     constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
     constexpr int U = T::U;
+    if constexpr (G == 64) {
+        // a worker is a whole wave: its tickets, and so its draws, are scalar
+        j = wave_uniform(j);
+        j_end = wave_uniform(j_end);
+        step = wave_uniform(step);
+    }
     if (j >= j_end) return;
 
     // units base + gl, base + gl + G, ... of a row; absent units are read
@@ -476,13 +572,14 @@ __device__ __forceinline__ void run_rows_pipelined(
     };
     auto fetch_units = [&](const uint8_t *rec, int nunits, Unit<VK> *dst) { fetch_chunk(rec, 0, nunits, dst); };
     // branch-free gathers of one chunk held in registers, issued ...
-    auto gather_issue = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U]) {
+    auto gather_issue = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U], X *(*xa)[U]) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
             for (int e = 0; e < U; ++e) {
                 const bool ok = (base + gl + q * G) * U + e < nnz;
-                xv[q][e] = load_agent(xat(x, ok ? cu[q].c[e] : 0, xsh));
+                xa[q][e] = xat(x, ok ? cu[q].c[e] : 0, xsh);
+                xv[q][e] = load_agent(xa[q][e]);
             }
     };
     // ... and consumed
@@ -496,7 +593,16 @@ __device__ __forceinline__ void run_rows_pipelined(
             }
         return acc;
     };
-    auto chunk_scatter = [&](const Unit<VK> *cu, int base, int nnz, X s) {
+    // the scatter of a chunk whose gathers computed the addresses xa
+    auto chunk_scatter = [&](const Unit<VK> *cu, X *(*xa)[U], int base, int nnz, X s) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e)
+                if ((base + gl + q * G) * U + e < nnz) atomic_add(xa[q][e], -s * (X)cu[q].v[e]);
+    };
+    // the scatter of a chunk re-read from the record (long rows)
+    auto chunk_scatter_reread = [&](const Unit<VK> *cu, int base, int nnz, X s) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q)
 #pragma unroll
@@ -528,6 +634,7 @@ __device__ __forceinline__ void run_rows_pipelined(
     // prologue: ticket j in full, ticket j + step's locator
     uint32_t i;
     U4 u = pick(j, i);
+    i = as_varying(i);
     const uint8_t *rec;
     int nnz;
     locate_nb(rows, i, rec, nnz);
@@ -547,6 +654,7 @@ __device__ __forceinline__ void run_rows_pipelined(
     // (tickets drawn past the end have valid rows and are simply not used)
     uint32_t i1;
     U4 u1 = pick(j + step, i1);
+    i1 = as_varying(i1);
     RowLoc l1 = locator_load(i1);
 
     // staleness samples (TRACE)
@@ -562,7 +670,8 @@ __device__ __forceinline__ void run_rows_pipelined(
         uint64_t t0 = 0, t1 = 0;
         // 1. this ticket's gathers
         X xv[UPL][U];
-        gather_issue(un, 0, nnz, xv);
+        X *xa[UPL][U];
+        gather_issue(un, 0, nnz, xv, xa);
         if constexpr (TRACE) {
             // (right behind the gathers: a branch before them would make the
             // wait for this ticket's units at their issue a wait for everything)
@@ -592,6 +701,7 @@ __device__ __forceinline__ void run_rows_pipelined(
         if constexpr (SIDE) sd1 = gload<double2>(side + i1);
         uint32_t i2;
         const U4 u2 = pick(jn + step, i2);
+        i2 = as_varying(i2);
         const RowLoc l2 = locator_load(i2);
         // 3. gather-dot: the first chunk from registers (waiting for these
         // gathers only), then further chunks of long rows, re-read after it so
@@ -601,7 +711,8 @@ __device__ __forceinline__ void run_rows_pipelined(
             Unit<VK> t[UPL];
             fetch_chunk(rec, base, nunits, t);
             X tv[UPL][U];
-            gather_issue(t, base, nnz, tv);
+            X *ta[UPL][U];
+            gather_issue(t, base, nnz, tv, ta);
             acc = gather_dot(t, base, nnz, tv, acc);
         }
         acc = group_sum<G>(acc);
@@ -613,11 +724,11 @@ __device__ __forceinline__ void run_rows_pipelined(
         }
         const X s = gamma * (acc - bi) * inv_w;
         // 4. lock-free scatter
-        chunk_scatter(un, 0, nnz, s);
+        chunk_scatter(un, xa, 0, nnz, s);
         for (int base = G * UPL; base < nunits; base += G * UPL) {
             Unit<VK> t[UPL];
             fetch_chunk(rec, base, nunits, t);
-            chunk_scatter(t, base, nnz, s);
+            chunk_scatter_reread(t, base, nnz, s);
         }
         if constexpr (TRACE) {
             ++mine;
@@ -656,6 +767,243 @@ __device__ __forceinline__ void run_rows_pipelined(
         i1 = i2;
         l1 = l2;
     }
+}
+
+// s_waitcnt immediate (gfx9 encoding) for vmcnt(0) alone: expcnt(7) and
+// lgkmcnt(15) are their maxima, i.e. no wait on those counters.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Tickets per batch of the batched worker loop: B records held in registers,
+// so fewer for wider rows per lane (units per lane UPL).
+template <int UPL> struct BatchOf { static constexpr int value = UPL == 1 ? 8 : (UPL == 2 ? 4 : 2); };
+
+// The same tickets as run_rows_pipelined (all-coordinate update, rows from
+// `pick`), with the row records fetched in batches.  A wave's vector loads
+// complete in order, so a wait for a ticket's gathers is also a wait for
+// every record requested before them: a record requested one ticket ahead
+// puts an HBM round trip on every ticket, whatever else overlaps it.  Here
+// the only loads between batch boundaries are the tickets' own gathers (and
+// the extra chunks of long rows).  At a boundary the wave requests the
+// records of the next B tickets, whose locators arrived at the previous
+// boundary, together with the draws' locators of the batch after, waits for
+// them once, takes the alias decisions (a taken alias re-reads its row and
+// waits for it), and then runs the B tickets back to back: gathers, wait,
+// dot, atomics.  One record round trip per B tickets instead of per ticket.
+// Reads of x happen exactly where the other loops make them (after the
+// worker's previous atomics, in program order), so a lone worker still
+// equals the sequential oracle.  TRACE as in run_rows_pipelined.
+template <int VK, int XK, int G, int UPL, bool TRACE, class Pick>
+__device__ __forceinline__ void run_rows_batched(
+    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
+    const double2 *side, int64_t j, int64_t j_end, int64_t step, int uniform,
+    typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int gl, const Pick pick,
+    uint64_t *tau_ctr = nullptr, int64_t wave = 0, TauAcc *tacc = nullptr) {
+    using T = VT<VK>;
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    using H = typename T::hdr_t;
+    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
+    constexpr int U = T::U;
+    constexpr int B = BatchOf<UPL>::value;
+    if constexpr (G == 64) {
+        j = wave_uniform(j);
+        j_end = wave_uniform(j_end);
+        step = wave_uniform(step);
+    }
+    if (j >= j_end) return;
+
+    static_assert(T::UB <= (int)sizeof(kZeroPad), "zero pad smaller than a unit");
+    auto fetch_chunk = [&](const uint8_t *rec, int base, int nunits, Unit<VK> *dst) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) {
+            const int uu = base + gl + q * G;
+            dst[q].load(uu < nunits ? rec + T::HB + (int64_t)uu * T::UB : kZeroPad);
+        }
+    };
+    auto gather_issue = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U], X *(*xa)[U]) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const bool ok = (base + gl + q * G) * U + e < nnz;
+                xa[q][e] = xat(x, ok ? cu[q].c[e] : 0, xsh);
+                xv[q][e] = load_agent(xa[q][e]);
+            }
+    };
+    auto gather_dot = [&](const Unit<VK> *cu, int base, int nnz, X (*xv)[U], X acc) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const bool ok = (base + gl + q * G) * U + e < nnz;
+                acc = ok ? fma((X)cu[q].v[e], xv[q][e], acc) : acc;
+            }
+        return acc;
+    };
+    // the scatter of a chunk whose gathers computed the addresses xa
+    auto chunk_scatter = [&](const Unit<VK> *cu, X *(*xa)[U], int base, int nnz, X s) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e)
+                if ((base + gl + q * G) * U + e < nnz) atomic_add(xa[q][e], -s * (X)cu[q].v[e]);
+    };
+    // the scatter of a chunk re-read from the record (long rows)
+    auto chunk_scatter_reread = [&](const Unit<VK> *cu, int base, int nnz, X s) {
+#pragma unroll
+        for (int q = 0; q < UPL; ++q)
+#pragma unroll
+            for (int e = 0; e < U; ++e)
+                if ((base + gl + q * G) * U + e < nnz) atomic_add(xat(x, cu[q].c[e], xsh), -s * (X)cu[q].v[e]);
+    };
+    auto locator_load = [&](uint32_t r) -> RowLoc {
+        return gload<RowLoc>(rows.loc != nullptr ? (const void *)(rows.loc + r) : (const void *)kZeroPad);
+    };
+    auto from_locator = [&](uint32_t r, const RowLoc &l, const uint8_t *&rec, int &nnz) {
+        const bool ragged = rows.loc != nullptr;
+        rec = ragged ? rows.rec + (int64_t)l.off16 * 16 : rows.rec + (int64_t)r * rows.stride;
+        nnz = ragged ? (int)l.nnz : rows.fixed_nnz;
+    };
+
+    // the batch in registers: slot b holds ticket jb + b * step
+    uint32_t si[B], suc[B];
+    const uint8_t *srec[B];
+    int snnz[B];
+    H sh[B];
+    Unit<VK> sun[B][UPL];
+    double2 ssd[B];
+    X sbi[B], sinv[B];
+    // the next batch's draws and locators
+    uint32_t ni[B], nuc[B];
+    RowLoc nl[B];
+
+    // the draws and locators of the batch that starts at ticket jn.  With
+    // G >= 16 lane b of a group draws ticket jn + b * step (one pass of the
+    // generator for the whole batch) and every lane reads its group's B draws
+    // back; narrower groups draw ticket by ticket.
+    auto draw_batch = [&](int64_t jn) {
+        if constexpr (G >= 16) {
+            uint32_t il;
+            const U4 ul = pick(jn + (int64_t)(gl % B) * step, il);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ni[b] = as_varying(group_lane<G>(il, b));
+                nuc[b] = group_lane<G>(ul.c, b);
+                nl[b] = locator_load(ni[b]);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                nuc[b] = pick(jn + (int64_t)b * step, ni[b]).c;
+                nl[b] = locator_load(ni[b]);
+            }
+        }
+    };
+    // the records of the batch whose locators arrived, then the draws and
+    // locators of the batch after it (first ticket jn), all requested together
+    auto request_batch = [&](int64_t jn) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            si[b] = ni[b];
+            suc[b] = nuc[b];
+            from_locator(si[b], nl[b], srec[b], snnz[b]);
+            if constexpr (SIDE) {
+                const gv2u ta = gload<gv2u>(srec[b] + offsetof(H, thresh));
+                sh[b].thresh = ta.x;
+                sh[b].alias = (int32_t)ta.y;
+            } else {
+                sh[b] = load_hdr<VK>(srec[b]);
+            }
+            fetch_chunk(srec[b], 0, (snnz[b] + U - 1) / U, sun[b]);
+            if constexpr (SIDE) ssd[b] = gload<double2>(side + si[b]);
+        }
+        draw_batch(jn);
+    };
+    // the alias decisions of the batch (its loads have arrived), then b_i, 1/w_i
+    auto resolve_batch = [&]() {
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (!uniform && !(suc[b] < sh[b].thresh)) {
+                si[b] = (uint32_t)sh[b].alias;
+                locate_nb(rows, si[b], srec[b], snnz[b]);
+                sh[b] = load_hdr<VK>(srec[b]);
+                fetch_chunk(srec[b], 0, (snnz[b] + U - 1) / U, sun[b]);
+                if constexpr (SIDE) ssd[b] = gload<double2>(side + si[b]);
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            }
+            if constexpr (SIDE) {
+                sbi[b] = ssd[b].x;
+                sinv[b] = ssd[b].y;
+            } else {
+                sbi[b] = (X)sh[b].b;
+                sinv[b] = (X)sh[b].inv_w;
+            }
+        }
+    };
+
+    // prologue: the first batch's draws and locators
+    draw_batch(j);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+
+    int64_t nstep = 0;
+    uint32_t mine = 0;
+    uint64_t c0v[kTauShards], c1v[kTauShards];
+    for (;;) {
+        request_batch(j + (int64_t)B * step);
+        resolve_batch();
+        bool done = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (!done) {
+                const int nnz = snnz[b];
+                const int nunits = (nnz + U - 1) / U;
+                const bool samp = TRACE && (nstep % kTauPeriod == kTauFlush);
+                uint64_t t0 = 0, t1 = 0;
+                X xv[UPL][U];
+                X *xa[UPL][U];
+                gather_issue(sun[b], 0, nnz, xv, xa);
+                if constexpr (TRACE) {
+                    if (samp) {
+                        tau_issue(tau_ctr, c0v);
+                        t0 = wall_clock64();
+                    }
+                }
+                X acc = gather_dot(sun[b], 0, nnz, xv, (X)0);
+                for (int base = G * UPL; base < nunits; base += G * UPL) {
+                    Unit<VK> tu[UPL];
+                    fetch_chunk(srec[b], base, nunits, tu);
+                    X tv[UPL][U];
+                    X *ta[UPL][U];
+                    gather_issue(tu, base, nnz, tv, ta);
+                    acc = gather_dot(tu, base, nnz, tv, acc);
+                }
+                acc = group_sum<G>(acc);
+                if constexpr (TRACE) {
+                    if (samp) {
+                        tau_issue(tau_ctr, c1v);
+                        t1 = wall_clock64();
+                    }
+                }
+                const X s = gamma * (acc - sbi[b]) * sinv[b];
+                chunk_scatter(sun[b], xa, 0, nnz, s);
+                for (int base = G * UPL; base < nunits; base += G * UPL) {
+                    Unit<VK> tu[UPL];
+                    fetch_chunk(srec[b], base, nunits, tu);
+                    chunk_scatter_reread(tu, base, nnz, s);
+                }
+                if constexpr (TRACE) {
+                    ++mine;
+                    if (nstep % kTauFlush == kTauFlush - 1) tau_flush_wave(tau_ctr, wave, gl, mine);
+                    ++nstep;
+                    if (samp) tau_accumulate(*tacc, tau_sum(c0v), tau_sum(c1v), t0, t1);
+                }
+                j += step;
+                done = j >= j_end;
+            }
+        }
+        if (done) break;
+    }
+    if constexpr (TRACE) tau_flush_leader(tau_ctr, wave, gl, mine);
 }
 
 // Sampled rows: ticket j's Philox draw and its bucket.

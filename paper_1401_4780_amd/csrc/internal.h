@@ -55,7 +55,7 @@ struct SweepArgs {
     uint64_t *trace;       // nullable: staleness samples, kTraceWords words per wave (device.h)
     uint64_t *tau_ctr;     // the completion counter's shards when trace is set
     int32_t slices;        // 1: without-replacement slice scheme (t_begin, t_end are sweep multiples)
-    int32_t pipe;          // 1: software-pipelined worker loop (asynchronous, all-coordinate)
+    int32_t pipe;          // worker loop (asynchronous, all-coordinate): 1 software-pipelined, 2 batched records
 };
 
 // ---------------------------------------------------------------------------
@@ -69,10 +69,11 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
                                              uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        // each 64-bit product is one multiply-add instruction (both halves)
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo_a = (uint32_t)pa, hi_a = (uint32_t)(pa >> 32);
+        const uint32_t lo_b = (uint32_t)pb, hi_b = (uint32_t)(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;

@@ -51,9 +51,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const SweepArgs a) {
 }
 
 // The same worker loop with the steps of consecutive tickets overlapped
-// (run_tickets_pipelined): for asynchronous, all-coordinate sweeps.  TRACE:
-// the instance that samples the staleness.
-template <int VK, int XK, int G, bool TRACE>
+// (LOOP 1, run_tickets_pipelined) or with the records fetched in batches
+// (LOOP 2, run_rows_batched): for asynchronous, all-coordinate sweeps.
+// TRACE: the instance that samples the staleness.
+template <int VK, int XK, int G, bool TRACE, int LOOP>
 __global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -62,9 +63,14 @@ __global__ __launch_bounds__(256) void sweep_pipe_kernel(const SweepArgs a) {
     const int64_t worker = wave * (64 / G) + (lane / G);
     if (worker >= a.R) return;
     TauAcc acc;
-    run_tickets_pipelined<VK, XK, G, Upl<G>::value, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side,
-                                                           a.t_begin + worker, a.t_end, a.R, a.stream_id, a.key0,
-                                                           a.key1, a.uniform, (X)a.gamma, gl, a.tau_ctr, wave, &acc);
+    if constexpr (LOOP == 2)
+        run_rows_batched<VK, XK, G, Upl<G>::value, TRACE>(
+            a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, a.t_begin + worker, a.t_end, a.R, a.uniform,
+            (X)a.gamma, gl, SampledPick{(uint32_t)a.rows.m, a.stream_id, a.key0, a.key1}, a.tau_ctr, wave, &acc);
+    else
+        run_tickets_pipelined<VK, XK, G, Upl<G>::value, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side,
+                                                               a.t_begin + worker, a.t_end, a.R, a.stream_id, a.key0,
+                                                               a.key1, a.uniform, (X)a.gamma, gl, a.tau_ctr, wave, &acc);
     if constexpr (TRACE) tau_store(acc, a.trace, wave, lane);
 }
 
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(256) void sweep_slices_kernel(const SweepArgs a) {
 
 // The same slice walks, each fed to the software-pipelined worker loop as a
 // stream of tickets (asynchronous, all-coordinate sweeps).
-template <int VK, int XK, int G, bool TRACE>
+template <int VK, int XK, int G, bool TRACE, int LOOP>
 __global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs a) {
     using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
     const int lane = threadIdx.x & 63;
@@ -127,11 +133,17 @@ __global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs 
     const int64_t start = worker * L;
     const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
     TauAcc acc;
-    if (Lw > 0)
-        run_rows_pipelined<VK, XK, G, Upl<G>::value, TRACE>(
-            a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, 0, (a.t_end - a.t_begin) / m * Lw, 1, 1,
-            (X)a.gamma, gl, SlicePick{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1},
-            a.tau_ctr, wave, &acc);
+    const SlicePick walk{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1};
+    if (Lw > 0) {
+        if constexpr (LOOP == 2)
+            run_rows_batched<VK, XK, G, Upl<G>::value, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side,
+                                                              0, (a.t_end - a.t_begin) / m * Lw, 1, 1, (X)a.gamma,
+                                                              gl, walk, a.tau_ctr, wave, &acc);
+        else
+            run_rows_pipelined<VK, XK, G, Upl<G>::value, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side,
+                                                                0, (a.t_end - a.t_begin) / m * Lw, 1, 1, (X)a.gamma,
+                                                                gl, walk, a.tau_ctr, wave, &acc);
+    }
     if constexpr (TRACE) tau_store(acc, a.trace, wave, lane);
 }
 
@@ -166,13 +178,21 @@ static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
     int64_t grid;
     int block;
     sweep_geometry(a, G, &grid, &block);
+    if (a.pipe == 2 && a.trace)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, true, 2>), dim3(grid), dim3(block), 0, st, a);
+        });
+    if (a.pipe == 2)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, false, 2>), dim3(grid), dim3(block), 0, st, a);
+        });
     if (a.pipe && a.trace)
         return dispatch_lanes(G, [&](auto g) {
-            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, true>), dim3(grid), dim3(block), 0, st, a);
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, true, 1>), dim3(grid), dim3(block), 0, st, a);
         });
     if (a.pipe)
         return dispatch_lanes(G, [&](auto g) {
-            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, false>), dim3(grid), dim3(block), 0, st, a);
+            hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, false, 1>), dim3(grid), dim3(block), 0, st, a);
         });
     return dispatch_lanes(G, [&](auto g) {
         hipLaunchKernelGGL((sweep_slices_kernel<VK, XK, decltype(g)::value>), dim3(grid), dim3(block), 0, st, a);
@@ -200,13 +220,21 @@ static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     int64_t grid;
     int block;
     sweep_geometry(a, G, &grid, &block);
+    if (a.pipe == 2 && a.trace)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, true, 2>), dim3(grid), dim3(block), 0, st, a);
+        });
+    if (a.pipe == 2)
+        return dispatch_lanes(G, [&](auto g) {
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, false, 2>), dim3(grid), dim3(block), 0, st, a);
+        });
     if (a.pipe && a.trace)
         return dispatch_lanes(G, [&](auto g) {
-            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, true>), dim3(grid), dim3(block), 0, st, a);
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, true, 1>), dim3(grid), dim3(block), 0, st, a);
         });
     if (a.pipe)
         return dispatch_lanes(G, [&](auto g) {
-            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, false>), dim3(grid), dim3(block), 0, st, a);
+            hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, false, 1>), dim3(grid), dim3(block), 0, st, a);
         });
     return dispatch_lanes(G, [&](auto g) {
         hipLaunchKernelGGL((sweep_kernel<VK, XK, decltype(g)::value>), dim3(grid), dim3(block), 0, st, a);

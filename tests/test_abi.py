@@ -28,7 +28,7 @@ def test_library_exports_every_declared_function():
     assert "asyrk_create" in names and "asyrk_solve" in names and "asyrk_residual" in names
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
-    assert L.asyrk_abi_version() == 2
+    assert L.asyrk_abi_version() == 3
 
 
 def _c_layout(struct, fields):

@@ -531,14 +531,16 @@ def test_autotune_picks_a_lane_width():
     _say("autotune")
     sysm = make_system(s, device=True)
     best, pipe, rates = sysm.autotune(in_flight=800)
-    assert best in (1, 2, 4, 8, 16, 32, 64) and len(rates) == 14 and all(r > 0 for r in rates.values())
-    best_plain = max(r for (g, p), r in rates.items() if not p)
-    best_pipe = max(r for (g, p), r in rates.items() if p)
-    assert pipe == (best_pipe > 1.03 * best_plain)
-    top = best_pipe if pipe else best_plain
-    assert best == min(g for (g, p), r in rates.items() if p == pipe and r >= 0.97 * top)
+    assert best in (1, 2, 4, 8, 16, 32, 64) and len(rates) == 21 and all(r > 0 for r in rates.values())
+    top = {lp: max(r for (g, p), r in rates.items() if p == lp) for lp in (0, 1, 2)}
+    want = 0
+    for lp in (1, 2):
+        if top[lp] > 1.03 * top[want]:
+            want = lp
+    assert pipe == want, (pipe, top)
+    assert best == min(g for (g, p), r in rates.items() if p == pipe and r >= 0.97 * top[pipe])
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6, in_flight=800)
-    assert st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
+    assert st["lanes"] == best and st["pipelined"] == pipe and st["status"] == "OK"
     # the tuned loop applies at the tuned R only; elsewhere the rule (R <= 8192)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=20_000)
     assert st["pipelined"] == 0
@@ -550,7 +552,7 @@ def test_autotune_picks_a_lane_width():
     R = sysm.info()["tuned_in_flight"]
     assert R == R_max or (R >= 1024 and R < R_max and R & (R - 1) == 0)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=200, seed=1, tol=1e-6)
-    assert st["in_flight"] == R and st["lanes"] == best and st["pipelined"] == int(pipe) and st["status"] == "OK"
+    assert st["in_flight"] == R and st["lanes"] == best and st["pipelined"] == pipe and st["status"] == "OK"
     # other kinds of solve were not timed at that R: they keep the default one,
     # and the lane rule (the tuned pair is not theirs either)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, order="slices")
@@ -578,8 +580,11 @@ def test_autotune_picks_a_lane_width():
 
 @pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f64"), (4, "f32"), (1, "bf16"),
                                          (16, "bf16")])
-def test_pipelined_single_worker_matches_oracle(lanes, dtype):
-    """One asynchronous worker running the pipelined loop performs plain RK:
+@pytest.mark.parametrize("loop", [1, 2])
+def test_pipelined_single_worker_matches_oracle(lanes, dtype, loop):
+    """One asynchronous worker running the pipelined loop (1) or the batched
+    loop (2, records of the next batch of tickets fetched while the current
+    batch is processed) performs plain RK:
     its gathers for ticket t + 1 must see its own atomics of ticket t (ragged
     rows of 1..37 entries, three 300-entry rows that take the multi-chunk path,
     norm-weighted sampling through the alias branch).  FP32/BF16 values take
@@ -589,19 +594,20 @@ def test_pipelined_single_worker_matches_oracle(lanes, dtype):
     lens = rng.integers(1, 38, 700)
     lens[[3, 100, 555]] = 300
     s = synth.ragged_rows(700, 400, lens, seed=5, dtype=dtype)
-    _say(f"pipelined single worker lanes={lanes} values={dtype}")
+    _say(f"pipelined single worker lanes={lanes} values={dtype} loop={loop}")
     ref = oracle_run(s, 0.9, 6, 11)
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=0.9, sweeps=6, seed=11, in_flight=1, lanes=lanes,
-                      pipeline=True, history=16)
-    assert st["status"] == "OK" and st["pipelined"] == 1
+                      pipeline=loop, history=16)
+    assert st["status"] == "OK" and st["pipelined"] == loop
     assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
     sysm.close()
 
 
 @pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16")])
-def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype):
+@pytest.mark.parametrize("loop", [1, 2])
+def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype, loop):
     """One asynchronous worker walking its slice (all rows) through the
     pipelined loop is the oracle's one-worker slice scheme: 1e-12, ragged rows
     with three multi-chunk ones, several sweeps, and a resume at a sweep
@@ -610,18 +616,18 @@ def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype):
     lens = rng.integers(1, 38, 900)
     lens[[7, 200, 899]] = 300
     s = synth.ragged_rows(900, 450, lens, seed=6, dtype=dtype)
-    _say(f"pipelined single-worker slices lanes={lanes} values={dtype}")
+    _say(f"pipelined single-worker slices lanes={lanes} values={dtype} loop={loop}")
     ref = oracle_run(s, 0.8, 5, 9, slices=True, workers=1)
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=0.8, sweeps=5, seed=9, in_flight=1, lanes=lanes,
-                      order="slices", pipeline=True, history=8)
-    assert st["status"] == "OK" and st["pipelined"] == 1
+                      order="slices", pipeline=loop, history=8)
+    assert st["status"] == "OK" and st["pipelined"] == loop
     assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-12
     torch = _torch()
     x3 = torch.zeros(s.n, dtype=torch.float64, device="cuda")
-    st = sysm.solve(x3, 0.8, 2, 9, in_flight=1, lanes=lanes, order="slices", pipeline=True)
-    sysm.solve(x3, 0.8, 3, 9, in_flight=1, lanes=lanes, order="slices", pipeline=True,
+    st = sysm.solve(x3, 0.8, 2, 9, in_flight=1, lanes=lanes, order="slices", pipeline=loop)
+    sysm.solve(x3, 0.8, 3, 9, in_flight=1, lanes=lanes, order="slices", pipeline=loop,
                ticket0=st["next_ticket"])
     assert np.linalg.norm(x3.cpu().numpy() - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     sysm.close()
@@ -636,20 +642,21 @@ PIPE_CASES = {
 
 @pytest.mark.parametrize("case", sorted(PIPE_CASES))
 def test_pipelined_async_matches_plain_loop(case):
-    """Many workers: the pipelined loop reaches 1e-6 in about the sweeps the
-    plain loop needs (same R, lanes, seed)."""
+    """Many workers: the pipelined and batched loops reach 1e-6 in about the
+    sweeps the plain loop needs (same R, lanes, seed)."""
     make, it = PIPE_CASES[case]
     s = make()
     _say(f"pipelined async {case}")
     sysm = make_system(s, device=True)
     out = {}
-    for pipe in (False, True):
+    for pipe in (0, 1, 2):
         x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=300, seed=3, tol=1e-6, in_flight=512,
                           lanes=4, pipeline=pipe, iter_dtype=it)
-        assert st["status"] == "OK" and st["pipelined"] == int(pipe), (pipe, st["status"])
+        assert st["status"] == "OK" and st["pipelined"] == pipe, (pipe, st["status"])
         assert np.linalg.norm(x - s.x_star) <= 1.05e-6 * np.linalg.norm(s.x_star)
         out[pipe] = st["sweeps_done"]
-    assert out[True] <= 1.5 * out[False] + 1, out
+    assert out[1] <= 1.5 * out[0] + 1, out
+    assert out[2] <= 1.5 * out[0] + 1, out
     sysm.close()
 
 
@@ -665,16 +672,21 @@ def test_pipelined_option_checks():
         assert st["pipelined"] == 0, kw
     # tracing keeps the loop the solve would run without it
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64, trace=True)
-    assert st["pipelined"] == 1 and st["tau_samples"] > 0
-    # slice walks run in either loop; few workers take the pipelined one
+    assert st["pipelined"] == 2 and st["tau_samples"] > 0
+    # slice walks run in any loop; few workers take the batched one
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, order="slices", in_flight=64)
-    assert st["pipelined"] == 1
+    assert st["pipelined"] == 2
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, order="slices", in_flight=64, pipeline=False)
     assert st["pipelined"] == 0
-    st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64)
-    assert st["pipelined"] == 1  # the rule for few workers
+    # the rule: batched up to 1024 workers, pipelined up to 8192, plain above
+    for R, loop in ((64, 2), (1024, 2), (1025, 1), (8192, 1), (8193, 0)):
+        st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=R)
+        assert st["pipelined"] == loop, (R, st["pipelined"])
     st = sysm.solve(np.zeros(s.n), 1.0, 1, 0, in_flight=64, pipeline=False)
     assert st["pipelined"] == 0
+    with pytest.raises(P.AsyrkError) as ei:
+        sysm.solve(np.zeros(s.n), 1.0, 1, 0, pipeline=3)
+    assert ei.value.name == "INVALID_ARG"
     sysm.close()
 
 

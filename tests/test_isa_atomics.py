@@ -89,20 +89,37 @@ def test_pipelined_gathers_issue_back_to_back(kernels):
     pipe = {k: v for k, v in kernels.items() if "sweep_pipe_kernel" in k}
     assert len(pipe) >= 35
     for name, body in pipe.items():
-        run = best = 0
-        for line in body.splitlines():
-            t = line.strip()
-            if re.match(r"(global|flat)_load_dword(x2)?\b.*\bsc1\b", t):
-                run += 1
-                best = max(best, run)
-            elif t.startswith("s_waitcnt"):
-                run = 0
+        best = _longest_gather_run(body)
         # at least one unit's entries leave together: a lane whose units are
         # still arriving issues each unit's gathers as soon as that unit lands
-        # (waits for unit data, not between gathers); serialized gathers would
+        # (its waits retire unit data, not gathers); serialized gathers would
         # show runs of one
         want = min(_lane_entries(name), _unit_entries(name))
         assert best >= want, (name, best, want)
+
+
+def _longest_gather_run(body):
+    """Most coherent gathers (sc1 loads) issued with no wait between them
+    that retires a gather.  Vector memory operations retire in issue order, so
+    s_waitcnt vmcnt(N) retires all but the newest N outstanding ones; the
+    queue is followed in program order through the listing."""
+    queue, run, best = [], 0, 0
+    for line in body.splitlines():
+        t = line.strip()
+        if re.match(r"(global|flat|buffer)_(load|store|atomic)", t):
+            g = re.match(r"(global|flat)_load_dword(x2)?\b.*\bsc1\b", t) is not None
+            queue.append(g)
+            if g:
+                run += 1
+                best = max(best, run)
+        else:
+            w = re.match(r"s_waitcnt\b.*\bvmcnt\((\d+)\)", t)
+            if w:
+                keep = int(w.group(1))
+                done, queue = (queue[:-keep], queue[-keep:]) if keep else (queue, [])
+                if any(done):
+                    run = 0
+    return best
 
 
 def test_device_setup_weights_are_unfused(kernels):
