@@ -190,7 +190,7 @@ def run_c2(args):
     per_launch_s = kern_s / launches
     achieved = bytes_per_row * M / per_launch_s / 1e9
     kernel = (("sweep_pipe_kernel" if sts[0]["pipelined"] else "sweep_kernel")
-              + f"<F32,F64,{sts[0]['lanes']}>")
+              + f"<F32,F64,{sts[0]['lanes']}{',batched' if sts[0]['pipelined'] == 2 else ''}>")
     traffic = traffic_from_profile(kernel, sts[0]["in_flight"])
 
     result = {
