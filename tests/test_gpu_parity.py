@@ -419,6 +419,24 @@ def test_lambda_max_power_iteration():
     sysm.close()
 
 
+def test_lambda_max_power_iteration_with_a_spectral_gap():
+    """Zipf columns: the hottest column dominates A^T A, so lambda_1 stands
+    apart (lambda_2 / lambda_1 ~ 0.74 here) and the Rayleigh quotient's error
+    falls like (lambda_2 / lambda_1)^(2k): after 200 steps it is at rounding
+    level, so the estimate must equal eigvalsh's lambda_max to 1e-10."""
+    s = synth.skewed_rows(3000, 600, seed=4, dtype="f64")
+    _say("lambda_max with a spectral gap")
+    A = s.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    assert ev[-2] / ev[-1] < 0.8
+    sysm = make_system(s, device=True)
+    lam, tau = sysm.lambda_max(iters=200, seed=1)
+    assert abs(lam - ev[-1]) <= 1e-10 * ev[-1], (lam, ev[-1])
+    fro2 = float(np.sum(s.val64 ** 2))
+    assert tau == math.floor(fro2 / (2 * math.e * lam)) - 1
+    sysm.close()
+
+
 def test_edge_cases():
     _say("edge cases")
     # one row
