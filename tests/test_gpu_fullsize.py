@@ -16,7 +16,10 @@ at any size:
     (R far below Corollary 1's bound: the asynchronous curve tracks plain RK);
   * the benchmark's other legs reach 1e-6 too: slices without replacement in
     fewer sweeps than sampled rows, Algorithm 1's single-coordinate update
-    (gamma = 1/mu, uniform rows) within its budget.
+    (gamma = 1/mu, uniform rows) within its budget;
+  * one worker alone, in the pipelined and in the batched loop, performs
+    sequential RK over a whole sweep: equal to the oracle to 1e-12 (also on
+    the skewed system, whose long rows take several chunks).
 """
 import sys
 
@@ -103,6 +106,25 @@ def test_fullsize_bench_configuration_tracks_the_oracle(big):
          f"{ref['err'][1]:.4f} {ref['err'][2]:.4f}")
 
 
+def test_fullsize_lone_worker_loops_equal_the_oracle(big):
+    """One worker (R = 1, a wave per row) for a whole sweep of the full system,
+    in the pipelined and in the batched loop: each ticket reads x after the
+    worker's previous atomics, so the run is sequential RK on the oracle's
+    ticket sequence, 4,000,000 tickets, equal to the FP64 oracle to 1e-12."""
+    import torch
+    s, sysm, d = big
+    _say("full-size oracle: one sweep")
+    ref = oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, N, np.zeros(N), 1.0, M, 21, want_res=False)
+    nref = np.linalg.norm(ref["x"])
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for loop in (1, 2):
+        _say(f"full-size lone worker, loop {loop}")
+        x.zero_()
+        st = sysm.solve(x, 1.0, 1, 21, in_flight=1, lanes=64, pipeline=loop, final_resid=False)
+        assert st["status"] == "OK" and st["pipelined"] == loop and st["row_updates"] == M, st
+        assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-12 * nref, loop
+
+
 def test_fullsize_slices_and_algorithm1(big):
     import torch
     s, sysm, d = big
@@ -178,5 +200,13 @@ def test_fullsize_skewed_threshold():
     x.zero_()
     st = sysm.solve(x, 1.0, 5, 5, x_ref=d(s.x_star), in_flight=16384, history=8)
     assert st["status"] == "DIVERGED", st
+    # the batched loop with a lone wave-wide worker at this size (rows of up
+    # to 2000 entries take several chunks): sequential RK, equal to the oracle
+    _say("full-size skewed: lone batched worker against the oracle, one sweep")
+    ref = oracle.rk_run(s.row_ptr, s.col, s.val64, s.b, s.n, np.zeros(s.n), 1.0, s.m, 23, want_res=False)
+    x.zero_()
+    st1 = sysm.solve(x, 1.0, 1, 23, in_flight=1, lanes=64, pipeline=2, final_resid=False)
+    assert st1["status"] == "OK" and st1["pipelined"] == 2
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     _say(f"full-size skewed: R0={R0} err after 5 sweeps {h[5]:.3f}; R=16384 diverged after {st['sweeps_done']}")
     sysm.close()
