@@ -408,7 +408,10 @@ class System:
               history=0, iter_dtype=None, order="replacement", pipeline=None, final_resid=True) -> dict:
         """Run from x (float64, overwritten with the result).  Returns the stats
         as a dict with ``status`` ("OK", "NOT_CONVERGED", "DIVERGED" or
-        "CANCELLED") and, when ``history`` > 0, the monitored-error history."""
+        "CANCELLED") and, when ``history`` > 0, the monitored-error history.
+        ``pipeline``: None for the library's choice, 0 (or False) the plain
+        worker loop, 1 (or True) the pipelined one, 2 the batched one; the
+        stats' ``pipelined`` names the loop that ran."""
         _expect(x, self.device, "float64", "x")
         _expect_len(x, self.n, "x")
         if x_ref is not None:
