@@ -304,8 +304,8 @@ def test_refinement_reaches_1e10(dtype, inner):
 # completed between a sampled ticket's read of x and its scatter, counted by
 # a completion counter every wave advances after each step.
 
-@pytest.mark.parametrize("pipeline,order", [(False, "replacement"), (True, "replacement"),
-                                            (False, "slices"), (True, "slices")])
+@pytest.mark.parametrize("pipeline,order", [(0, "replacement"), (1, "replacement"), (2, "replacement"),
+                                            (0, "slices"), (1, "slices"), (2, "slices")])
 def test_trace_lone_worker_sees_no_other_update(pipeline, order):
     """One worker: nobody else completes an update while its ticket is in
     flight, so every sampled delay is exactly 0 (in every worker loop)."""
@@ -322,7 +322,7 @@ def test_trace_lone_worker_sees_no_other_update(pipeline, order):
     sysm.close()
 
 
-@pytest.mark.parametrize("pipeline", [False, True])
+@pytest.mark.parametrize("pipeline", [0, 1, 2])
 def test_trace_staleness_grows_with_workers(pipeline):
     """More workers in flight, more updates land inside one ticket's window:
     the measured delay grows with R and stays of the order of R - 1 (each
@@ -344,16 +344,36 @@ def test_trace_staleness_grows_with_workers(pipeline):
     sysm.close()
 
 
-def test_traced_pipelined_solve_converges():
-    """The traced pipelined loop computes the same method: it reaches 1e-6."""
+@pytest.mark.parametrize("pipeline", [1, 2])
+def test_traced_pipelined_solve_converges(pipeline):
+    """The traced pipelined and batched loops compute the same method: they
+    reach 1e-6."""
     s = synth.uniform_rows(40_000, 10_000, 20, seed=1, dtype="f32")
-    _say("traced pipelined solve to 1e-6")
+    _say(f"traced solve to 1e-6, loop {pipeline}")
     sysm = make_system(s, device=True)
     x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=60, seed=4, tol=1e-6, in_flight=2048, trace=True,
-                      pipeline=True)
-    assert st["status"] == "OK" and st["pipelined"] == 1, st
+                      pipeline=pipeline)
+    assert st["status"] == "OK" and st["pipelined"] == pipeline, st
     assert np.linalg.norm(x - s.x_star) <= 1e-6 * np.linalg.norm(s.x_star)
     assert st["tau_design"] == 2047 and st["tau_samples"] > 0
+    sysm.close()
+
+
+@pytest.mark.parametrize("loop", [1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_lone_worker_fp32_iterate_within_fp32_floor(loop, dtype):
+    """One asynchronous worker with the FP32 iterate and FP32 atomics, in the
+    pipelined and batched loops: sequential RK in FP32 arithmetic, within 1e-6
+    of the FP64 oracle relative to ||x*|| (the FP32 floor of the replay test)."""
+    s = synth.uniform_rows(2000, 500, 10, seed=0, dtype=dtype)
+    _say(f"lone worker, FP32 iterate, {dtype} values, loop {loop}")
+    ref = oracle_run(s, 1.0, 20, 0)
+    sysm = make_system(s, device=True)
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, in_flight=1, lanes=16, pipeline=loop,
+                      iter_dtype="f32", history=32)
+    assert st["status"] == "OK" and st["pipelined"] == loop
+    assert np.linalg.norm(x - ref["x"]) <= 1e-6 * np.linalg.norm(s.x_star)
+    assert np.max(np.abs(st["history"] - ref["err"])) <= 1e-6
     sysm.close()
 
 
@@ -849,10 +869,11 @@ def test_iterate_stride_regimes_match_oracle(n, stride):
     ref = oracle_run(s32, 1.0, 3, 5)
     sysm = make_system(s32, device=True)
     assert sysm.info()["iterate_stride"] == stride
-    x, st = gpu_solve(sysm, s32, True, gamma=1.0, sweeps=3, seed=5, in_flight=1, lanes=4, pipeline=True,
-                      iter_dtype="f64", history=8)
-    assert st["status"] == "OK" and st["pipelined"] == 1
-    assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    for loop in (1, 2):
+        x, st = gpu_solve(sysm, s32, True, gamma=1.0, sweeps=3, seed=5, in_flight=1, lanes=4, pipeline=loop,
+                          iter_dtype="f64", history=8)
+        assert st["status"] == "OK" and st["pipelined"] == loop
+        assert np.linalg.norm(x - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
     x, st = gpu_solve(sysm, s32, True, gamma=1.0, sweeps=3, seed=5, mode="replay", iter_dtype="f32")
     assert st["status"] == "OK"
     assert np.linalg.norm(x - ref["x"]) <= 1e-6 * np.linalg.norm(s32.x_star)  # FP32 floor
