@@ -1068,4 +1068,229 @@ struct SlicePick {
     }
 };
 
+// ---------------------------------------------------------------- split worker
+//
+// A wave-wide worker (G = 64) split over two waves of one workgroup: the
+// fetch wave draws the rows of a batch of tickets, loads their locators and
+// records, takes the alias decisions and leaves each ticket's units and
+// scalars in LDS; the compute wave runs the tickets from LDS: gathers, dot,
+// sum, step, atomics.  The two alternate between two LDS buffers, one
+// barrier per batch: while the compute wave runs batch k, the fetch wave
+// fills the other buffer with batch k + 1.  The compute wave then issues no
+// record or locator loads of its own (rows longer than 64 units aside), so
+// its waits on the vector memory counter are for its gathers and its earlier
+// atomics only; LDS reads are counted apart.  Its reads of x happen where the
+// other loops make them (after the worker's previous atomics, in program
+// order), so a lone worker equals the sequential oracle.  Both waves run the
+// same number of batches, from values uniform over the workgroup, and pass
+// the same barriers; neither leaves the loop early.
+
+template <int VK> struct SplitBatch { static constexpr int value = VK == ASYRK_BF16 ? 4 : 8; };
+
+// One ticket's scalars in LDS (the units sit in their own array).
+template <int XK> struct SplitMeta {
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    const uint8_t *rec;
+    int nnz;
+    X bi, inv_w;
+};
+
+// Barrier of the two waves of a split worker; the fences order LDS only, so
+// the compute wave does not wait for its atomics here.
+__device__ __forceinline__ void split_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// role 0: compute wave, 1: fetch wave; lane = the lane in the wave.  j, j_end
+// and step must be the same in both waves.  lu / lm: the workgroup's two
+// batch buffers.
+template <int VK, int XK, bool TRACE, class Pick>
+__device__ __forceinline__ void run_rows_split(
+    const Rows rows, typename std::conditional<XK == ASYRK_F64, double, float>::type *x, int xsh,
+    const double2 *side, int64_t j, int64_t j_end, int64_t step, int uniform,
+    typename std::conditional<XK == ASYRK_F64, double, float>::type gamma, int role, int lane, const Pick pick,
+    Unit<VK> (*lu)[SplitBatch<VK>::value][64], SplitMeta<XK> (*lm)[SplitBatch<VK>::value],
+    uint64_t *tau_ctr = nullptr, int64_t wave = 0, TauAcc *tacc = nullptr) {
+    using T = VT<VK>;
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    using H = typename T::hdr_t;
+    constexpr bool SIDE = (XK == ASYRK_F64) && (VK != ASYRK_F64);
+    constexpr int G = 64;
+    constexpr int U = T::U;
+    constexpr int B = SplitBatch<VK>::value;
+    j = wave_uniform(j);
+    j_end = wave_uniform(j_end);
+    step = wave_uniform(step);
+    const int64_t span = (int64_t)B * step;
+    const int64_t nb = j < j_end ? (j_end - j + span - 1) / span : 0;
+    if (nb == 0) return;  // both waves alike, before any barrier
+
+    static_assert(T::UB <= (int)sizeof(kZeroPad), "zero pad smaller than a unit");
+    auto unit_at = [&](const uint8_t *rec, int uu, int nunits) -> const uint8_t * {
+        return uu < nunits ? rec + T::HB + (int64_t)uu * T::UB : kZeroPad;
+    };
+
+    if (role == 1) {
+        // ---- fetch wave: batch jb into buffer buf
+        auto fetch = [&](int64_t jb, int buf) {
+            uint32_t il;
+            const U4 ul = pick(jb + (int64_t)(lane % B) * step, il);
+            uint32_t ri[B], ru[B];
+            RowLoc rl[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ri[b] = as_varying(group_lane<G>(il, b));
+                ru[b] = group_lane<G>(ul.c, b);
+                rl[b] = gload<RowLoc>(rows.loc != nullptr ? (const void *)(rows.loc + ri[b]) : (const void *)kZeroPad);
+            }
+            const uint8_t *rec[B];
+            int nnz[B];
+            H h[B];
+            Unit<VK> un[B];
+            double2 sd[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const bool ragged = rows.loc != nullptr;
+                rec[b] = ragged ? rows.rec + (int64_t)rl[b].off16 * 16 : rows.rec + (int64_t)ri[b] * rows.stride;
+                nnz[b] = ragged ? (int)rl[b].nnz : rows.fixed_nnz;
+                h[b] = load_hdr<VK>(rec[b]);
+                un[b].load(unit_at(rec[b], lane, (nnz[b] + U - 1) / U));
+                if constexpr (SIDE) sd[b] = gload<double2>(side + ri[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (!uniform && !(ru[b] < h[b].thresh)) {
+                    ri[b] = (uint32_t)h[b].alias;
+                    locate_nb(rows, ri[b], rec[b], nnz[b]);
+                    h[b] = load_hdr<VK>(rec[b]);
+                    un[b].load(unit_at(rec[b], lane, (nnz[b] + U - 1) / U));
+                    if constexpr (SIDE) sd[b] = gload<double2>(side + ri[b]);
+                }
+                lu[buf][b][lane] = un[b];
+                if (lane == 0) {
+                    SplitMeta<XK> mt;
+                    mt.rec = rec[b];
+                    mt.nnz = nnz[b];
+                    if constexpr (SIDE) {
+                        mt.bi = sd[b].x;
+                        mt.inv_w = sd[b].y;
+                    } else {
+                        mt.bi = (X)h[b].b;
+                        mt.inv_w = (X)h[b].inv_w;
+                    }
+                    lm[buf][b] = mt;
+                }
+            }
+        };
+        fetch(j, 0);
+        split_barrier();
+        for (int64_t k = 0; k < nb; ++k) {
+            if (k + 1 < nb) fetch(j + (k + 1) * span, (int)((k + 1) & 1));
+            split_barrier();
+        }
+        return;
+    }
+
+    // ---- compute wave
+    auto gather_issue = [&](const Unit<VK> &cu, int base, int nnz, X *xv, X **xa) {
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+            const bool ok = (base + lane) * U + e < nnz;
+            xa[e] = xat(x, ok ? cu.c[e] : 0, xsh);
+            xv[e] = load_agent(xa[e]);
+        }
+    };
+    auto gather_dot = [&](const Unit<VK> &cu, int base, int nnz, const X *xv, X acc) {
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+            const bool ok = (base + lane) * U + e < nnz;
+            acc = ok ? fma((X)cu.v[e], xv[e], acc) : acc;
+        }
+        return acc;
+    };
+    auto scatter = [&](const Unit<VK> &cu, X *const *xa, int base, int nnz, X s) {
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+            if ((base + lane) * U + e < nnz) atomic_add(xa[e], -s * (X)cu.v[e]);
+    };
+    auto scatter_reread = [&](const Unit<VK> &cu, int base, int nnz, X s) {
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+            if ((base + lane) * U + e < nnz) atomic_add(xat(x, cu.c[e], xsh), -s * (X)cu.v[e]);
+    };
+
+    split_barrier();  // batch 0 is in buffer 0
+    int64_t nstep = 0;
+    uint32_t mine = 0;
+    uint64_t c0v[kTauShards], c1v[kTauShards];
+    for (int64_t k = 0; k < nb; ++k) {
+        const int buf = (int)(k & 1);
+        const int64_t jb = j + k * span;
+        Unit<VK> cu = lu[buf][0][lane];
+        SplitMeta<XK> mt = lm[buf][0];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (jb + (int64_t)b * step < j_end) {
+                const int nnz = mt.nnz;
+                const int nunits = (nnz + U - 1) / U;
+                const bool samp = TRACE && (nstep % kTauPeriod == kTauFlush);
+                uint64_t t0 = 0, t1 = 0;
+                X xv[U];
+                X *xa[U];
+                gather_issue(cu, 0, nnz, xv, xa);
+                if constexpr (TRACE) {
+                    if (samp) {
+                        tau_issue(tau_ctr, c0v);
+                        t0 = wall_clock64();
+                    }
+                }
+                // the next ticket's unit and scalars, read from LDS while
+                // these gathers are in flight (LDS reads wait on their own
+                // counter)
+                Unit<VK> ncu = cu;
+                SplitMeta<XK> nmt = mt;
+                if (b + 1 < B) {
+                    ncu = lu[buf][b + 1][lane];
+                    nmt = lm[buf][b + 1];
+                }
+                X acc = gather_dot(cu, 0, nnz, xv, (X)0);
+                for (int base = G; base < nunits; base += G) {
+                    Unit<VK> tu;
+                    tu.load(unit_at(mt.rec, base + lane, nunits));
+                    X tv[U];
+                    X *ta[U];
+                    gather_issue(tu, base, nnz, tv, ta);
+                    acc = gather_dot(tu, base, nnz, tv, acc);
+                }
+                acc = group_sum<G>(acc);
+                if constexpr (TRACE) {
+                    if (samp) {
+                        tau_issue(tau_ctr, c1v);
+                        t1 = wall_clock64();
+                    }
+                }
+                const X s = gamma * (acc - mt.bi) * mt.inv_w;
+                scatter(cu, xa, 0, nnz, s);
+                for (int base = G; base < nunits; base += G) {
+                    Unit<VK> tu;
+                    tu.load(unit_at(mt.rec, base + lane, nunits));
+                    scatter_reread(tu, base, nnz, s);
+                }
+                if constexpr (TRACE) {
+                    ++mine;
+                    if (nstep % kTauFlush == kTauFlush - 1) tau_flush_wave(tau_ctr, wave, lane, mine);
+                    ++nstep;
+                    if (samp) tau_accumulate(*tacc, tau_sum(c0v), tau_sum(c1v), t0, t1);
+                }
+                cu = ncu;
+                mt = nmt;
+            }
+        }
+        split_barrier();  // buffer buf is free again; the next batch is in the other one
+    }
+    if constexpr (TRACE) tau_flush_leader(tau_ctr, wave, lane, mine);
+}
+
 }  // namespace asyrk

@@ -147,6 +147,58 @@ __global__ __launch_bounds__(256) void sweep_slices_pipe_kernel(const SweepArgs 
     if constexpr (TRACE) tau_store(acc, a.trace, wave, lane);
 }
 
+// The batched loop of a wave-wide worker split over two waves (a fetch wave
+// and a compute wave, run_rows_split): one workgroup per worker, two LDS
+// batch buffers.  Sampled rows, or (SLICES) the worker's slice walk.
+template <int VK, int XK, bool TRACE, bool SLICES>
+__global__ __launch_bounds__(128) void sweep_split_kernel(const SweepArgs a) {
+    using X = typename std::conditional<XK == ASYRK_F64, double, float>::type;
+    constexpr int B = SplitBatch<VK>::value;
+    __shared__ Unit<VK> lu[2][B][64];
+    __shared__ SplitMeta<XK> lm[2][B];
+    // a scalar: each wave branches to its role as a whole and never runs the
+    // other role's code (whose barriers it would otherwise pass with no
+    // lanes active: s_barrier counts waves, not lanes)
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t worker = blockIdx.x;
+    if (worker >= a.R) return;  // the whole workgroup
+    TauAcc acc;
+    if constexpr (SLICES) {
+        const int64_t m = a.rows.m;
+        const int64_t L = (m + a.R - 1) / a.R;
+        const int64_t start = worker * L;
+        const int64_t Lw = start >= m ? 0 : (m - start < L ? m - start : L);
+        if (Lw > 0) {
+            const SlicePick walk{start, a.t_begin / m, (uint32_t)Lw, (uint32_t)worker, a.key0, a.key1};
+            run_rows_split<VK, XK, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, 0,
+                                          (a.t_end - a.t_begin) / m * Lw, 1, 1, (X)a.gamma, role, lane, walk, lu,
+                                          lm, a.tau_ctr, worker, &acc);
+        }
+    } else {
+        run_rows_split<VK, XK, TRACE>(a.rows, reinterpret_cast<X *>(a.x), a.xshift, a.side, a.t_begin + worker,
+                                      a.t_end, a.R, a.uniform, (X)a.gamma, role, lane,
+                                      SampledPick{(uint32_t)a.rows.m, a.stream_id, a.key0, a.key1}, lu, lm,
+                                      a.tau_ctr, worker, &acc);
+    }
+    if constexpr (TRACE) {
+        if (role == 0) tau_store(acc, a.trace, worker, lane);
+    }
+}
+
+// The batched loop with G = 64 runs split over two waves up to this many
+// workers (one workgroup of two waves per worker).
+constexpr int64_t kSplitMaxR = 512;
+
+template <int VK, int XK, bool SLICES>
+static hipError_t launch_split(const SweepArgs &a, hipStream_t st) {
+    if (a.trace)
+        hipLaunchKernelGGL((sweep_split_kernel<VK, XK, true, SLICES>), dim3(a.R), dim3(128), 0, st, a);
+    else
+        hipLaunchKernelGGL((sweep_split_kernel<VK, XK, false, SLICES>), dim3(a.R), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
 // Calls f(std::integral_constant<int, G>) for a lane-group width G in
 // {1, 2, 4, ..., 64}, then returns the launch status.
 template <class F>
@@ -178,6 +230,7 @@ static hipError_t launch_slices_vk(int G, const SweepArgs &a, hipStream_t st) {
     int64_t grid;
     int block;
     sweep_geometry(a, G, &grid, &block);
+    if (a.pipe == 2 && G == 64 && a.R <= kSplitMaxR) return launch_split<VK, XK, true>(a, st);
     if (a.pipe == 2 && a.trace)
         return dispatch_lanes(G, [&](auto g) {
             hipLaunchKernelGGL((sweep_slices_pipe_kernel<VK, XK, decltype(g)::value, true, 2>), dim3(grid), dim3(block), 0, st, a);
@@ -220,6 +273,7 @@ static hipError_t launch_sweep_vk(int G, const SweepArgs &a, hipStream_t st) {
     int64_t grid;
     int block;
     sweep_geometry(a, G, &grid, &block);
+    if (a.pipe == 2 && G == 64 && a.R <= kSplitMaxR) return launch_split<VK, XK, false>(a, st);
     if (a.pipe == 2 && a.trace)
         return dispatch_lanes(G, [&](auto g) {
             hipLaunchKernelGGL((sweep_pipe_kernel<VK, XK, decltype(g)::value, true, 2>), dim3(grid), dim3(block), 0, st, a);

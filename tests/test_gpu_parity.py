@@ -344,6 +344,36 @@ def test_trace_staleness_grows_with_workers(pipeline):
     sysm.close()
 
 
+@pytest.mark.parametrize("order", ["replacement", "slices"])
+def test_trace_split_worker(order):
+    """The batched loop with 64 lanes (a fetch wave and a compute wave per
+    worker, up to 512 workers): a lone worker measures exactly 0, the delay
+    grows with R, and the traced solve reaches 1e-6."""
+    s = synth.uniform_rows(200_000, 50_000, 20, seed=1, dtype="f32")
+    sysm = make_system(s, device=True)
+    _say(f"trace split worker R=1 order={order}")
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=1, in_flight=1, lanes=64, trace=True,
+                      pipeline=2, order=order)
+    assert st["pipelined"] == 2 and st["lanes"] == 64
+    assert st["tau_samples"] == len(range(4, s.m, 64))
+    assert st["tau_obs_max"] == 0 and st["tau_obs_mean"] == 0, st
+    means = []
+    for R in (16, 128, 512):
+        _say(f"trace split worker R={R} order={order}")
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=2, seed=R, in_flight=R, lanes=64, trace=True,
+                          pipeline=2, order=order)
+        assert st["tau_samples"] > 0 and st["tau_obs_max"] >= st["tau_obs_mean"] > 0, st
+        assert 0.05 * (R - 1) <= st["tau_obs_mean"] <= 8 * R, (R, st["tau_obs_mean"])
+        means.append(st["tau_obs_mean"])
+    assert means[0] < means[1] < means[2], means
+    _say(f"split worker to 1e-6 order={order}")
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=60, seed=4, tol=1e-6, in_flight=256, lanes=64,
+                      trace=True, pipeline=2, order=order)
+    assert st["status"] == "OK", st
+    assert np.linalg.norm(x - s.x_star) <= 1e-6 * np.linalg.norm(s.x_star)
+    sysm.close()
+
+
 @pytest.mark.parametrize("pipeline", [1, 2])
 def test_traced_pipelined_solve_converges(pipeline):
     """The traced pipelined and batched loops compute the same method: they
@@ -617,12 +647,13 @@ def test_autotune_picks_a_lane_width():
 # ------------------------------------------------------------------ pipelined worker loop
 
 @pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f64"), (4, "f32"), (1, "bf16"),
-                                         (16, "bf16")])
+                                         (16, "bf16"), (64, "f64"), (64, "f32"), (64, "bf16")])
 @pytest.mark.parametrize("loop", [1, 2])
 def test_pipelined_single_worker_matches_oracle(lanes, dtype, loop):
     """One asynchronous worker running the pipelined loop (1) or the batched
     loop (2, records of the next batch of tickets fetched while the current
-    batch is processed) performs plain RK:
+    batch is processed; with 64 lanes split over a fetch wave and a compute
+    wave that meet at a barrier per batch) performs plain RK:
     its gathers for ticket t + 1 must see its own atomics of ticket t (ragged
     rows of 1..37 entries, three 300-entry rows that take the multi-chunk path,
     norm-weighted sampling through the alias branch).  FP32/BF16 values take
@@ -643,7 +674,8 @@ def test_pipelined_single_worker_matches_oracle(lanes, dtype, loop):
     sysm.close()
 
 
-@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16")])
+@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16"), (64, "f64"),
+                                         (64, "f32"), (64, "bf16")])
 @pytest.mark.parametrize("loop", [1, 2])
 def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype, loop):
     """One asynchronous worker walking its slice (all rows) through the

@@ -6,6 +6,8 @@ package's own flags and checks what the hot path relies on:
 * every sweep kernel scatters with hardware float atomics
   (global/flat_atomic_add_f32 or _f64), never a compare-and-swap loop;
 * no packed-FP32 instruction appears anywhere (the build disables them);
+* the split worker's barriers (two waves, one barrier per batch) wait on the
+  LDS counter only, never on the vector memory counter;
 * the pipelined worker loop issues a lane's gathers for a ticket together:
   at least one unit's entries (4, or 8 for BF16) of agent-scope loads in a
   row with no wait between them, never one load per wait;
@@ -58,6 +60,21 @@ def test_sweeps_use_hardware_float_atomics(kernels):
     for name, body in sweeps.items():
         assert re.search(r"(global|flat)_atomic_add_f(32|64)\b", body), name
         assert "cmpswap" not in body, name
+
+
+def test_split_worker_barriers_wait_on_lds_only(kernels):
+    """The split worker's two waves meet at a barrier per batch; the fences
+    around it order LDS only, so no barrier waits on the vector memory
+    counter (which would make the compute wave wait for its own atomics)."""
+    split = {k: v for k, v in kernels.items() if "sweep_split_kernel" in k}
+    assert len(split) >= 20, len(split)
+    for name, body in split.items():
+        lines = [ln.strip() for ln in body.splitlines()]
+        bars = [i for i, ln in enumerate(lines) if ln.startswith("s_barrier")]
+        assert len(bars) >= 4, (name, len(bars))  # two per role
+        for i in bars:
+            for ln in lines[max(0, i - 6):i]:
+                assert not (ln.startswith("s_waitcnt") and "vmcnt" in ln), (name, ln)
 
 
 def test_no_packed_fp32_instructions(kernels):
