@@ -647,7 +647,7 @@ def test_autotune_picks_a_lane_width():
 # ------------------------------------------------------------------ pipelined worker loop
 
 @pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f64"), (4, "f32"), (1, "bf16"),
-                                         (16, "bf16"), (64, "f64"), (64, "f32"), (64, "bf16")])
+                                         (16, "bf16"), (32, "f32"), (64, "f64"), (64, "f32"), (64, "bf16")])
 @pytest.mark.parametrize("loop", [1, 2])
 def test_pipelined_single_worker_matches_oracle(lanes, dtype, loop):
     """One asynchronous worker running the pipelined loop (1) or the batched
@@ -674,8 +674,8 @@ def test_pipelined_single_worker_matches_oracle(lanes, dtype, loop):
     sysm.close()
 
 
-@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16"), (64, "f64"),
-                                         (64, "f32"), (64, "bf16")])
+@pytest.mark.parametrize("lanes,dtype", [(1, "f64"), (4, "f64"), (16, "f32"), (4, "bf16"), (32, "f64"),
+                                         (64, "f64"), (64, "f32"), (64, "bf16")])
 @pytest.mark.parametrize("loop", [1, 2])
 def test_pipelined_single_worker_slices_matches_oracle(lanes, dtype, loop):
     """One asynchronous worker walking its slice (all rows) through the
