@@ -141,7 +141,10 @@ typedef struct asyrk_solve_params {
                                 8, 4 or 2 tickets together, for G >= 8, G = 4 and
                                 G <= 2, and runs them back to back: same arithmetic and
                                 reads of x, one record round trip per batch; the
-                                fastest loop with few workers in flight).  1 and 2 need
+                                fastest loop with few workers in flight; with G = 64
+                                and R <= 512 each worker is two waves of one
+                                workgroup, one fetching the next batch's records into
+                                LDS while the other computes).  1 and 2 need
                                 ASYNC and UPDATE_ALL (with order 1 each worker's slice
                                 walk is its ticket stream).  0 = plain.
                                 -1 (set by asyrk_solve_params_init) = the autotuned
