@@ -374,6 +374,38 @@ def test_trace_split_worker(order):
     sysm.close()
 
 
+@pytest.mark.parametrize("lanes", [4, 16, 64])
+def test_slices_with_more_workers_than_rows(lanes):
+    """R above m in the slice order: every row belongs to one worker's slice of
+    one, the rest have empty slices and no tickets.  In the split worker
+    (64 lanes) those are whole workgroups that leave at once; in the one-wave
+    loops they are groups of a wave that sit out while the others run.  The
+    sweeps still visit every row once each: with gamma = 1 on a system of
+    orthonormal rows one sweep lands exactly on x*."""
+    m, k = 700, 4
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal((m, k))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    row_ptr = np.arange(0, m * k + 1, k, dtype=np.int64)
+    # disjoint supports (orthonormal rows), columns ascending within each row
+    col = np.sort(rng.permutation(m * k).reshape(m, k), axis=1).ravel().astype(np.int32)
+    xs0 = rng.standard_normal(m * k)
+    b = (v.ravel() * xs0[col]).reshape(m, k).sum(axis=1)
+    s = synth.SparseSystem(m, m * k, row_ptr, col, v.ravel().copy(), "f64", v.ravel().copy(), xs0, b)
+    A = s.dense()
+    assert np.all(np.count_nonzero(A, axis=0) == 1)
+    _say(f"slices, R > m, lanes={lanes}")
+    sysm = make_system(s, device=True)
+    for pipe in (1, 2):
+        x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=1, seed=3, in_flight=900, lanes=lanes,
+                          order="slices", pipeline=pipe)
+        assert st["status"] == "OK" and st["pipelined"] == pipe and st["row_updates"] == s.m
+        # sum of the projections onto the rows = the projection onto their span
+        xs = A.T @ np.linalg.lstsq(A @ A.T, s.b, rcond=None)[0]
+        assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs), (pipe, lanes)
+    sysm.close()
+
+
 @pytest.mark.parametrize("pipeline", [1, 2])
 def test_traced_pipelined_solve_converges(pipeline):
     """The traced pipelined and batched loops compute the same method: they
