@@ -421,17 +421,18 @@ def test_traced_pipelined_solve_converges(pipeline):
     sysm.close()
 
 
+@pytest.mark.parametrize("lanes", [16, 64])
 @pytest.mark.parametrize("loop", [1, 2])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_lone_worker_fp32_iterate_within_fp32_floor(loop, dtype):
+def test_lone_worker_fp32_iterate_within_fp32_floor(loop, dtype, lanes):
     """One asynchronous worker with the FP32 iterate and FP32 atomics, in the
     pipelined and batched loops: sequential RK in FP32 arithmetic, within 1e-6
     of the FP64 oracle relative to ||x*|| (the FP32 floor of the replay test)."""
     s = synth.uniform_rows(2000, 500, 10, seed=0, dtype=dtype)
-    _say(f"lone worker, FP32 iterate, {dtype} values, loop {loop}")
+    _say(f"lone worker, FP32 iterate, {dtype} values, loop {loop}, lanes {lanes}")
     ref = oracle_run(s, 1.0, 20, 0)
     sysm = make_system(s, device=True)
-    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, in_flight=1, lanes=16, pipeline=loop,
+    x, st = gpu_solve(sysm, s, True, gamma=1.0, sweeps=20, seed=0, in_flight=1, lanes=lanes, pipeline=loop,
                       iter_dtype="f32", history=32)
     assert st["status"] == "OK" and st["pipelined"] == loop
     assert np.linalg.norm(x - ref["x"]) <= 1e-6 * np.linalg.norm(s.x_star)
