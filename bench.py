@@ -488,7 +488,7 @@ def run_skewed(args, Rs=None, sweeps=100, baseline=True, short=False):
     best = max(converging or res, key=lambda q: res[q]["rows_per_s"])
     cb = None
     if baseline and not args.no_cpu_baseline:
-        cb = cpu_baseline(s, max_sweeps=2, target_s=4.0)
+        cb = cpu_baseline(s, max_sweeps=5, target_s=4.0)
     out = {"metric": "row updates/s (skewed rows, hot columns)", "value": res[best]["rows_per_s"],
            "unit": "row updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
            "vs_baseline": None, "data": "synthetic", "dtype": "f64",
